@@ -1,0 +1,286 @@
+"""ctypes front end of the CPU FP64 oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It loads ``oracle/liboracle.so`` (built
+from ``hpsmc_oracle.c`` with gcc) and shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "hpsmc_oracle.c")
+
+F_KINDS = {"affine": 0, "u_minus_u3": 1, "sin": 2, "u2_over_1pu2": 3, "neg_u3": 4, "u_sin_u": 5}
+SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4}
+IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
+SCHEDULES = {"sequential": 0, "sweeps": 1}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, OpenMP over nodes)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", _SO, _SRC, "-lm"],
+                              cwd=_HERE)
+    return _SO
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int32), ("n_intervals", C.c_int32), ("n_instances", C.c_int32),
+        ("t_breaks", C.POINTER(C.c_double)), ("degree", C.POINTER(C.c_int32)), ("nstar", C.POINTER(C.c_int32)),
+        ("f_kind", C.c_int32), ("src_kind", C.c_int32), ("ic_kind", C.c_int32), ("schedule", C.c_int32),
+        ("f_param", C.c_double * 4), ("src_param", C.c_double * 8), ("ic_param", C.c_double * 4),
+        ("ic_data", C.POINTER(C.c_double)),
+        ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        d, i32, i64, p = C.c_double, C.c_int32, C.c_int64, C.c_void_p
+        pp = C.POINTER(_Problem)
+        sig = {
+            "or_philox4x32_10": (None, [p, p, p]),
+            "or_legendre": (d, [C.c_int, d]), "or_legendre_deriv": (d, [C.c_int, d]),
+            "or_jacobi11": (d, [C.c_int, d]), "or_phi": (d, [C.c_int, d]),
+            "or_jg11": (C.c_int, [C.c_int, p, p]), "or_lgl": (C.c_int, [C.c_int, p, p]),
+            "or_matrix_A": (C.c_int, [C.c_int, p]), "or_matrix_B": (C.c_int, [C.c_int, p]),
+            "or_reconstruct": (C.c_int, [C.c_int, C.c_int, C.c_int, p, p]),
+            "or_eval": (C.c_int, [C.c_int, C.c_int, C.c_int, d, p, p, d, p]),
+            "or_residual": (d, [pp, C.c_int, p, p, d]),
+            "or_f": (d, [pp, d]), "or_fprime": (d, [pp, d]),
+            "or_source": (d, [pp, p, d]), "or_exact": (d, [pp, p, d]),
+            "or_grid": (C.c_int, [pp, C.c_int, p, p]),
+            "or_ic_nodes": (C.c_int, [pp, C.c_int, p]),
+            "or_sample_path": (d, [pp, p, C.c_int, C.c_int, C.c_int, i64, i64, p]),
+            "or_estimate": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, p, p, i64, i64, i64, p, p, p]),
+            "or_iterate": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, p, p, p]),
+            "or_solve": (C.c_int, [pp, C.c_int, p, p]),
+            "or_loss_grad": (C.c_int, [pp, C.c_int, p, p, p, p]),
+            "or_exit_fraction": (d, [C.c_int, d, C.c_int, p, i64, C.c_uint64]),
+            "or_num_threads": (C.c_int, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+# ---------------------------------------------------------------- primitives
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def jg11(n):
+    x, w = np.zeros(n), np.zeros(n)
+    _check(lib().or_jg11(n, _ptr(x), _ptr(w)), "jg11")
+    return x, w
+
+
+def lgl(M):
+    x, w = np.zeros(M + 1), np.zeros(M + 1)
+    _check(lib().or_lgl(M, _ptr(x), _ptr(w)), "lgl")
+    return x, w
+
+
+def matrix_A(n):
+    A = np.zeros((n, n))
+    _check(lib().or_matrix_A(n, _ptr(A)), "matrix_A")
+    return A
+
+
+def matrix_B(M):
+    B = np.zeros((M + 1, M + 1))
+    _check(lib().or_matrix_B(M, _ptr(B)), "matrix_B")
+    return B
+
+
+def legendre(k, x):
+    return lib().or_legendre(k, float(x))
+
+
+def legendre_deriv(k, x):
+    return lib().or_legendre_deriv(k, float(x))
+
+
+def jacobi11(p, x):
+    return lib().or_jacobi11(p, float(x))
+
+
+def phi(p, x):
+    return lib().or_phi(p, float(x))
+
+
+def reconstruct(dim, n, M, U):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    Ut = np.zeros_like(U)
+    _check(lib().or_reconstruct(dim, n, M, _ptr(U), _ptr(Ut)), "reconstruct")
+    return Ut
+
+
+def evaluate(dim, n, M, h, Ut, X, xi):
+    Ut = np.ascontiguousarray(Ut, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    out = np.zeros(3)
+    _check(lib().or_eval(dim, n, M, float(h), _ptr(Ut), _ptr(X), float(xi), _ptr(out)), "eval")
+    return out
+
+
+def exit_fraction(dim, T, nstar, starts, seed=0):
+    starts = np.ascontiguousarray(starts, dtype=np.float64)
+    return lib().or_exit_fraction(dim, float(T), int(nstar), _ptr(starts), starts.shape[0], seed)
+
+
+def num_threads():
+    return lib().or_num_threads()
+
+
+# ---------------------------------------------------------------- problems
+class Problem:
+    """Holds an ``or_problem`` and the arrays it points into.
+
+    ``wl`` is a workload description (``paper_2608_22190_amd.workloads.Workload``
+    or any object with the same attributes)."""
+
+    def __init__(self, wl):
+        self.wl = wl
+        self.t_breaks = np.ascontiguousarray(wl.t_breaks, dtype=np.float64)
+        self.degree = np.ascontiguousarray(wl.degree, dtype=np.int32)
+        self.nstar = np.ascontiguousarray(wl.nstar, dtype=np.int32)
+        ic = wl.ic_data
+        self.ic_data = None if ic is None else np.ascontiguousarray(ic, dtype=np.float64).reshape(-1)
+        s = _Problem()
+        s.dim, s.n = wl.dim, wl.n
+        s.n_intervals, s.n_instances = len(wl.degree), wl.n_instances
+        s.t_breaks = self.t_breaks.ctypes.data_as(C.POINTER(C.c_double))
+        s.degree = self.degree.ctypes.data_as(C.POINTER(C.c_int32))
+        s.nstar = self.nstar.ctypes.data_as(C.POINTER(C.c_int32))
+        s.f_kind, s.src_kind, s.ic_kind = F_KINDS[wl.f], SRC_KINDS[wl.src], IC_KINDS[wl.ic]
+        s.schedule = SCHEDULES[wl.schedule]
+        for i, v in enumerate(wl.f_param):
+            s.f_param[i] = v
+        for i, v in enumerate(wl.src_param):
+            s.src_param[i] = v
+        for i, v in enumerate(wl.ic_param):
+            s.ic_param[i] = v
+        s.ic_data = (self.ic_data.ctypes.data_as(C.POINTER(C.c_double)) if self.ic_data is not None
+                     else C.POINTER(C.c_double)())
+        s.M, s.iters, s.fresh_per_iter, s.seed = wl.M, wl.iters, int(wl.fresh_per_iter), wl.seed
+        self.s = s
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+    @property
+    def nsp(self):
+        return self.wl.n ** self.wl.dim
+
+    def interval_size(self, iv):
+        return self.nsp * (int(self.degree[iv]) + 1)
+
+    def grid(self, iv=0):
+        x = np.zeros(self.wl.n)
+        t = np.zeros(int(self.degree[iv]) + 1)
+        _check(lib().or_grid(self.ref, iv, _ptr(x), _ptr(t)), "grid")
+        return x, t
+
+    def ic_nodes(self, inst=0):
+        u0 = np.zeros(self.nsp)
+        _check(lib().or_ic_nodes(self.ref, inst, _ptr(u0)), "ic_nodes")
+        return u0
+
+    def f(self, u):
+        return lib().or_f(self.ref, float(u))
+
+    def fprime(self, u):
+        return lib().or_fprime(self.ref, float(u))
+
+    def source(self, X, t):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        return lib().or_source(self.ref, _ptr(X), float(t))
+
+    def exact(self, X, t):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        return lib().or_exact(self.ref, _ptr(X), float(t))
+
+    def residual(self, iv, Ut, X, tau):
+        Ut = np.ascontiguousarray(Ut, dtype=np.float64)
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        return lib().or_residual(self.ref, iv, _ptr(Ut), _ptr(X), float(tau))
+
+    def sample_path(self, Ut, inst, iv, iter_tag, node, sample):
+        Ut = np.ascontiguousarray(Ut, dtype=np.float64)
+        L = np.zeros(1, dtype=np.int64)
+        S = lib().or_sample_path(self.ref, _ptr(Ut), inst, iv, iter_tag, int(node), int(sample), _ptr(L))
+        return S, int(L[0])
+
+    def estimate(self, U, inst=0, iv=0, iter_tag=0, nodes=None, m_lo=0, m_hi=None):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        m_hi = self.wl.M if m_hi is None else m_hi
+        if nodes is None:
+            nn = self.nsp * int(self.degree[iv])
+            nptr = None
+        else:
+            nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+            nn = nodes.size
+            nptr = _ptr(nodes)
+        eps, ssq = np.zeros(nn), np.zeros(nn)
+        steps = np.zeros(nn, dtype=np.int64)
+        _check(lib().or_estimate(self.ref, inst, iv, iter_tag, _ptr(U), nptr, nn, m_lo, m_hi,
+                                 _ptr(eps), _ptr(ssq), _ptr(steps)), "estimate")
+        return eps, ssq, steps
+
+    def iterate(self, U, inst=0, iv=0, iter_tag=0):
+        U = np.array(U, dtype=np.float64, copy=True)
+        mx = np.zeros(1)
+        st = np.zeros(1, dtype=np.int64)
+        _check(lib().or_iterate(self.ref, inst, iv, iter_tag, _ptr(U), _ptr(mx), _ptr(st)), "iterate")
+        return U, float(mx[0]), int(st[0])
+
+    def solve(self, inst=0):
+        total = sum(self.interval_size(iv) for iv in range(len(self.degree)))
+        U = np.zeros(total)
+        nmx = self.wl.iters * (len(self.degree) if self.wl.schedule == "sequential" else 1)
+        mx = np.zeros(nmx)
+        _check(lib().or_solve(self.ref, inst, _ptr(U), _ptr(mx)), "solve")
+        out, off = [], 0
+        for iv in range(len(self.degree)):
+            sz = self.interval_size(iv)
+            out.append(U[off:off + sz].reshape(self.nsp, int(self.degree[iv]) + 1))
+            off += sz
+        return out, mx
+
+    def loss_grad(self, c0, target, inst=0):
+        c0 = np.ascontiguousarray(c0, dtype=np.float64).reshape(-1)
+        target = np.ascontiguousarray(target, dtype=np.float64).reshape(-1)
+        loss = np.zeros(1)
+        grad = np.zeros(self.nsp)
+        _check(lib().or_loss_grad(self.ref, inst, _ptr(c0), _ptr(target), _ptr(loss), _ptr(grad)),
+               "loss_grad")
+        return float(loss[0]), grad

@@ -1,0 +1,230 @@
+"""Pins of the oracle's Monte Carlo estimator and residual iteration.
+
+- brute force: in 1-D the walk of Lemma 2.1 is a +-J lattice walk, so the exact
+  expectation of the path quadrature (eq. indexL, eq. interIQ) follows from a
+  dynamic program over lattice positions; the oracle's Monte Carlo estimate must
+  sit within 4 standard errors, and the alternative readings (forward time
+  labels, summing the last inside point) must be rejected by the same test;
+- manufactured sources: s = u_t - Lap u - f(u) against finite differences;
+- exact fixed point: a manufactured solution inside the discrete space makes
+  the residual vanish identically, so the increment is zero to rounding for any
+  sample count and path length (special case of eq. ufg_ep1);
+- geometric decrease of max|eps| (Theorem 3.1) and error against the exact
+  solution on a small single-step problem shaped like Ex. 1;
+- Table 1 boundary-hitting rates (loose pin, reading of Lemma 2.1);
+- the sweep schedule reaches the same fixed point as Algorithm 1;
+- reverse-mode gradient against central finite differences at fixed keys.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2608_22190_amd import workloads as W
+
+
+def _exact_nodal(pb, iv=0):
+    x, t = pb.grid(iv)
+    d = pb.wl.dim
+    U = np.zeros((pb.nsp, len(t)))
+    for jf in range(pb.nsp):
+        idx = np.unravel_index(jf, (pb.wl.n,) * d)
+        X = [x[i] for i in idx]
+        for l in range(len(t)):
+            U[jf, l] = pb.exact(X, t[l])
+    return U
+
+
+# ------------------------------------------------------------------ philox
+def test_philox_is_a_keyed_bijection_sample():
+    outs = {tuple(O.philox([c, 0, 0, 0], [0, 0])) for c in range(2000)}
+    assert len(outs) == 2000
+    a = O.philox([1, 2, 3, 4], [5, 6])
+    assert not np.array_equal(a, O.philox([1, 2, 3, 4], [5, 7]))
+    assert np.array_equal(a, O.philox([1, 2, 3, 4], [5, 6]))
+
+
+def test_philox_words_are_uniform():
+    w = np.concatenate([O.philox([c, 7, 0, 0], [11, 0]) for c in range(4000)]).astype(np.float64)
+    counts, _ = np.histogram(w / 2 ** 32, bins=16, range=(0, 1))
+    exp = w.size / 16
+    chi2 = np.sum((counts - exp) ** 2 / exp)
+    assert chi2 < 40.0  # 15 dof, p ~ 5e-4
+
+
+# ------------------------------------------------------------------ sources
+@pytest.mark.parametrize("src,f,dim", [("sin_decay", "u_minus_u3", 1), ("longtime", "sin", 2),
+                                       ("cos_decay", "neg_u3", 3), ("quad", "u2_over_1pu2", 2),
+                                       ("longtime", "sin", 1)])
+def test_manufactured_source_matches_finite_differences(src, f, dim):
+    wl = W.small(dim=dim, n=4, src=src, f=f, src_param=[0.3, -0.5, 0.7, 0, 0, 0, 0, 0])
+    pb = O.Problem(wl)
+    rng = np.random.default_rng(3)
+    h = 1e-4
+    for _ in range(4):
+        X = rng.uniform(-0.9, 0.9, dim)
+        t = rng.uniform(0.1, 2.0)
+        ut = (pb.exact(X, t + h) - pb.exact(X, t - h)) / (2 * h)
+        lap = 0.0
+        for i in range(dim):
+            e = np.zeros(dim); e[i] = h
+            lap += (pb.exact(X + e, t) - 2 * pb.exact(X, t) + pb.exact(X - e, t)) / h ** 2
+        s = ut - lap - pb.f(pb.exact(X, t))
+        assert abs(pb.source(X, t) - s) < 2e-5 * (1 + abs(s))
+
+
+# ------------------------------------------------------------------ brute force
+def _dp_expectation(pb, Ut, x0, t_ell, t0, nstar, tau_forward=False, include_last=False):
+    """exact E[Q_L] for the 1-D sign walk by a DP over lattice sites"""
+    span = t_ell - t0
+    delta = span / nstar
+    J = math.sqrt(2 * delta)
+    p = {0: 1.0}
+    total = 0.0
+    for q in range(nstar):
+        tau = (t0 + q * delta) if tau_forward else (t0 + span - q * delta)
+        nxt = {}
+        for k, pr in p.items():
+            xq = x0 + J * k
+            r = pb.residual(0, Ut, [xq], tau)
+            for s in (-1, 1):
+                y = xq + J * s
+                if abs(y) >= 1.0:
+                    if include_last:
+                        total += 0.5 * pr * delta * r
+                    continue
+                total += 0.5 * pr * delta * r
+                nxt[k + s] = nxt.get(k + s, 0.0) + 0.5 * pr
+        p = nxt
+    return total
+
+
+def test_estimator_matches_bruteforce_expectation():
+    nstar = 14
+    wl = W.small(dim=1, n=6, M_deg=3, M=40000, T=0.6, nstar=nstar, f="u_minus_u3", src="sin_decay")
+    pb = O.Problem(wl)
+    x, t = pb.grid(0)
+    rng = np.random.default_rng(1)
+    U = rng.standard_normal((pb.nsp, 4)) * 0.5
+    Ut = O.reconstruct(1, wl.n, 3, U.reshape(-1))
+    checked = 0
+    for jf, ell in [(0, 3), (2, 2), (4, 3), (5, 1)]:
+        node = jf + pb.nsp * (ell - 1)
+        eps, ssq, _ = pb.estimate(U, nodes=[node])
+        m = wl.M
+        se = math.sqrt(max(ssq[0] / m - eps[0] ** 2, 0.0) / m)
+        ref = _dp_expectation(pb, Ut, x[jf], t[ell], 0.0, nstar)
+        assert abs(eps[0] - ref) < 4 * se + 1e-14, (jf, ell, eps[0], ref, se)
+        # the test has power against the alternative readings R6 and R11
+        alt_fwd = _dp_expectation(pb, Ut, x[jf], t[ell], 0.0, nstar, tau_forward=True)
+        alt_last = _dp_expectation(pb, Ut, x[jf], t[ell], 0.0, nstar, include_last=True)
+        if abs(alt_fwd - ref) > 12 * se:
+            checked += 1
+            assert abs(eps[0] - alt_fwd) > 6 * se
+        if abs(alt_last - ref) > 12 * se:
+            checked += 1
+            assert abs(eps[0] - alt_last) > 6 * se
+    assert checked >= 3
+
+
+def test_sample_path_matches_estimate_and_is_reproducible():
+    wl = W.small(dim=2, n=4, M_deg=3, M=16, T=0.4, src="longtime", f="sin", nstar=50)
+    pb = O.Problem(wl)
+    U = np.random.default_rng(2).standard_normal((pb.nsp, 4))
+    Ut = O.reconstruct(2, 4, 3, U.reshape(-1))
+    node = 5 + pb.nsp * 2
+    S = [pb.sample_path(Ut, 0, 0, 0, node, i)[0] for i in range(wl.M)]
+    eps, _, _ = pb.estimate(U, nodes=[node])
+    assert abs(np.mean(S) - eps[0]) < 1e-15 * (1 + abs(eps[0])) * 10
+    assert pb.sample_path(Ut, 0, 0, 0, node, 3) == pb.sample_path(Ut, 0, 0, 0, node, 3)
+
+
+# ------------------------------------------------------------------ fixed point
+@pytest.mark.parametrize("dim,f", [(1, "u_minus_u3"), (2, "sin"), (3, "neg_u3")])
+def test_exact_fixed_point_in_discrete_space(dim, f):
+    wl = W.small(dim=dim, n=3, M_deg=2, M=32, T=0.5, src="quad", f=f, nstar=60,
+                 src_param=[0.8, -0.4, 0.3, 0, 0, 0, 0, 0])
+    pb = O.Problem(wl)
+    U = _exact_nodal(pb)
+    eps, _, steps = pb.estimate(U)
+    assert np.all(steps > 0)
+    assert np.max(np.abs(eps)) < 1e-13
+
+
+def test_iteration_converges_to_polynomial_solution():
+    wl = W.small(dim=1, n=5, M_deg=3, M=64, T=0.5, iters=22, src="quad", f="u_minus_u3",
+                 src_param=[0.8, -0.4, 0.3, 0, 0, 0, 0, 0])
+    pb = O.Problem(wl)
+    Us, mx = pb.solve()
+    ex = _exact_nodal(pb)
+    assert np.max(np.abs(Us[0] - ex)) < 1e-9
+    assert mx[-1] < 1e-9 and mx[0] > 1e-3
+
+
+def test_single_step_error_decreases_geometrically():
+    """Ex. 1-shaped run (1-D, u = e^{-t} sin(pi x)), Theorem 3.1: max|eps|
+    decays geometrically to a noise floor; the error against the exact
+    solution ends small."""
+    wl = W.small(dim=1, n=8, M_deg=6, M=200, T=0.5, iters=7, c=0.1)
+    pb = O.Problem(wl)
+    Us, mx = pb.solve()
+    err = np.max(np.abs(Us[0] - _exact_nodal(pb)))
+    assert err < 1e-4
+    assert mx[3] < 0.1 * mx[0] and mx[6] < 0.01 * mx[0]
+
+
+# ------------------------------------------------------------------ table 1
+def test_table1_boundary_hitting_rates():
+    table = {(0.2, 20): 64.88, (0.2, 50): 69.28, (0.2, 100): 71.07,
+             (0.5, 20): 87.44, (0.5, 50): 90.52, (0.5, 100): 92.46,
+             (1.0, 20): 97.25, (1.0, 50): 98.76, (1.0, 100): 98.97}
+    starts = np.random.default_rng(5).uniform(-1, 1, (20000, 2))
+    got = {}
+    for (T, ns), pct in table.items():
+        got[(T, ns)] = 100 * O.exit_fraction(2, T, ns, starts, seed=0)
+        assert abs(got[(T, ns)] - pct) < 4.5, ((T, ns), got[(T, ns)], pct)
+    for T in (0.2, 0.5, 1.0):
+        assert got[(T, 20)] <= got[(T, 50)] + 0.3 <= got[(T, 100)] + 0.6
+    for ns in (20, 50, 100):
+        assert got[(0.2, ns)] < got[(0.5, ns)] < got[(1.0, ns)]
+
+
+# ------------------------------------------------------------------ schedules
+def test_sweeps_reach_the_sequential_fixed_point():
+    base = dict(dim=1, n=4, M_deg=[2, 3, 2], M=32, T=0.6, n_intervals=3, src="quad",
+                f="u_minus_u3", src_param=[0.8, -0.4, 0.3, 0, 0, 0, 0, 0])
+    seq = O.Problem(W.small(iters=16, **base))
+    swp = O.Problem(W.small(iters=22, schedule="sweeps", **base))
+    Useq, _ = seq.solve()
+    Uswp, mx = swp.solve()
+    for iv in range(3):
+        ex = _exact_nodal(seq, iv)
+        assert np.max(np.abs(Useq[iv] - ex)) < 1e-8
+        assert np.max(np.abs(Uswp[iv] - ex)) < 1e-8
+    assert mx[-1] < 1e-8
+
+
+# ------------------------------------------------------------------ gradient
+@pytest.mark.parametrize("f", ["sin", "affine"])
+def test_reverse_mode_gradient_matches_central_differences(f):
+    n = 3
+    c0 = W.c5_coefficients(1, n=n, seed=4).reshape(-1)
+    wl = W.small(dim=2, n=n, M_deg=2, M=12, T=0.5, iters=2, f=f, f_param=[0.7, 0.1, 0, 0],
+                 src="longtime", ic="phi", ic_data=c0[None], nstar=40)
+    pb = O.Problem(wl)
+    target = W.c5_target(1, pb.nsp, seed=1)[0]
+    loss, grad = pb.loss_grad(c0, target)
+
+    def loss_at(c):
+        q = O.Problem(wl.with_(ic_data=c[None]))
+        Us, _ = q.solve()
+        return 0.5 * np.sum((Us[0][:, -1] - target) ** 2)
+
+    assert abs(loss_at(c0) - loss) < 1e-12 * (1 + loss)
+    h = 1e-4
+    for k in range(n * n):
+        e = np.zeros_like(c0); e[k] = h
+        fd = (loss_at(c0 + e) - loss_at(c0 - e)) / (2 * h)
+        tol = 1e-6 * (1 + abs(grad[k])) if f == "sin" else 1e-9 * (1 + abs(grad[k]))
+        assert abs(fd - grad[k]) < tol, (k, fd, grad[k])
