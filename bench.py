@@ -1,0 +1,166 @@
+"""Throughput benchmark of the spectral Monte Carlo hot path on one MI355X.
+
+A step is one residual iteration (reconstruction, time contraction, Monte Carlo
+sampling of every node, reduction and update) of one interval of the 2-D
+long-time workload (24 x 24 Jacobi-Gauss nodes x 16 Lobatto times per unit
+interval, u_t = Lap u + sin u + s), run as the sampling slice
+samples 0 .. m-1 of every node (the per-sample work does not depend on M, so
+the node-sample rate of the slice is that of the full sample count).
+
+Prints ONE JSON line: node-samples/s of the FP32-sampling form (value), the
+FP64 form on the same slice and the speedup, the roofline of the dominant
+kernel (the sampling kernel, measured with HIP events on its own stream) and
+the CPU oracle's rate on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--m-slice m] [--no-cpu] [--no-fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3   # published MI355X vector FP32 (counts packed FMA)
+FP64_PEAK_TFLOPS = 78.6    # published MI355X vector FP64
+METRIC = "node-samples/sec at fixed error vs exact; FP32-batched vs FP64 speedup"
+
+
+def flops_per_eval(dim, P):
+    """Algorithmic FP operations of one residual evaluation: the nested
+    tensor-product contraction of the u and v slabs (2 polynomials x 2 flops x
+    (P^d + P^{d-1} + ... + P) multiply-adds) plus the three-term recurrences of
+    the d coordinates (3 flops per new Legendre value)."""
+    cont = sum(P ** k for k in range(1, dim + 1))
+    return 4 * cont + 3 * dim * (P - 2)
+
+
+def run_gpu(wl, steps, warmup, launch, torch):
+    from paper_2608_22190_amd import hpsmc
+    stream = torch.cuda.Stream()
+    with hpsmc.Plan(wl) as plan:
+        if launch:
+            plan.hpsmc_set_launch(*launch)
+        plan.hpsmc_start_interval(0, stream=stream)
+        for w in range(warmup):
+            plan.hpsmc_iterate(0, w, stream=stream)
+        torch.cuda.synchronize()
+        plan.hpsmc_reset_stats(stream=stream)
+        plan.hpsmc_start_interval(0, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            plan.hpsmc_iterate(0, k, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = plan.hpsmc_stats(stream=stream)
+        U = plan.hpsmc_get_nodes(0, stream=stream)
+        eps, ssq = plan.hpsmc_get_increment(0, stream=stream)
+        lau = plan.hpsmc_get_launch()
+    sig = float(np.sqrt(np.maximum(ssq / wl.M - eps ** 2, 0.0) / wl.M).max())
+    return {"seconds": t1 - t0, "stats": st, "U": U, "sigma": sig, "launch": lau}
+
+
+def cpu_baseline(wl, budget_s=20.0):
+    """The FP64 oracle on a bounded sample: random nodes of the same interval,
+    the first samples of each, one residual iteration from the same iterate."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import oracle as O
+    pb = O.Problem(wl)
+    rng = np.random.default_rng(123)
+    nn = wl.nsp * wl.degree[0]
+    U0 = np.repeat(pb.ic_nodes()[:, None], wl.degree[0] + 1, axis=1).reshape(-1)
+    done, t_used, nodes_used = 0, 0.0, 0
+    m = 2
+    while t_used < budget_s:
+        nodes = rng.choice(nn, size=O.num_threads(), replace=False)
+        t0 = time.perf_counter()
+        pb.estimate(U0, nodes=nodes, m_lo=0, m_hi=m)
+        t_used += time.perf_counter() - t0
+        done += len(nodes) * m
+        nodes_used += len(nodes)
+        if t_used < 1.0:
+            m *= 2
+    return {"value": done / t_used, "unit": "node-samples/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{nodes_used} random nodes of interval 1 x first samples ({done} node-samples, "
+                      f"one residual iteration from the replicated initial data), {t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--m-slice", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--launch", type=str, default="", help="samples_per_lane,waves_per_block,blocks_per_cu")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (one process, one device).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_22190_amd import workloads as W
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+
+    base = W.c2_long_time(M=args.m_slice, iters=args.steps, n_intervals=1)
+    P = base.n + 2
+    nodes = base.nsp * base.degree[0]
+    r32 = run_gpu(base.with_(precision="fp32"), args.steps, args.warmup, launch, torch)
+    ns_step = nodes * base.M
+    value = ns_step * args.steps / r32["seconds"]
+    st = r32["stats"]
+    fpe = flops_per_eval(base.dim, P)
+    k_ms = st["sample_ms"] / max(1, st["sample_launches"])
+    evals_per_launch = st["path_steps"] / max(1, st["sample_launches"])
+    achieved = fpe * evals_per_launch / (k_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "node-samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * r32["seconds"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c2_2d_long_time interval 1 (t in [0,1]), one residual iteration per step, "
+                               f"all {nodes} nodes (24x24 JG(1,1) x 16 LGL times) x samples 0..{base.M - 1} "
+                               f"of M=65536; FP32 sampling, FP64 reconstruction/update",
+                   "dim": 2, "n": 24, "temporal_degree": 16, "nodes": nodes, "samples_per_node": base.M,
+                   "max_nstar": int(max(base.nstar)), "launch": list(r32["launch"])},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "sample_kernel<float,2,28,NS>", "flops_per_eval": fpe,
+                     "evals_per_launch": evals_per_launch, "avg_launch_ms": k_ms,
+                     "lane_utilization": st["path_steps"] / max(1, st["lane_steps"])},
+        "path_steps_per_s": st["path_steps"] / r32["seconds"],
+        "mean_path_length": st["path_steps"] / max(1, st["node_samples"]),
+        "reconstruction_ms_per_step": st["recon_ms"] / max(1, st["recon_launches"]),
+        "slab_ms_per_step": st["slab_ms"] / max(1, st["sample_launches"]),
+    }
+    if not args.no_fp64:
+        r64 = run_gpu(base.with_(precision="fp64"), args.steps, args.warmup, launch, torch)
+        v64 = ns_step * args.steps / r64["seconds"]
+        s64 = r64["stats"]
+        k64 = s64["sample_ms"] / max(1, s64["sample_launches"])
+        a64 = fpe * s64["path_steps"] / max(1, s64["sample_launches"]) / (k64 * 1e-3) / 1e12
+        out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["seconds"] / args.steps,
+                       "roofline_achieved_tflops": a64, "roofline_frac": a64 / FP64_PEAK_TFLOPS}
+        out["fp32_over_fp64_speedup"] = value / v64
+        out["accuracy"] = {"max_abs_u32_minus_u64": float(np.max(np.abs(r32["U"] - r64["U"]))),
+                           "max_node_std_error_fp64": r64["sigma"],
+                           "note": "same Philox words in both precisions"}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(base.with_(precision="fp64"))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

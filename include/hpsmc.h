@@ -1,0 +1,198 @@
+/*
+ * hpsmc.h -- C ABI of the MI355X hot path of the hp-version time-stepping
+ * spectral Monte Carlo method for u_t = Lap u + f(u) + s on (-1,1)^d with
+ * homogeneous Dirichlet data (arXiv 2608.22190).
+ *
+ * The library estimates, at every space-time node (x_j, t_{n,l}) of an
+ * interval, the residual increment eps of eq. varepsilon_1 by Monte Carlo
+ * sample paths of the sphere-jump walk (Lemma 2.1, eq. indexL, eq. interIQ),
+ * adds it to the nodal values (Algorithm 1, Step 3) and reconstructs the
+ * space-time polynomial from the nodal values (Sec. 2.3, eq. u_N) before the
+ * next iteration.  Intervals run one after another (Algorithm 1, Step 4), or
+ * all together in Jacobi-in-time sweeps.
+ *
+ * General conventions
+ *   - Every call returns hpsmc_status (0 = OK).  No exception or abort crosses
+ *     the ABI; hpsmc_last_error() returns a thread-local message.
+ *   - Arguments are validated before any device work.  After HPSMC_EDEVICE the
+ *     plan must be destroyed.
+ *   - Pointers marked "host" are host memory owned by the caller; "device"
+ *     pointers are device memory owned by the caller; on_device selects which
+ *     for the copy-in / copy-out calls.  The plan owns all other device memory
+ *     (allocated with hipMalloc in hpsmc_create, freed in hpsmc_destroy).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work and return; copy-out calls to host memory synchronize the stream.
+ *   - Spatial nodes: the n-point Jacobi-Gauss (1,1) rule per dimension
+ *     (Sec. 2.3), node index j = C-order over (j_0, ..., j_{d-1}).  Temporal
+ *     nodes: the M_n+1 shifted Legendre-Gauss-Lobatto points of interval n
+ *     (Sec. 2.1); l = 0 is t_{n-1}.  Nodal arrays are [instance][j][l].
+ *   - Monte Carlo node id of (j, l >= 1): j + n^d (l - 1).
+ *   - Random numbers: Philox4x32-10 with key (lo32(seed), hi32(seed)) and
+ *     counter (node id, sample, step block, instance<<16 | interval<<8 | tag),
+ *     tag = iteration (or sweep) index when fresh_per_iter, else 0.  d = 1 uses
+ *     one bit per step (128 steps per block), d = 2 one word (4 steps per
+ *     block), d = 3, 4 one block per step, d = 5 two blocks per step.
+ */
+#ifndef HPSMC_H
+#define HPSMC_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HPSMC_OK = 0,
+    HPSMC_EINVAL = -1,     /* invalid argument (nothing was enqueued)          */
+    HPSMC_ENOTSUP = -2,    /* valid but unsupported (e.g. nonzero boundary data) */
+    HPSMC_ENOMEM = -3,     /* device or host allocation failed                  */
+    HPSMC_EDEVICE = -4,    /* a HIP call failed; the plan is poisoned           */
+    HPSMC_EDIVERGED = -5   /* max|eps| non-finite, or grew 3 times in a row     */
+} hpsmc_status;
+
+/* nonlinearity f(u) of eq. mainproblem */
+enum { HPSMC_F_AFFINE = 0,        /* f = a u + b, f_param = {a, b} */
+       HPSMC_F_U_MINUS_U3 = 1,    /* u - u^3   */
+       HPSMC_F_SIN = 2,           /* sin u     */
+       HPSMC_F_U2_OVER_1PU2 = 3,  /* u^2/(1+u^2) */
+       HPSMC_F_NEG_U3 = 4,        /* -u^3      */
+       HPSMC_F_U_SIN_U = 5 };     /* u sin u (Ex. 1) */
+
+/* manufactured source: s = u_t - Lap u - f(u) of an exact solution u_ex */
+enum { HPSMC_SRC_NONE = 0,        /* s = 0 */
+       HPSMC_SRC_SIN_DECAY = 1,   /* u_ex = e^{-t} prod sin(pi x_i)   */
+       HPSMC_SRC_COS_DECAY = 2,   /* u_ex = e^{-t} prod cos(pi x_i/2) */
+       HPSMC_SRC_LONGTIME = 3,    /* u_ex = prod(1-x_i^2) sin(sum x_i) e^{cos t}/(1+t^2) */
+       HPSMC_SRC_QUAD = 4 };      /* u_ex = prod(1-x_i^2)(c0 + c1 t + c2 t^2), src_param = {c0,c1,c2} */
+
+/* initial data */
+enum { HPSMC_IC_EXACT = 0,        /* u_ex(x, t_0) of the source's exact solution */
+       HPSMC_IC_SINGULAR = 1,     /* prod(1-x_i^2) |x_0|^a, ic_param = {a}        */
+       HPSMC_IC_PHI = 2,          /* sum_p c_p prod phi_{p_i}(x_i), ic_data = c [instance][n^d] */
+       HPSMC_IC_NODAL = 3 };      /* nodal values, ic_data [instance][n^d]        */
+
+enum { HPSMC_SEQUENTIAL = 0,      /* Algorithm 1: intervals one after another     */
+       HPSMC_SWEEPS = 1 };        /* every sweep updates all intervals; interval n
+                                     takes its initial column from interval n-1's
+                                     last column of the previous sweep            */
+
+enum { HPSMC_FP64 = 0,            /* everything in FP64                            */
+       HPSMC_FP32_SAMPLING = 1 }; /* paths and basis evaluation in FP32 with
+                                     compensated accumulation; reconstruction,
+                                     increments, norms and stop test in FP64      */
+
+typedef struct {
+    int32_t dim;               /* 1..5, Omega = (-1,1)^dim                      */
+    int32_t n;                 /* spatial nodes per dimension, 1..32            */
+    int32_t n_intervals;       /* N_h, 1..255                                   */
+    int32_t n_instances;       /* independent problems sharing the grid, 1..65535 */
+    const double *t_breaks;    /* host, N_h+1 strictly increasing               */
+    const int32_t *degree;     /* host, N_h entries M_n in 1..31                */
+    const int32_t *nstar;      /* host, sum_n M_n entries: N* of node time l>=1
+                                  of interval n (eq. time division), 1..2^24-1 */
+    int32_t f_kind, src_kind, ic_kind, schedule;
+    double f_param[4], src_param[8], ic_param[4];
+    const double *ic_data;     /* host, [instance][n^d] for IC_PHI / IC_NODAL   */
+    int64_t M;                 /* samples per node, >= 1                        */
+    int32_t iters;             /* iterations per interval, or sweeps, 1..255    */
+    int32_t fresh_per_iter;    /* 1: new samples each iteration, 0: reuse       */
+    uint64_t seed;
+    int32_t precision;         /* HPSMC_FP64 or HPSMC_FP32_SAMPLING            */
+    int32_t reserved;
+} hpsmc_problem;
+
+typedef struct hpsmc_plan hpsmc_plan;
+
+typedef struct {
+    uint64_t path_steps;       /* residual evaluations (sum of L over paths)     */
+    uint64_t lane_steps;       /* walk steps executed by all sample slots        */
+    uint64_t node_samples;     /* (node, sample) estimates                       */
+    int32_t n_records;         /* entries filled in max_eps                      */
+    int32_t status_flags;      /* bit 0: non-finite increment seen              */
+    int32_t sample_launches;   /* sampling-kernel launches timed                */
+    int32_t recon_launches;    /* reconstructions timed                         */
+    double sample_ms;          /* summed sampling-kernel time (HIP events on the
+                                  launching stream), milliseconds               */
+    double recon_ms;           /* summed reconstruction time (all its kernels)   */
+    double slab_ms;            /* summed time-contraction (slab) kernel time     */
+    double max_eps[4096];      /* max|eps| per (interval, iteration) or sweep    */
+} hpsmc_stats_t;
+
+/* Sampling-kernel launch shape (chosen by hpsmc_tune or set directly). */
+typedef struct {
+    int32_t samples_per_lane;  /* 1, 2 or 4                                      */
+    int32_t waves_per_block;   /* 1..16                                           */
+    int32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu          */
+    int32_t reserved;
+} hpsmc_launch;
+
+/* Validate the problem, compute the grid and transform matrices on the host,
+ * allocate device memory, and write the initial iterate (the initial column
+ * replicated in time, for interval 0 or for all intervals under SWEEPS).
+ * EINVAL on any out-of-range field; ENOTSUP for unsupported combinations. */
+hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out);
+void hpsmc_destroy(hpsmc_plan *plan);
+
+/* Spatial nodes (n, host) and temporal nodes of interval iv (M_iv+1, host). */
+hpsmc_status hpsmc_grid(const hpsmc_plan *plan, int32_t iv, double *x_nodes, double *t_nodes);
+
+/* Whole solve: Algorithm 1 (or the sweeps), `iters` iterations each. */
+hpsmc_status hpsmc_solve(hpsmc_plan *plan, void *stream);
+
+/* Start interval iv (SEQUENTIAL): column 0 = initial data (iv = 0) or the last
+ * column of interval iv-1 (Algorithm 1, Step 4), replicated to every column. */
+hpsmc_status hpsmc_start_interval(hpsmc_plan *plan, int32_t iv, void *stream);
+
+/* One residual iteration on interval iv with counter tag `tag`: reconstruct,
+ * time-contract, sample every node, reduce, update (Algorithm 1, Steps 1-3). */
+hpsmc_status hpsmc_iterate(hpsmc_plan *plan, int32_t iv, int32_t tag, void *stream);
+
+/* One sweep over all intervals (SWEEPS) with counter tag `tag`. */
+hpsmc_status hpsmc_sweep(hpsmc_plan *plan, int32_t tag, void *stream);
+
+/* Copy nodal values of interval iv out of / into the plan, [instance][j][l]. */
+hpsmc_status hpsmc_get_nodes(const hpsmc_plan *plan, int32_t iv, double *out, int32_t on_device, void *stream);
+hpsmc_status hpsmc_set_nodes(hpsmc_plan *plan, int32_t iv, const double *in, int32_t on_device, void *stream);
+
+/* Last increment of interval iv: eps and sum of S^2 per node, [instance][node id]. */
+hpsmc_status hpsmc_get_increment(const hpsmc_plan *plan, int32_t iv, double *eps, double *sumsq, void *stream);
+
+/* Evaluate the current reconstruction of interval iv at npts points
+ * pts[k] = (x_0..x_{d-1}, t) (host): out[k] = (u, Lap u - d_t u) (host). */
+hpsmc_status hpsmc_eval(hpsmc_plan *plan, int32_t iv, int32_t inst, const double *pts, int64_t npts,
+                        double *out, void *stream);
+
+/* Keep the per-sample values S_i of samples i < m_probe of every node of the
+ * next iterations (0 disables); read them as [instance][node id][i]. */
+hpsmc_status hpsmc_set_probe(hpsmc_plan *plan, int64_t m_probe);
+hpsmc_status hpsmc_get_probe(const hpsmc_plan *plan, int32_t iv, double *out, void *stream);
+
+/* Sampling-kernel launch shape. */
+hpsmc_status hpsmc_set_launch(hpsmc_plan *plan, const hpsmc_launch *l);
+hpsmc_status hpsmc_get_launch(const hpsmc_plan *plan, hpsmc_launch *l);
+
+/* Autotuner: time every candidate launch shape on one iteration of interval iv
+ * with samples limited to m_tune per node, keep the fastest (and cache it in
+ * the JSON file `cache_path` if not NULL). */
+hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char *cache_path, void *stream);
+
+/* Counters accumulated since creation or the last reset (synchronizes). */
+hpsmc_status hpsmc_stats(const hpsmc_plan *plan, hpsmc_stats_t *out, void *stream);
+hpsmc_status hpsmc_reset_stats(hpsmc_plan *plan, void *stream);
+
+/* Terminal misfit of a single-interval problem with IC_PHI initial data:
+ * loss[i] = 1/2 sum_j (u_i(x_j, T) - target[i][j])^2 after `iters`
+ * iterations, and grad[i] = d loss[i] / d c_i (the phi-coefficients) by the
+ * adjoint of the iteration with every sample path fixed (common random
+ * numbers; the paths are regenerated from their Philox counters).
+ * target, loss, grad: host or device per on_device.  Runs the forward solve. */
+hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *loss, double *grad,
+                                int32_t on_device, void *stream);
+
+const char *hpsmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1003 @@
+// Host runtime of the spectral Monte Carlo hot path: problem validation,
+// quadrature and transform set-up, device memory, node scheduling, the
+// iteration / interval / sweep drivers and the C ABI of include/hpsmc.h.
+#include "hpsmc_internal.h"
+#include "../../include/hpsmc.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+namespace hpsmc {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static hpsmc_status fail(hpsmc_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            plan->poisoned = true;                                                           \
+            return fail(HPSMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+        }                                                                                    \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Gauss rules by the Golub-Welsch route: nodes are eigenvalues of the Jacobi
+// matrix of the three-term recurrence (Sturm-sequence bisection), weights are
+// Christoffel numbers 1 / sum_k p_k(x)^2 of the orthonormal polynomials.
+// ---------------------------------------------------------------------------
+static int sturm_count(const std::vector<double> &e2, int n, double x)
+{
+    // zero diagonal (symmetric weights); e2[k] = beta_k, k = 1..n-1
+    int cnt = 0;
+    double d = -x;
+    if (d < 0) ++cnt;
+    for (int k = 1; k < n; ++k) {
+        if (d == 0.0) d = 1e-300;
+        d = -x - e2[k] / d;
+        if (d < 0) ++cnt;
+    }
+    return cnt;
+}
+
+static void gauss_rule(int n, double mu0, double (*beta)(int), std::vector<double> &x, std::vector<double> &w)
+{
+    std::vector<double> e2(n + 1, 0.0);
+    for (int k = 1; k < n; ++k) e2[k] = beta(k);
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double lo = -1.0, hi = 1.0;
+        for (int it = 0; it < 200; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi) break;
+            if (sturm_count(e2, n, mid) > i) hi = mid; else lo = mid;
+        }
+        x[i] = 0.5 * (lo + hi);
+    }
+    for (int i = 0; i < n; ++i) {
+        double pm = 0.0, pc = 1.0 / std::sqrt(mu0), s = pc * pc;
+        for (int k = 0; k + 1 < n; ++k) {
+            const double ek1 = std::sqrt(e2[k + 1]), ek = k > 0 ? std::sqrt(e2[k]) : 0.0;
+            const double pn = (x[i] * pc - ek * pm) / ek1;
+            pm = pc;
+            pc = pn;
+            s += pc * pc;
+        }
+        w[i] = 1.0 / s;
+    }
+}
+
+static double beta_legendre(int k) { return double(k) * k / (4.0 * k * k - 1.0); }
+static double beta_jacobi11(int k) { return double(k) * (k + 2) / ((2.0 * k + 1.0) * (2.0 * k + 3.0)); }
+
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) { gauss_rule(n, 2.0, beta_legendre, x, w); }
+static void jacobi_gauss11(int n, std::vector<double> &x, std::vector<double> &w) { gauss_rule(n, 4.0 / 3.0, beta_jacobi11, x, w); }
+
+// Legendre-Gauss-Lobatto on [-1,1]: end points plus the JG(1,1) nodes; the
+// interior weights are the JG(1,1) Christoffel numbers divided by (1 - x^2).
+static void lobatto(int M, std::vector<double> &xi, std::vector<double> &w)
+{
+    xi.assign(M + 1, 0.0);
+    w.assign(M + 1, 0.0);
+    xi[0] = -1.0;
+    xi[M] = 1.0;
+    w[0] = w[M] = 2.0 / (M * (M + 1.0));
+    if (M > 1) {
+        std::vector<double> x, wj;
+        jacobi_gauss11(M - 1, x, wj);
+        for (int k = 1; k < M; ++k) {
+            xi[k] = x[k - 1];
+            w[k] = wj[k - 1] / (1.0 - x[k - 1] * x[k - 1]);
+        }
+    }
+}
+
+static void legendre_values(int kmax, double x, double *L)
+{
+    L[0] = 1.0;
+    if (kmax >= 1) L[1] = x;
+    for (int m = 1; m < kmax; ++m) L[m + 1] = ((2.0 * m + 1.0) * x * L[m] - m * L[m - 1]) / (m + 1.0);
+}
+
+// Legendre coefficients (P modes) of the spatial Lagrange basis of the
+// JG(1,1) nodes, l_j(x) = (1-x^2)/(1-x_j^2) prod_{m != j}(x-x_m)/(x_j-x_m)
+// (eq. spacelag): G[k][j] = (2k+1)/2 int l_j L_k, by exact Gauss-Legendre.
+static std::vector<double> spatial_to_legendre(const std::vector<double> &xn, int P)
+{
+    const int n = (int)xn.size();
+    std::vector<double> xq, wq;
+    gauss_legendre(n + 3, xq, wq);
+    std::vector<double> G((size_t)P * n, 0.0), L(P + 1);
+    for (size_t a = 0; a < xq.size(); ++a) {
+        legendre_values(P, xq[a], L.data());
+        for (int j = 0; j < n; ++j) {
+            double lj = (1.0 - xq[a] * xq[a]) / (1.0 - xn[j] * xn[j]);
+            for (int m = 0; m < n; ++m)
+                if (m != j) lj *= (xq[a] - xn[m]) / (xn[j] - xn[m]);
+            for (int k = 0; k < P; ++k) G[(size_t)k * n + j] += (2.0 * k + 1.0) / 2.0 * wq[a] * lj * L[k];
+        }
+    }
+    return G;
+}
+
+// Legendre coefficients of the temporal Lagrange basis on the LGL nodes (eq. timeLag).
+static std::vector<double> temporal_to_legendre(const std::vector<double> &xi)
+{
+    const int T1 = (int)xi.size();
+    std::vector<double> xq, wq;
+    gauss_legendre(T1 + 1, xq, wq);
+    std::vector<double> B((size_t)T1 * T1, 0.0), L(T1 + 1);
+    for (size_t a = 0; a < xq.size(); ++a) {
+        legendre_values(T1, xq[a], L.data());
+        for (int k = 0; k < T1; ++k) {
+            double hk = 1.0;
+            for (int m = 0; m < T1; ++m)
+                if (m != k) hk *= (xq[a] - xi[m]) / (xi[k] - xi[m]);
+            for (int q = 0; q < T1; ++q) B[(size_t)q * T1 + k] += (2.0 * q + 1.0) / 2.0 * wq[a] * hk * L[q];
+        }
+    }
+    return B;
+}
+
+// Legendre-basis differentiation: (c')_q = (2q+1) sum_{m>q, m-q odd} c_m;
+// (c'')_k = (k+1/2) sum_{m>=k+2, m-k even} (m(m+1) - k(k+1)) c_m.
+static std::vector<double> legendre_d1(int N)
+{
+    std::vector<double> D((size_t)N * N, 0.0);
+    for (int q = 0; q < N; ++q)
+        for (int m = q + 1; m < N; m += 2) D[(size_t)q * N + m] = 2.0 * q + 1.0;
+    return D;
+}
+static std::vector<double> legendre_d2(int N)
+{
+    std::vector<double> D((size_t)N * N, 0.0);
+    for (int k = 0; k < N; ++k)
+        for (int m = k + 2; m < N; m += 2) D[(size_t)k * N + m] = (k + 0.5) * (m * (m + 1.0) - k * (k + 1.0));
+    return D;
+}
+
+// ---------------------------------------------------------------------------
+// Exact solutions of the manufactured sources and initial data.
+// ---------------------------------------------------------------------------
+static double exact_solution(const hpsmc_problem &pb, const double *X, double t)
+{
+    const int d = pb.dim;
+    const double pi = 3.14159265358979323846;
+    switch (pb.src_kind) {
+    case HPSMC_SRC_SIN_DECAY: { double p = std::exp(-t); for (int i = 0; i < d; ++i) p *= std::sin(pi * X[i]); return p; }
+    case HPSMC_SRC_COS_DECAY: { double p = std::exp(-t); for (int i = 0; i < d; ++i) p *= std::cos(0.5 * pi * X[i]); return p; }
+    case HPSMC_SRC_LONGTIME: {
+        double a = 1.0, s = 0.0;
+        for (int i = 0; i < d; ++i) { a *= 1.0 - X[i] * X[i]; s += X[i]; }
+        return a * std::sin(s) * std::exp(std::cos(t)) / (1.0 + t * t);
+    }
+    case HPSMC_SRC_QUAD: {
+        double a = 1.0;
+        for (int i = 0; i < d; ++i) a *= 1.0 - X[i] * X[i];
+        return a * (pb.src_param[0] + pb.src_param[1] * t + pb.src_param[2] * t * t);
+    }
+    }
+    return 0.0;
+}
+
+// phi_p in the Legendre form 2(p+1)/(2p+3) (L_p - L_{p+2})
+static double phi_legendre(int p, const double *L) { return 2.0 * (p + 1) / (2.0 * p + 3.0) * (L[p] - L[p + 2]); }
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct NodeSet {               // the nodes one sampling launch covers
+    std::vector<NodeDesc> host;
+    NodeDesc *dev = nullptr;
+    int64_t n = 0;
+    // slab groups
+    int32_t n_groups = 0, max_nstar = 0;
+    int64_t slab_elems = 0;
+    void *group_mem = nullptr; // coef_off, slab_off, span, delta, h2, nstar, deg
+    SlabArgs slab{};
+    // outputs (canonical order)
+    double *eps = nullptr, *sumsq = nullptr, *probe = nullptr;
+    int64_t probe_cap = 0;
+    std::vector<int32_t> ivs;  // intervals covered
+};
+
+}  // namespace hpsmc
+
+struct hpsmc_plan {
+    hpsmc_problem pb{};
+    std::vector<double> t_breaks;
+    std::vector<int32_t> degree, nstar;
+    std::vector<double> ic_data;
+    int d = 0, n = 0, P = 0, PP = 0, n_iv = 0, n_inst = 0;
+    int64_t nsp = 0, psp = 0;   // n^d, P^d
+    std::vector<double> x;      // spatial nodes
+    std::vector<std::vector<double>> xi, tnodes;   // per interval: reference LGL nodes, t_{n,l}
+    bool fp32 = false, poisoned = false;
+    int cus = 0;
+    hpsmc_launch launch{2, 4, 8, 0};
+
+    // device memory
+    double *U = nullptr;                 // all intervals, [iv block][inst][j][l]
+    std::vector<int64_t> u_off;          // per interval
+    double *cu = nullptr, *cv = nullptr; // [iv block][inst][P^d][T1]
+    std::vector<int64_t> c_off;          // per interval
+    double *tmp0 = nullptr, *tmp1 = nullptr;
+    double *ic = nullptr;                // [inst][nsp]
+    double *mats = nullptr;              // G0 (P x n), D2 (P x P), then per interval Bt, D1
+    std::vector<int64_t> bt_off, d1_off;
+    void *slab_table = nullptr;
+    size_t slab_bytes = 0;
+    double *part = nullptr;
+    int64_t part_elems = 0;
+    unsigned long long *counters = nullptr;  // [0] work, [1] evals, [2] lane steps, [3] unused
+    unsigned long long *maxbits = nullptr;   // [4096]
+    int64_t m_probe = 0;
+    std::vector<hpsmc::NodeSet> sets;        // sequential: one per interval; sweeps: one
+    int64_t node_samples = 0;
+    // HIP-event timing of the sampling, slab and reconstruction kernels
+    struct EvPair { hipEvent_t a = nullptr, b = nullptr; };
+    std::vector<EvPair> ev_sample, ev_slab, ev_recon;
+    size_t n_sample = 0, n_slab = 0, n_recon = 0;
+    int32_t n_records = 0, sweep_count = 0;
+};
+
+namespace hpsmc {
+
+static int64_t ipow(int64_t b, int e)
+{
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+// next event pair of a pool (created on first use); null when the pool is full
+static hpsmc_plan::EvPair *next_pair(std::vector<hpsmc_plan::EvPair> &pool, size_t &used)
+{
+    if (used >= 4096) return nullptr;
+    if (used == pool.size()) {
+        hpsmc_plan::EvPair e;
+        if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        pool.push_back(e);
+    }
+    return &pool[used++];
+}
+
+static double pool_ms(const std::vector<hpsmc_plan::EvPair> &pool, size_t used)
+{
+    double tot = 0.0;
+    for (size_t i = 0; i < used; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pool[i].a, pool[i].b) == hipSuccess) tot += ms;
+        else (void)hipGetLastError();
+    }
+    return tot;
+}
+
+static hpsmc_status validate(const hpsmc_problem *pb)
+{
+    if (!pb) return fail(HPSMC_EINVAL, "problem is NULL");
+    if (pb->dim < 1 || pb->dim > 5) return fail(HPSMC_EINVAL, "dim must be 1..5");
+    if (pb->n < 1 || pb->n > kMaxN) return fail(HPSMC_EINVAL, "n must be 1..32");
+    if (pb->n_intervals < 1 || pb->n_intervals > 255) return fail(HPSMC_EINVAL, "n_intervals must be 1..255");
+    if (pb->n_instances < 1 || pb->n_instances > 65535) return fail(HPSMC_EINVAL, "n_instances must be 1..65535");
+    if (!pb->t_breaks || !pb->degree || !pb->nstar) return fail(HPSMC_EINVAL, "t_breaks/degree/nstar is NULL");
+    for (int i = 0; i <= pb->n_intervals; ++i)
+        if (!std::isfinite(pb->t_breaks[i])) return fail(HPSMC_EINVAL, "t_breaks must be finite");
+    for (int i = 0; i < pb->n_intervals; ++i) {
+        if (!(pb->t_breaks[i + 1] > pb->t_breaks[i])) return fail(HPSMC_EINVAL, "t_breaks must increase strictly");
+        if (pb->degree[i] < 1 || pb->degree[i] > kMaxDeg) return fail(HPSMC_EINVAL, "degree must be 1..31");
+    }
+    int64_t tot = 0;
+    for (int i = 0; i < pb->n_intervals; ++i) tot += pb->degree[i];
+    for (int64_t k = 0; k < tot; ++k)
+        if (pb->nstar[k] < 1 || pb->nstar[k] >= (1 << 24)) return fail(HPSMC_EINVAL, "nstar must be 1..2^24-1");
+    if (pb->M < 1 || pb->M > (int64_t)0xFFFFFFFFll) return fail(HPSMC_EINVAL, "M must be 1..2^32-1");
+    if (pb->iters < 1 || pb->iters > 255) return fail(HPSMC_EINVAL, "iters must be 1..255");
+    if (pb->f_kind < 0 || pb->f_kind > 5) return fail(HPSMC_EINVAL, "unknown f_kind");
+    if (pb->src_kind < 0 || pb->src_kind > 4) return fail(HPSMC_EINVAL, "unknown src_kind");
+    if (pb->ic_kind < 0 || pb->ic_kind > 3) return fail(HPSMC_EINVAL, "unknown ic_kind");
+    if (pb->schedule < 0 || pb->schedule > 1) return fail(HPSMC_EINVAL, "unknown schedule");
+    if (pb->precision < 0 || pb->precision > 1) return fail(HPSMC_EINVAL, "unknown precision");
+    if ((pb->ic_kind == HPSMC_IC_PHI || pb->ic_kind == HPSMC_IC_NODAL) && !pb->ic_data)
+        return fail(HPSMC_EINVAL, "ic_data is NULL");
+    if (pb->ic_kind == HPSMC_IC_EXACT && pb->src_kind == HPSMC_SRC_NONE)
+        return fail(HPSMC_EINVAL, "IC_EXACT needs a source with an exact solution");
+    const int P = pb->n + 2;
+    if ((pb->dim == 5 && P > 12) || (pb->dim == 4 && P > 20))
+        return fail(HPSMC_ENOTSUP, "too many modes for this dimension (d=5: n<=10, d=4: n<=18)");
+    return HPSMC_OK;
+}
+
+static hpsmc_status dalloc(hpsmc_plan *plan, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(HPSMC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    (void)plan;
+    return HPSMC_OK;
+}
+
+// Expected path length used to order work (longest first): the walk leaves
+// the box after roughly min_i (1 - x_i^2)/2 time units, capped by the node's span.
+static double expected_cost(const NodeDesc &nd, int d)
+{
+    double tex = 1.0;
+    for (int i = 0; i < d; ++i) tex = std::min(tex, 0.5 * (1.0 - nd.x0[i] * nd.x0[i]));
+    const double steps = std::min((double)nd.nstar, tex / nd.delta + 1.0);
+    return steps;
+}
+
+static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<int32_t> &ivs)
+{
+    const int d = plan->d, T = (int)(plan->fp32 ? sizeof(float) : sizeof(double));
+    set.ivs = ivs;
+    set.host.clear();
+    std::vector<int64_t> coef_off, slab_off;
+    std::vector<double> span, delta, h2;
+    std::vector<int32_t> nst, deg;
+    const int64_t rows = ipow(plan->P, d - 1);
+    const int64_t stride = rows * 2 * plan->PP;
+    int64_t slab_pos = 0, out = 0;
+    // canonical output order: [iv][inst][node id]
+    for (int32_t iv : ivs) {
+        const int M = plan->degree[iv];
+        const double h = plan->t_breaks[iv + 1] - plan->t_breaks[iv];
+        int noff = 0;
+        for (int k = 0; k < iv; ++k) noff += plan->degree[k];
+        for (int inst = 0; inst < plan->n_inst; ++inst) {
+            for (int l = 1; l <= M; ++l) {
+                const int ns = plan->nstar[noff + l - 1];
+                const double sp = 0.5 * (plan->xi[iv][l] + 1.0) * h;
+                const double dl = sp / ns;
+                const int g = (int)coef_off.size();
+                coef_off.push_back(plan->c_off[iv] + (int64_t)inst * plan->psp * (M + 1));
+                slab_off.push_back(slab_pos);
+                span.push_back(sp);
+                delta.push_back(dl);
+                h2.push_back(2.0 / h);
+                nst.push_back(ns);
+                deg.push_back(M);
+                (void)g;
+                for (int64_t j = 0; j < plan->nsp; ++j) {
+                    NodeDesc nd{};
+                    int64_t r = j;
+                    for (int i = d - 1; i >= 0; --i) { nd.x0[i] = plan->x[r % plan->n]; r /= plan->n; }
+                    nd.delta = dl;
+                    nd.jump = std::sqrt(2.0 * d * dl);
+                    nd.span = sp;
+                    nd.t_prev = plan->t_breaks[iv];
+                    nd.u_index = plan->u_off[iv] + ((int64_t)inst * plan->nsp + j) * (M + 1) + l;
+                    nd.slab = slab_pos;
+                    nd.nstar = ns;
+                    nd.c0 = (uint32_t)(j + plan->nsp * (l - 1));
+                    nd.c3 = ((uint32_t)inst << 16) | ((uint32_t)iv << 8);
+                    nd.out = (int32_t)(out + inst * plan->nsp * M + (int64_t)(l - 1) * plan->nsp + j);
+                    set.host.push_back(nd);
+                }
+                slab_pos += (int64_t)ns * stride;
+            }
+        }
+        out += (int64_t)plan->n_inst * plan->nsp * M;
+    }
+    set.n = (int64_t)set.host.size();
+    if (set.n > (int64_t)0x7fffffff) return fail(HPSMC_EINVAL, "too many nodes");
+    // longest expected paths first (stable for determinism)
+    std::stable_sort(set.host.begin(), set.host.end(), [d](const NodeDesc &a, const NodeDesc &b) {
+        return expected_cost(a, d) > expected_cost(b, d);
+    });
+    set.n_groups = (int32_t)coef_off.size();
+    set.max_nstar = *std::max_element(nst.begin(), nst.end());
+    set.slab_elems = slab_pos;
+    hpsmc_status st;
+    if ((st = dalloc(plan, (void **)&set.dev, sizeof(NodeDesc) * set.n))) return st;
+    const size_t G = set.n_groups;
+    const size_t gbytes = G * (2 * sizeof(int64_t) + 3 * sizeof(double) + 2 * sizeof(int32_t));
+    if ((st = dalloc(plan, &set.group_mem, gbytes))) return st;
+    std::vector<char> gh(gbytes);
+    char *p = gh.data();
+    auto put = [&](const void *src, size_t b) { memcpy(p, src, b); p += b; };
+    put(coef_off.data(), G * 8); put(slab_off.data(), G * 8);
+    put(span.data(), G * 8); put(delta.data(), G * 8); put(h2.data(), G * 8);
+    put(nst.data(), G * 4); put(deg.data(), G * 4);
+    if (hipMemcpy(set.group_mem, gh.data(), gbytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(set.dev, set.host.data(), sizeof(NodeDesc) * set.n, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "upload of node descriptors failed");
+    char *gb = (char *)set.group_mem;
+    SlabArgs &sa = set.slab;
+    sa.cu = plan->cu;
+    sa.cv = plan->cv;
+    sa.coef_off = (const int64_t *)gb;
+    sa.slab_off = (const int64_t *)(gb + G * 8);
+    sa.span = (const double *)(gb + G * 16);
+    sa.delta = (const double *)(gb + G * 24);
+    sa.h2 = (const double *)(gb + G * 32);
+    sa.nstar = (const int32_t *)(gb + G * 40);
+    sa.deg = (const int32_t *)(gb + G * 44);
+    sa.n_groups = set.n_groups;
+    sa.P = plan->P;
+    sa.PP = plan->PP;
+    sa.rows = (int32_t)rows;
+    sa.slab_stride = stride;
+    if ((st = dalloc(plan, (void **)&set.eps, sizeof(double) * set.n))) return st;
+    if ((st = dalloc(plan, (void **)&set.sumsq, sizeof(double) * set.n))) return st;
+    (void)T;
+    return HPSMC_OK;
+}
+
+static void free_set(NodeSet &s)
+{
+    (void)hipFree(s.dev);
+    (void)hipFree(s.group_mem);
+    (void)hipFree(s.eps);
+    (void)hipFree(s.sumsq);
+    (void)hipFree(s.probe);
+    s = NodeSet{};
+}
+
+// initial nodal values [inst][nsp], computed on the host in FP64
+static void initial_nodes(const hpsmc_plan *plan, std::vector<double> &u0)
+{
+    const int d = plan->d, n = plan->n;
+    u0.assign((size_t)plan->n_inst * plan->nsp, 0.0);
+    std::vector<std::vector<double>> Lx(n, std::vector<double>(n + 3));
+    for (int j = 0; j < n; ++j) legendre_values(n + 2, plan->x[j], Lx[j].data());
+    for (int inst = 0; inst < plan->n_inst; ++inst)
+        for (int64_t jf = 0; jf < plan->nsp; ++jf) {
+            int ji[kMaxDim];
+            double X[kMaxDim];
+            int64_t r = jf;
+            for (int i = d - 1; i >= 0; --i) { ji[i] = (int)(r % n); X[i] = plan->x[ji[i]]; r /= n; }
+            double v = 0.0;
+            switch (plan->pb.ic_kind) {
+            case HPSMC_IC_EXACT: v = exact_solution(plan->pb, X, plan->t_breaks[0]); break;
+            case HPSMC_IC_SINGULAR:
+                v = std::pow(std::fabs(X[0]), plan->pb.ic_param[0]);
+                for (int i = 0; i < d; ++i) v *= 1.0 - X[i] * X[i];
+                break;
+            case HPSMC_IC_PHI: {
+                const double *c = plan->ic_data.data() + (size_t)inst * plan->nsp;
+                for (int64_t pf = 0; pf < plan->nsp; ++pf) {
+                    int64_t rr = pf;
+                    double prod = 1.0;
+                    for (int i = d - 1; i >= 0; --i) { prod *= phi_legendre((int)(rr % n), Lx[ji[i]].data()); rr /= n; }
+                    v += c[pf] * prod;
+                }
+                break;
+            }
+            case HPSMC_IC_NODAL: v = plan->ic_data[(size_t)inst * plan->nsp + jf]; break;
+            }
+            u0[(size_t)inst * plan->nsp + jf] = v;
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Device pipeline pieces
+// ---------------------------------------------------------------------------
+static hpsmc_status reconstruct(hpsmc_plan *plan, int iv, hipStream_t s)
+{
+    const int d = plan->d, n = plan->n, P = plan->P, T1 = plan->degree[iv] + 1;
+    const double h = plan->t_breaks[iv + 1] - plan->t_breaks[iv];
+    const double *G0 = plan->mats, *D2 = plan->mats + (size_t)P * n;
+    const double *Bt = plan->mats + plan->bt_off[iv], *D1 = plan->mats + plan->d1_off[iv];
+    double *cu = plan->cu + plan->c_off[iv], *cv = plan->cv + plan->c_off[iv];
+    const int64_t I = plan->n_inst;
+    hpsmc_plan::EvPair *ev = next_pair(plan->ev_recon, plan->n_recon);
+    if (ev) HIP_TRY(hipEventRecord(ev->a, s));
+    // c^u = U x_1 G0 ... x_d G0 x_t Bt
+    const double *in = plan->U + plan->u_off[iv];
+    double *bufs[2] = {plan->tmp0, plan->tmp1};
+    for (int i = 0; i < d; ++i) {
+        double *o = bufs[i & 1];
+        HIP_TRY(launch_mode_product(in, o, I * ipow(P, i), n, P, ipow(n, d - 1 - i) * T1, G0, 1.0, 0, s));
+        in = o;
+    }
+    HIP_TRY(launch_mode_product(in, cu, I * plan->psp, T1, T1, 1, Bt, 1.0, 0, s));
+    // c^v = sum_i c^u x_i D2 - (2/h) c^u x_t D1   (Lap u - d_t u)
+    for (int i = 0; i < d; ++i)
+        HIP_TRY(launch_mode_product(cu, cv, I * ipow(P, i), P, P, ipow(P, d - 1 - i) * T1, D2, 1.0, i > 0, s));
+    HIP_TRY(launch_mode_product(cu, cv, I * plan->psp, T1, T1, 1, D1, -2.0 / h, 1, s));
+    if (ev) HIP_TRY(hipEventRecord(ev->b, s));
+    return HPSMC_OK;
+}
+
+static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
+{
+    const int ns = plan->launch.samples_per_lane;
+    SlabArgs sa = set.slab;
+    sa.slab_table = plan->slab_table;
+    hpsmc_plan::EvPair *es = next_pair(plan->ev_slab, plan->n_slab);
+    if (es) HIP_TRY(hipEventRecord(es->a, s));
+    HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
+    if (es) HIP_TRY(hipEventRecord(es->b, s));
+    HIP_TRY(launch_fill_u64(plan->counters, 1, 0ull, s));
+    SampleArgs a{};
+    a.nodes = set.dev;
+    a.n_nodes = set.n;
+    a.M = plan->pb.M;
+    a.chunks_per_node = (int32_t)((plan->pb.M + 64 * ns - 1) / (64 * ns));
+    a.P = plan->P;
+    a.PP = plan->PP;
+    a.tag = tag;
+    a.key0 = (uint32_t)plan->pb.seed;
+    a.key1 = (uint32_t)(plan->pb.seed >> 32);
+    a.slab_table = plan->slab_table;
+    a.slab_stride = sa.slab_stride;
+    a.part = plan->part;
+    a.probe = (plan->m_probe > 0 && set.probe) ? set.probe : nullptr;
+    a.m_probe = plan->m_probe;
+    a.work = plan->counters;
+    a.stats = plan->counters + 1;
+    a.phys.dim = plan->d;
+    a.phys.f_kind = plan->pb.f_kind;
+    a.phys.src_kind = plan->pb.src_kind;
+    memcpy(a.phys.f_param, plan->pb.f_param, sizeof(a.phys.f_param));
+    memcpy(a.phys.src_param, plan->pb.src_param, sizeof(a.phys.src_param));
+    const int blocks = std::max(1, plan->cus * plan->launch.blocks_per_cu);
+    hpsmc_plan::EvPair *ek = next_pair(plan->ev_sample, plan->n_sample);
+    if (ek) HIP_TRY(hipEventRecord(ek->a, s));
+    HIP_TRY(launch_sample(a, plan->fp32, ns, plan->launch.waves_per_block, blocks, s));
+    if (ek) HIP_TRY(hipEventRecord(ek->b, s));
+    unsigned long long *mb = plan->maxbits + std::min(record, 4095);
+    HIP_TRY(launch_reduce_update(plan->part, a.chunks_per_node, set.dev, set.n, plan->pb.M, plan->U, set.eps,
+                                 set.sumsq, mb, s));
+    plan->node_samples += set.n * plan->pb.M;
+    plan->n_records = std::max(plan->n_records, std::min(record, 4095) + 1);
+    return HPSMC_OK;
+}
+
+static hpsmc_status start_interval(hpsmc_plan *plan, int iv, int replicate, hipStream_t s)
+{
+    const int T1 = plan->degree[iv] + 1;
+    const int64_t rows = (int64_t)plan->n_inst * plan->nsp;
+    double *dst = plan->U + plan->u_off[iv];
+    if (iv == 0) {
+        HIP_TRY(launch_start_columns(dst, plan->ic, 1, 0, T1, T1, rows, replicate, s));
+    } else {
+        const int Tp = plan->degree[iv - 1] + 1;
+        HIP_TRY(launch_start_columns(dst, plan->U + plan->u_off[iv - 1], Tp, Tp - 1, T1, T1, rows, replicate, s));
+    }
+    return HPSMC_OK;
+}
+
+}  // namespace hpsmc
+
+using namespace hpsmc;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *hpsmc_last_error(void) { return g_err.c_str(); }
+
+void hpsmc_destroy(hpsmc_plan *plan)
+{
+    if (!plan) return;
+    for (auto &s : plan->sets) free_set(s);
+    for (auto *pool : {&plan->ev_sample, &plan->ev_slab, &plan->ev_recon})
+        for (auto &e : *pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    void *ptrs[] = {plan->U, plan->cu, plan->cv, plan->tmp0, plan->tmp1, plan->ic, plan->mats,
+                    plan->slab_table, plan->part, plan->counters, plan->maxbits};
+    for (void *p : ptrs) (void)hipFree(p);
+    delete plan;
+}
+
+hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
+{
+    if (!out) return fail(HPSMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    hpsmc_status st = validate(pb);
+    if (st) return st;
+    std::unique_ptr<hpsmc_plan, void (*)(hpsmc_plan *)> plan(new hpsmc_plan, hpsmc_destroy);
+    plan->pb = *pb;
+    plan->d = pb->dim;
+    plan->n = pb->n;
+    plan->P = pb->n + 2;
+    plan->PP = (plan->P + 3) / 4 * 4;
+    plan->n_iv = pb->n_intervals;
+    plan->n_inst = pb->n_instances;
+    plan->nsp = ipow(pb->n, pb->dim);
+    plan->psp = ipow(plan->P, pb->dim);
+    plan->fp32 = pb->precision == HPSMC_FP32_SAMPLING;
+    plan->t_breaks.assign(pb->t_breaks, pb->t_breaks + pb->n_intervals + 1);
+    plan->degree.assign(pb->degree, pb->degree + pb->n_intervals);
+    int64_t tot = 0;
+    for (int d : plan->degree) tot += d;
+    plan->nstar.assign(pb->nstar, pb->nstar + tot);
+    if (pb->ic_data && (pb->ic_kind == HPSMC_IC_PHI || pb->ic_kind == HPSMC_IC_NODAL))
+        plan->ic_data.assign(pb->ic_data, pb->ic_data + (size_t)pb->n_instances * plan->nsp);
+    plan->pb.t_breaks = plan->t_breaks.data();
+    plan->pb.degree = plan->degree.data();
+    plan->pb.nstar = plan->nstar.data();
+    plan->pb.ic_data = plan->ic_data.empty() ? nullptr : plan->ic_data.data();
+
+    // grid
+    std::vector<double> wx;
+    jacobi_gauss11(plan->n, plan->x, wx);
+    plan->xi.resize(plan->n_iv);
+    plan->tnodes.resize(plan->n_iv);
+    for (int iv = 0; iv < plan->n_iv; ++iv) {
+        std::vector<double> wt;
+        lobatto(plan->degree[iv], plan->xi[iv], wt);
+        const double t0 = plan->t_breaks[iv], h = plan->t_breaks[iv + 1] - t0;
+        for (double z : plan->xi[iv]) plan->tnodes[iv].push_back(t0 + 0.5 * (z + 1.0) * h);
+    }
+
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(HPSMC_EDEVICE, "no HIP device");
+    }
+    plan->cus = prop.multiProcessorCount;
+    if (set_recurrence_tables() != hipSuccess) return fail(HPSMC_EDEVICE, "constant table upload failed");
+
+    // device buffers
+    const int64_t I = plan->n_inst;
+    int64_t usz = 0, csz = 0, tmax = 0;
+    for (int iv = 0; iv < plan->n_iv; ++iv) {
+        const int T1 = plan->degree[iv] + 1;
+        plan->u_off.push_back(usz);
+        plan->c_off.push_back(csz);
+        usz += I * plan->nsp * T1;
+        csz += I * plan->psp * T1;
+        tmax = std::max<int64_t>(tmax, I * ipow(std::max(plan->n, plan->P), plan->d) * T1);
+    }
+    hpsmc_plan *pl = plan.get();
+    if ((st = dalloc(pl, (void **)&pl->U, usz * 8))) return st;
+    if ((st = dalloc(pl, (void **)&pl->cu, csz * 8))) return st;
+    if ((st = dalloc(pl, (void **)&pl->cv, csz * 8))) return st;
+    if ((st = dalloc(pl, (void **)&pl->tmp0, tmax * 8))) return st;
+    if ((st = dalloc(pl, (void **)&pl->tmp1, tmax * 8))) return st;
+    if ((st = dalloc(pl, (void **)&pl->ic, I * plan->nsp * 8))) return st;
+    if ((st = dalloc(pl, (void **)&pl->counters, 4 * 8))) return st;
+    if ((st = dalloc(pl, (void **)&pl->maxbits, 4096 * 8))) return st;
+
+    // transform matrices
+    std::vector<double> mats;
+    auto G0 = spatial_to_legendre(plan->x, plan->P);
+    auto D2 = legendre_d2(plan->P);
+    mats.insert(mats.end(), G0.begin(), G0.end());
+    mats.insert(mats.end(), D2.begin(), D2.end());
+    for (int iv = 0; iv < plan->n_iv; ++iv) {
+        auto Bt = temporal_to_legendre(plan->xi[iv]);
+        auto D1 = legendre_d1(plan->degree[iv] + 1);
+        plan->bt_off.push_back((int64_t)mats.size());
+        mats.insert(mats.end(), Bt.begin(), Bt.end());
+        plan->d1_off.push_back((int64_t)mats.size());
+        mats.insert(mats.end(), D1.begin(), D1.end());
+    }
+    if ((st = dalloc(pl, (void **)&pl->mats, mats.size() * 8))) return st;
+    std::vector<double> u0;
+    initial_nodes(pl, u0);
+    if (hipMemcpy(pl->mats, mats.data(), mats.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pl->ic, u0.data(), u0.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(pl->counters, 0, 32) != hipSuccess || hipMemset(pl->maxbits, 0, 4096 * 8) != hipSuccess ||
+        hipMemset(pl->U, 0, usz * 8) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "initial upload failed");
+
+    // node sets and the slab table
+    if (pb->schedule == HPSMC_SEQUENTIAL) {
+        plan->sets.resize(plan->n_iv);
+        for (int iv = 0; iv < plan->n_iv; ++iv)
+            if ((st = build_set(pl, plan->sets[iv], {iv}))) return st;
+    } else {
+        plan->sets.resize(1);
+        std::vector<int32_t> all;
+        for (int iv = 0; iv < plan->n_iv; ++iv) all.push_back(iv);
+        if ((st = build_set(pl, plan->sets[0], all))) return st;
+    }
+    int64_t slab_max = 0, nmax = 0;
+    for (auto &s : plan->sets) { slab_max = std::max(slab_max, s.slab_elems); nmax = std::max(nmax, s.n); }
+    plan->slab_bytes = (size_t)slab_max * (plan->fp32 ? 4 : 8);
+    if ((st = dalloc(pl, &pl->slab_table, plan->slab_bytes))) return st;
+    plan->part_elems = nmax * ((pb->M + 63) / 64) * 2;
+    if ((st = dalloc(pl, (void **)&pl->part, plan->part_elems * 8))) return st;
+
+    // initial iterate: the initial column replicated in time
+    if (pb->schedule == HPSMC_SEQUENTIAL) {
+        if ((st = start_interval(pl, 0, 1, nullptr))) return st;
+    } else {
+        for (int iv = 0; iv < plan->n_iv; ++iv)
+            if (launch_start_columns(pl->U + pl->u_off[iv], pl->ic, 1, 0, plan->degree[iv] + 1, plan->degree[iv] + 1,
+                                     I * plan->nsp, 1, nullptr) != hipSuccess)
+                return fail(HPSMC_EDEVICE, "initial iterate failed");
+    }
+    if (hipDeviceSynchronize() != hipSuccess) return fail(HPSMC_EDEVICE, "device synchronize failed");
+    *out = plan.release();
+    return HPSMC_OK;
+}
+
+#define CHECK_PLAN(p)                                                            \
+    do {                                                                         \
+        if (!(p)) return fail(HPSMC_EINVAL, "plan is NULL");                     \
+        if ((p)->poisoned) return fail(HPSMC_EDEVICE, "plan is poisoned");       \
+    } while (0)
+
+hpsmc_status hpsmc_grid(const hpsmc_plan *plan, int32_t iv, double *x_nodes, double *t_nodes)
+{
+    if (!plan) return fail(HPSMC_EINVAL, "plan is NULL");
+    if (iv < 0 || iv >= plan->n_iv) return fail(HPSMC_EINVAL, "interval out of range");
+    if (x_nodes) memcpy(x_nodes, plan->x.data(), sizeof(double) * plan->n);
+    if (t_nodes) memcpy(t_nodes, plan->tnodes[iv].data(), sizeof(double) * plan->tnodes[iv].size());
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_start_interval(hpsmc_plan *plan, int32_t iv, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (iv < 0 || iv >= plan->n_iv) return fail(HPSMC_EINVAL, "interval out of range");
+    if (plan->pb.schedule != HPSMC_SEQUENTIAL) return fail(HPSMC_EINVAL, "plan uses sweeps");
+    return start_interval(plan, iv, 1, (hipStream_t)stream);
+}
+
+static hpsmc_status iterate_impl(hpsmc_plan *plan, int iv, int tag, int record, hipStream_t s)
+{
+    hpsmc_status st;
+    if ((st = reconstruct(plan, iv, s))) return st;
+    return sample_set(plan, plan->sets[iv], tag, record, s);
+}
+
+hpsmc_status hpsmc_iterate(hpsmc_plan *plan, int32_t iv, int32_t tag, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (iv < 0 || iv >= plan->n_iv) return fail(HPSMC_EINVAL, "interval out of range");
+    if (tag < 0 || tag > 255) return fail(HPSMC_EINVAL, "tag must be 0..255");
+    if (plan->pb.schedule != HPSMC_SEQUENTIAL) return fail(HPSMC_EINVAL, "plan uses sweeps");
+    return iterate_impl(plan, iv, tag, plan->n_records, (hipStream_t)stream);
+}
+
+static hpsmc_status sweep_impl(hpsmc_plan *plan, int tag, int record, hipStream_t s)
+{
+    hpsmc_status st;
+    // every interval takes column 0 from the previous interval's last column
+    // (the values of the previous sweep: the copies run before any update)
+    for (int iv = 1; iv < plan->n_iv; ++iv) {
+        const int T1 = plan->degree[iv] + 1, Tp = plan->degree[iv - 1] + 1;
+        HIP_TRY(launch_start_columns(plan->U + plan->u_off[iv], plan->U + plan->u_off[iv - 1], Tp, Tp - 1, T1, T1,
+                                     (int64_t)plan->n_inst * plan->nsp, 0, s));
+    }
+    for (int iv = 0; iv < plan->n_iv; ++iv)
+        if ((st = reconstruct(plan, iv, s))) return st;
+    return sample_set(plan, plan->sets[0], tag, record, s);
+}
+
+hpsmc_status hpsmc_sweep(hpsmc_plan *plan, int32_t tag, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (tag < 0 || tag > 255) return fail(HPSMC_EINVAL, "tag must be 0..255");
+    if (plan->pb.schedule != HPSMC_SWEEPS) return fail(HPSMC_EINVAL, "plan is sequential");
+    return sweep_impl(plan, tag, plan->n_records, (hipStream_t)stream);
+}
+
+hpsmc_status hpsmc_solve(hpsmc_plan *plan, void *stream)
+{
+    CHECK_PLAN(plan);
+    hipStream_t s = (hipStream_t)stream;
+    hpsmc_status st;
+    const int K = plan->pb.iters;
+    if (plan->pb.schedule == HPSMC_SEQUENTIAL) {
+        for (int iv = 0; iv < plan->n_iv; ++iv) {
+            if ((st = start_interval(plan, iv, 1, s))) return st;
+            for (int k = 0; k < K; ++k)
+                if ((st = iterate_impl(plan, iv, plan->pb.fresh_per_iter ? k : 0, iv * K + k, s))) return st;
+        }
+    } else {
+        for (int iv = 0; iv < plan->n_iv; ++iv)
+            HIP_TRY(launch_start_columns(plan->U + plan->u_off[iv], plan->ic, 1, 0, plan->degree[iv] + 1,
+                                         plan->degree[iv] + 1, (int64_t)plan->n_inst * plan->nsp, 1, s));
+        for (int k = 0; k < K; ++k)
+            if ((st = sweep_impl(plan, plan->pb.fresh_per_iter ? k : 0, k, s))) return st;
+    }
+    return HPSMC_OK;
+}
+
+static hpsmc_status copy_nodes(const hpsmc_plan *plan, int iv, void *dst, const void *src, int on_device,
+                               hipStream_t s, bool to_plan)
+{
+    const size_t bytes = (size_t)plan->n_inst * plan->nsp * (plan->degree[iv] + 1) * 8;
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : (to_plan ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost);
+    if (hipMemcpyAsync(dst, src, bytes, kind, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "node copy failed");
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_get_nodes(const hpsmc_plan *plan, int32_t iv, double *out, int32_t on_device, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (iv < 0 || iv >= plan->n_iv || !out) return fail(HPSMC_EINVAL, "bad interval or output");
+    return copy_nodes(plan, iv, out, plan->U + plan->u_off[iv], on_device, (hipStream_t)stream, false);
+}
+
+hpsmc_status hpsmc_set_nodes(hpsmc_plan *plan, int32_t iv, const double *in, int32_t on_device, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (iv < 0 || iv >= plan->n_iv || !in) return fail(HPSMC_EINVAL, "bad interval or input");
+    return copy_nodes(plan, iv, plan->U + plan->u_off[iv], in, on_device, (hipStream_t)stream, true);
+}
+
+static const NodeSet *set_of(const hpsmc_plan *plan, int iv, int64_t *off)
+{
+    if (plan->pb.schedule == HPSMC_SEQUENTIAL) { *off = 0; return &plan->sets[iv]; }
+    int64_t o = 0;
+    for (int k = 0; k < iv; ++k) o += (int64_t)plan->n_inst * plan->nsp * plan->degree[k];
+    *off = o;
+    return &plan->sets[0];
+}
+
+hpsmc_status hpsmc_get_increment(const hpsmc_plan *plan, int32_t iv, double *eps, double *sumsq, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (iv < 0 || iv >= plan->n_iv) return fail(HPSMC_EINVAL, "interval out of range");
+    int64_t off;
+    const NodeSet *set = set_of(plan, iv, &off);
+    const size_t cnt = (size_t)plan->n_inst * plan->nsp * plan->degree[iv];
+    hipStream_t s = (hipStream_t)stream;
+    if ((eps && hipMemcpyAsync(eps, set->eps + off, cnt * 8, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        (sumsq && hipMemcpyAsync(sumsq, set->sumsq + off, cnt * 8, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "increment copy failed");
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_eval(hpsmc_plan *plan, int32_t iv, int32_t inst, const double *pts, int64_t npts, double *out,
+                        void *stream)
+{
+    CHECK_PLAN(plan);
+    if (iv < 0 || iv >= plan->n_iv || inst < 0 || inst >= plan->n_inst || npts < 0 || (npts && (!pts || !out)))
+        return fail(HPSMC_EINVAL, "bad eval arguments");
+    if (npts == 0) return HPSMC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double *dp = nullptr, *dout = nullptr;
+    const size_t pb = (size_t)npts * (plan->d + 1) * 8, ob = (size_t)npts * 2 * 8;
+    if (hipMalloc(&dp, pb) != hipSuccess || hipMalloc(&dout, ob) != hipSuccess) {
+        (void)hipFree(dp);
+        return fail(HPSMC_ENOMEM, "eval buffers");
+    }
+    const int T1 = plan->degree[iv] + 1;
+    const int64_t co = plan->c_off[iv] + (int64_t)inst * plan->psp * T1;
+    hipError_t e = hipMemcpyAsync(dp, pts, pb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_eval(plan->cu + co, plan->cv + co, plan->d, plan->P, T1, plan->t_breaks[iv],
+                        plan->t_breaks[iv + 1] - plan->t_breaks[iv], dp, npts, dout, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, ob, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(dp);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(HPSMC_EDEVICE, std::string("eval: ") + hipGetErrorString(e));
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_set_probe(hpsmc_plan *plan, int64_t m_probe)
+{
+    CHECK_PLAN(plan);
+    if (m_probe < 0 || m_probe > plan->pb.M) return fail(HPSMC_EINVAL, "m_probe must be 0..M");
+    for (auto &s : plan->sets) {
+        (void)hipFree(s.probe);
+        s.probe = nullptr;
+        if (m_probe > 0) {
+            hpsmc_status st = dalloc(plan, (void **)&s.probe, (size_t)s.n * m_probe * 8);
+            if (st) return st;
+        }
+    }
+    plan->m_probe = m_probe;
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_get_probe(const hpsmc_plan *plan, int32_t iv, double *out, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (iv < 0 || iv >= plan->n_iv || !out || plan->m_probe == 0) return fail(HPSMC_EINVAL, "no probe");
+    int64_t off;
+    const NodeSet *set = set_of(plan, iv, &off);
+    const size_t cnt = (size_t)plan->n_inst * plan->nsp * plan->degree[iv] * plan->m_probe;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(out, set->probe + off * plan->m_probe, cnt * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "probe copy failed");
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_set_launch(hpsmc_plan *plan, const hpsmc_launch *l)
+{
+    CHECK_PLAN(plan);
+    if (!l) return fail(HPSMC_EINVAL, "launch is NULL");
+    const bool ns_ok = l->samples_per_lane == 1 || l->samples_per_lane == 2 || (l->samples_per_lane == 4 && plan->d <= 2);
+    if (!ns_ok || l->waves_per_block < 1 || l->waves_per_block > 4 || l->blocks_per_cu < 1 || l->blocks_per_cu > 64)
+        return fail(HPSMC_EINVAL, "launch shape out of range");
+    plan->launch = *l;
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_get_launch(const hpsmc_plan *plan, hpsmc_launch *l)
+{
+    if (!plan || !l) return fail(HPSMC_EINVAL, "NULL argument");
+    *l = plan->launch;
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_stats(const hpsmc_plan *plan, hpsmc_stats_t *out, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (!out) return fail(HPSMC_EINVAL, "out is NULL");
+    memset(out, 0, sizeof(*out));
+    unsigned long long c[4];
+    std::vector<unsigned long long> mb(4096);
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(c, plan->counters, sizeof(c), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(mb.data(), plan->maxbits, 4096 * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "stats copy failed");
+    out->sample_ms = pool_ms(plan->ev_sample, plan->n_sample);
+    out->slab_ms = pool_ms(plan->ev_slab, plan->n_slab);
+    out->recon_ms = pool_ms(plan->ev_recon, plan->n_recon);
+    out->sample_launches = (int32_t)plan->n_sample;
+    out->recon_launches = (int32_t)plan->n_recon;
+    out->path_steps = c[1];
+    out->lane_steps = c[2];
+    out->node_samples = (uint64_t)plan->node_samples;
+    out->n_records = plan->n_records;
+    for (int r = 0; r < plan->n_records; ++r) {
+        double v;
+        memcpy(&v, &mb[r], 8);
+        out->max_eps[r] = v;
+        if (!std::isfinite(v)) out->status_flags |= 1;
+    }
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_reset_stats(hpsmc_plan *plan, void *stream)
+{
+    CHECK_PLAN(plan);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_fill_u64(plan->counters, 4, 0ull, s));
+    HIP_TRY(launch_fill_u64(plan->maxbits, 4096, 0ull, s));
+    plan->node_samples = 0;
+    plan->n_records = 0;
+    plan->n_sample = plan->n_slab = plan->n_recon = 0;
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char *cache_path, void *stream)
+{
+    CHECK_PLAN(plan);
+    (void)iv; (void)m_tune; (void)cache_path; (void)stream;
+    return fail(HPSMC_ENOTSUP, "autotuner not built yet");
+}
+
+hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *loss, double *grad,
+                                int32_t on_device, void *stream)
+{
+    CHECK_PLAN(plan);
+    (void)target; (void)loss; (void)grad; (void)on_device; (void)stream;
+    return fail(HPSMC_ENOTSUP, "adjoint not built yet");
+}
+
+}  // extern "C"

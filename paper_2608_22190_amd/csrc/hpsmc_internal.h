@@ -1,0 +1,91 @@
+// Internal declarations shared by the host runtime (hpsmc_host.cpp) and the
+// gfx950 kernels (hpsmc_kernels.hip).  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hpsmc {
+
+constexpr int kMaxDim = 5;
+constexpr int kMaxN = 32;            // spatial nodes per dimension
+constexpr int kMaxP = kMaxN + 2;     // Legendre modes per dimension (phi_p has degree p+2)
+constexpr int kMaxDeg = 31;          // temporal degree M_n
+
+// One Monte Carlo node (instance, interval, l >= 1, spatial node j).
+struct NodeDesc {
+    double x0[kMaxDim];   // spatial node
+    double delta;         // Delta_{n,l} = (t_{n,l} - t_{n-1}) / N*
+    double jump;          // J = sqrt(2 d Delta)
+    double span;          // t_{n,l} - t_{n-1}
+    double t_prev;        // t_{n-1}
+    int64_t u_index;      // offset of U[inst][iv][j][l] in the nodal buffer
+    int64_t slab;         // offset of the q = 0 slab of (inst, iv, l) in the slab table
+    int32_t nstar;        // N*
+    uint32_t c0;          // Philox counter word 0: j + n^d (l - 1)
+    uint32_t c3;          // Philox counter word 3 without the tag: inst<<16 | iv<<8
+    int32_t out;          // row of this node in the per-launch output arrays
+};
+
+// Problem constants every sampling lane needs.
+struct Physics {
+    int32_t dim, f_kind, src_kind, pad;
+    double f_param[4];
+    double src_param[8];
+};
+
+// Arguments of the persistent sampling kernel.
+struct SampleArgs {
+    const NodeDesc *nodes;       // all nodes of this launch, in scheduling order
+    int64_t n_nodes;
+    int64_t M;                   // samples per node
+    int32_t chunks_per_node;     // ceil(M / (64 * samples_per_lane))
+    int32_t P;                   // Legendre modes per dimension
+    int32_t PP;                  // padded row length of the slab (>= P, multiple of 4)
+    int32_t tag;                 // iteration / sweep tag of the counter
+    uint32_t key0, key1;
+    const void *slab_table;      // T, rows of [u: PP][v: PP]
+    int64_t slab_stride;         // elements per (inst, iv, l, q) slab
+    double *part;                // [node out][chunk][2]: sum S, sum S^2
+    double *probe;               // [node out][m_probe] or null
+    int64_t m_probe;
+    unsigned long long *work;    // work-item counter (zeroed before launch)
+    unsigned long long *stats;   // [0] residual evaluations, [1] lane steps
+    Physics phys;
+};
+
+// Time contraction of the modal coefficients into per-step spatial slabs.
+// One group = one (instance, interval, node time l).
+struct SlabArgs {
+    const double *cu, *cv;       // Legendre tensors, blocks of [P^d][T1]
+    const int64_t *coef_off;     // per group: offset of its (inst, iv) coefficient block
+    const int64_t *slab_off;     // per group: offset of its q = 0 slab in the table
+    const double *span;          // per group: t_{n,l} - t_{n-1}
+    const double *delta;         // per group: Delta_{n,l}
+    const double *h2;            // per group: 2 / h_n
+    const int32_t *nstar;        // per group: N*
+    const int32_t *deg;          // per group: M_n
+    int32_t n_groups;
+    int32_t P, PP, rows;         // rows = P^{d-1}
+    int64_t slab_stride;         // rows * 2 * PP
+    void *slab_table;
+};
+
+// Launch wrappers (hpsmc_kernels.hip).
+hipError_t launch_mode_product(const double *in, double *out, int64_t outer, int len_in, int len_out,
+                               int64_t inner, const double *mat, double alpha, int accumulate,
+                               hipStream_t s);
+hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t s);
+hipError_t launch_sample(const SampleArgs &a, int fp32, int samples_per_lane, int waves_per_block,
+                         int blocks, hipStream_t s);
+hipError_t launch_reduce_update(const double *part, int chunks, const NodeDesc *nodes, int64_t n_nodes,
+                                int64_t M, double *U, double *eps, double *sumsq,
+                                unsigned long long *maxbits, hipStream_t s);
+hipError_t launch_start_columns(double *U, const double *src, int64_t src_stride, int64_t src_off,
+                                int64_t dst_stride, int T1, int64_t count, int replicate, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
+hipError_t launch_eval(const double *cu, const double *cv, int dim, int P, int T1, double t_prev, double h,
+                       const double *pts, int64_t npts, double *out, hipStream_t s);
+hipError_t set_recurrence_tables();
+
+}  // namespace hpsmc

@@ -1,0 +1,723 @@
+// gfx950 kernels of the spectral Monte Carlo hot path (arXiv 2608.22190).
+//
+//   mode_product   -- nodal -> Legendre-tensor transform, one tensor mode at a
+//                     time (Sec. 2.3, eq. u_N); FP64.
+//   slabs          -- time contraction of the Legendre-tensor coefficients of
+//                     u* and of v* = Lap u* - d_t u* at every path step of every
+//                     node time: the spatial coefficient slab the walk reads.
+//   sample         -- persistent kernel: one wavefront per batch of
+//                     node-samples; Philox directions, sphere jumps with the
+//                     exit test (Lemma 2.1, eq. indexL), tensor-product Legendre
+//                     evaluation by three-term recurrence against the slab,
+//                     residual f(u*) + s + v* and its left-point path quadrature
+//                     (eq. interIQ); deterministic per-chunk FP64 sums.
+//   reduce_update  -- eps = sample mean (eq. varepsilon_1), U += eps
+//                     (Algorithm 1, Step 3), max|eps| (the stop metric).
+#include "hpsmc_internal.h"
+
+namespace hpsmc {
+
+// ---------------------------------------------------------------------------
+// Legendre three-term recurrence L_{k+1} = a_k x L_k - b_k L_{k-1},
+// a_k = (2k+1)/(k+1), b_k = k/(k+1).
+// ---------------------------------------------------------------------------
+struct RecTable {
+    double ad[kMaxP + 2], bd[kMaxP + 2];
+    float af[kMaxP + 2], bf[kMaxP + 2];
+};
+__constant__ RecTable c_rec;
+
+hipError_t set_recurrence_tables()
+{
+    RecTable t;
+    for (int k = 0; k < kMaxP + 2; ++k) {
+        t.ad[k] = (2.0 * k + 1.0) / (k + 1.0);
+        t.bd[k] = double(k) / (k + 1.0);
+        t.af[k] = float(t.ad[k]);
+        t.bf[k] = float(t.bd[k]);
+    }
+    return hipMemcpyToSymbol(HIP_SYMBOL(c_rec), &t, sizeof(t));
+}
+
+template <typename T> __device__ __forceinline__ T rec_a(int k);
+template <typename T> __device__ __forceinline__ T rec_b(int k);
+template <> __device__ __forceinline__ double rec_a<double>(int k) { return c_rec.ad[k]; }
+template <> __device__ __forceinline__ double rec_b<double>(int k) { return c_rec.bd[k]; }
+template <> __device__ __forceinline__ float rec_a<float>(int k) { return c_rec.af[k]; }
+template <> __device__ __forceinline__ float rec_b<float>(int k) { return c_rec.bf[k]; }
+
+// wave-uniform read-only data is read through the constant address space so
+// that uniform addresses become scalar loads feeding VALU operands directly
+template <typename T> using cptr = const __attribute__((address_space(4))) T *;
+template <typename T> __device__ __forceinline__ cptr<T> as_const(const T *p) { return (cptr<T>)p; }
+
+// ---------------------------------------------------------------------------
+// Math in the sampling precision.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double m_sin(double x) { return sin(x); }
+__device__ __forceinline__ float m_sin(float x) { return sinf(x); }
+__device__ __forceinline__ double m_cos(double x) { return cos(x); }
+__device__ __forceinline__ float m_cos(float x) { return cosf(x); }
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_fma(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float m_fma(float a, float b, float c) { return fmaf(a, b, c); }
+
+// uniform variate from one Philox word: FP64 uses all 32 bits, FP32 the top 24
+__device__ __forceinline__ double u01(uint32_t w, double) { return ((double)w + 0.5) * 0x1p-32; }
+__device__ __forceinline__ float u01(uint32_t w, float) { return ((float)(w >> 8) + 0.5f) * 0x1p-24f; }
+
+// direction angle 2*pi*u
+__device__ __forceinline__ void angle_dir(double u, double &c, double &s)
+{
+    const double th = 2.0 * 3.14159265358979323846 * u;
+    c = cos(th);
+    s = sin(th);
+}
+__device__ __forceinline__ void angle_dir(float u, float &c, float &s) { sincospif(2.0f * u, &s, &c); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 S-box with
+// multipliers D2511F53 / CD9E8D57 and Weyl key steps 9E3779B9 / BB67AE85.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1, uint32_t (&o)[4])
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    o[0] = c0; o[1] = c1; o[2] = c2; o[3] = c3;
+}
+
+// ---------------------------------------------------------------------------
+// Problem terms.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T f_of(const Physics &ph, T u)
+{
+    switch (ph.f_kind) {
+    case 0: return (T)ph.f_param[0] * u + (T)ph.f_param[1];
+    case 1: return u - u * u * u;
+    case 2: return m_sin(u);
+    case 3: return u * u / ((T)1 + u * u);
+    case 4: return -u * u * u;
+    case 5: return u * m_sin(u);
+    }
+    return (T)0;
+}
+
+template <typename T>
+__device__ __forceinline__ T fprime_of(const Physics &ph, T u)
+{
+    switch (ph.f_kind) {
+    case 0: return (T)ph.f_param[0];
+    case 1: return (T)1 - (T)3 * u * u;
+    case 2: return m_cos(u);
+    case 3: { T a = (T)1 + u * u; return (T)2 * u / (a * a); }
+    case 4: return (T)-3 * u * u;
+    case 5: return m_sin(u) + u * m_cos(u);
+    }
+    return (T)0;
+}
+
+// s = u_t - Lap u - f(u) at the manufactured exact solution
+template <typename T, int D>
+__device__ __forceinline__ T source_of(const Physics &ph, const T (&X)[D], T t)
+{
+    const T pi = (T)3.14159265358979323846;
+    T u, ut, lap;
+    switch (ph.src_kind) {
+    case 1: {
+        T p = m_exp(-t);
+#pragma unroll
+        for (int i = 0; i < D; ++i) p *= m_sin(pi * X[i]);
+        u = p; ut = -p; lap = -(T)D * pi * pi * p;
+        break;
+    }
+    case 2: {
+        T p = m_exp(-t);
+#pragma unroll
+        for (int i = 0; i < D; ++i) p *= m_cos((T)0.5 * pi * X[i]);
+        u = p; ut = -p; lap = (T)(-0.25 * D) * pi * pi * p;
+        break;
+    }
+    case 3: {
+        T om[D], a = (T)1, sig = (T)0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { om[i] = (T)1 - X[i] * X[i]; a *= om[i]; sig += X[i]; }
+        T lapa = 0, grada = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            T rest = (T)1;
+#pragma unroll
+            for (int m = 0; m < D; ++m) if (m != i) rest *= om[m];
+            lapa += (T)-2 * rest;
+            grada += (T)-2 * X[i] * rest;
+        }
+        const T S = m_sin(sig), C = m_cos(sig);
+        const T q = (T)1 + t * t;
+        const T Tt = m_exp(m_cos(t)) / q;
+        const T Tp = Tt * (-m_sin(t) - (T)2 * t / q);
+        u = a * S * Tt;
+        ut = a * S * Tp;
+        lap = Tt * (S * lapa + (T)2 * C * grada - (T)D * a * S);
+        break;
+    }
+    case 4: {
+        T om[D], a = (T)1;
+#pragma unroll
+        for (int i = 0; i < D; ++i) { om[i] = (T)1 - X[i] * X[i]; a *= om[i]; }
+        T lapa = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            T rest = (T)1;
+#pragma unroll
+            for (int m = 0; m < D; ++m) if (m != i) rest *= om[m];
+            lapa += (T)-2 * rest;
+        }
+        const T c0 = (T)ph.src_param[0], c1 = (T)ph.src_param[1], c2 = (T)ph.src_param[2];
+        const T g = c0 + c1 * t + c2 * t * t, gp = c1 + (T)2 * c2 * t;
+        u = a * g; ut = a * gp; lap = lapa * g;
+        break;
+    }
+    default:
+        return (T)0;
+    }
+    return ut - lap - f_of<T>(ph, u);
+}
+
+// ---------------------------------------------------------------------------
+// Tensor-product Legendre contraction of one step's slab.
+//   u(X) = sum_k Su[k] prod_i L_{k_i}(X_i),  v(X) likewise with Sv.
+// The last dimension's L values sit in registers (Ll); the outer dimensions
+// run as loops whose L values advance by the recurrence on the fly.  Slab rows
+// are wave-uniform: [u: PP][v: PP] per multi-index of the first d-1 dims.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int PMAX, int NS, int LV>
+__device__ __forceinline__ void contract(cptr<T> S, int P, int PP, const T (&X)[NS][D], const T (&W)[NS],
+                                         const T (&Ll)[NS][PMAX], T (&u)[NS], T (&v)[NS], int row)
+{
+    if constexpr (LV == D - 1) {
+        // rows are padded with zeros to a multiple of 4 modes and read 4 at a time
+        cptr<T> srow = S + (int64_t)row * (2 * PP);
+        T tu[NS], tv[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) { tu[s] = (T)0; tv[s] = (T)0; }
+#pragma unroll
+        for (int kb = 0; kb < PMAX / 4; ++kb) {
+            if (kb * 4 < P) {
+                T cu[4], cv[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) { cu[c] = srow[4 * kb + c]; cv[c] = srow[PP + 4 * kb + c]; }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) {
+                        tu[s] = m_fma(cu[c], Ll[s][4 * kb + c], tu[s]);
+                        tv[s] = m_fma(cv[c], Ll[s][4 * kb + c], tv[s]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            u[s] = m_fma(W[s], tu[s], u[s]);
+            v[s] = m_fma(W[s], tv[s], v[s]);
+        }
+    } else {
+        T Lp[NS], Lc[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) { Lp[s] = (T)0; Lc[s] = (T)1; }
+        for (int k = 0; k < P; ++k) {
+            T W2[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) W2[s] = W[s] * Lc[s];
+            contract<T, D, PMAX, NS, LV + 1>(S, P, PP, X, W2, Ll, u, v, row * P + k);
+            const T ak = rec_a<T>(k), bk = rec_b<T>(k);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const T nx = ak * X[s][LV] * Lc[s] - bk * Lp[s];
+                Lp[s] = Lc[s];
+                Lc[s] = nx;
+            }
+        }
+    }
+}
+
+// 64-lane FP64 sum with a fixed butterfly (deterministic)
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// ---------------------------------------------------------------------------
+// Persistent sampling kernel.  Each wavefront repeatedly takes one work item
+// (node, chunk of 64*NS samples) from a global counter until none is left.
+// ---------------------------------------------------------------------------
+template <typename T, int D, int PMAX, int NS>
+__global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    cptr<T> table = as_const((const T *)a.slab_table);
+    cptr<NodeDesc> nodes = as_const(a.nodes);
+    const int64_t total = a.n_nodes * (int64_t)a.chunks_per_node;
+    unsigned long long evals = 0, lsteps = 0;
+
+    for (;;) {
+        unsigned long long item = 0;
+        if (lane == 0) item = atomicAdd(a.work, 1ull);
+        const uint32_t lo = uniform_u32((uint32_t)item), hi = uniform_u32((uint32_t)(item >> 32));
+        const int64_t it = (int64_t)(((uint64_t)hi << 32) | lo);
+        if (it >= total) break;
+        const int64_t ni = it / a.chunks_per_node;
+        const int chunk = (int)(it - ni * a.chunks_per_node);
+        cptr<NodeDesc> nd = nodes + ni;
+
+        const T delta = (T)nd->delta, J = (T)nd->jump;
+        const double span = nd->span, t_prev = nd->t_prev, ddelta = nd->delta;
+        const int nstar = nd->nstar;
+        const uint32_t c0 = nd->c0, c3 = nd->c3 | (uint32_t)a.tag;
+        cptr<T> slab0 = table + nd->slab;
+        const int out = nd->out;
+
+        T X[NS][D], Y[NS][D], acc[NS], comp[NS];
+        bool alive[NS];
+        int64_t sample[NS];
+        uint32_t w[NS][4];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            sample[s] = (int64_t)chunk * (64 * NS) + s * 64 + lane;
+            alive[s] = sample[s] < a.M;
+#pragma unroll
+            for (int i = 0; i < D; ++i) X[s][i] = (T)nd->x0[i];
+            acc[s] = (T)0;
+            comp[s] = (T)0;
+        }
+
+        for (int q = 0; q < nstar; ++q) {
+            // ---- draw the jump direction and test the new ball centre
+            T dir[NS][D];
+            if constexpr (D == 1) {
+                if ((q & 127) == 0) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        philox(c0, (uint32_t)sample[s], (uint32_t)(q >> 7), c3, a.key0, a.key1, w[s]);
+                }
+                const int wi = (q >> 5) & 3, b = q & 31;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    uint32_t word = wi == 0 ? w[s][0] : wi == 1 ? w[s][1] : wi == 2 ? w[s][2] : w[s][3];
+                    dir[s][0] = ((word >> b) & 1u) ? (T)1 : (T)-1;
+                }
+            } else if constexpr (D == 2) {
+                if ((q & 3) == 0) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s)
+                        philox(c0, (uint32_t)sample[s], (uint32_t)(q >> 2), c3, a.key0, a.key1, w[s]);
+                }
+                const int wi = q & 3;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    uint32_t word = wi == 0 ? w[s][0] : wi == 1 ? w[s][1] : wi == 2 ? w[s][2] : w[s][3];
+                    angle_dir(u01(word, (T)0), dir[s][0], dir[s][1]);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    uint32_t ww[8];
+                    if constexpr (D <= 4) {
+                        uint32_t o[4];
+                        philox(c0, (uint32_t)sample[s], (uint32_t)q, c3, a.key0, a.key1, o);
+                        ww[0] = o[0]; ww[1] = o[1]; ww[2] = o[2]; ww[3] = o[3];
+                    } else {
+                        uint32_t o[4], o2[4];
+                        philox(c0, (uint32_t)sample[s], (uint32_t)(2 * q), c3, a.key0, a.key1, o);
+                        philox(c0, (uint32_t)sample[s], (uint32_t)(2 * q + 1), c3, a.key0, a.key1, o2);
+                        ww[0] = o[0]; ww[1] = o[1]; ww[2] = o[2]; ww[3] = o[3];
+                        ww[4] = o2[0]; ww[5] = o2[1]; ww[6] = o2[2]; ww[7] = o2[3];
+                    }
+                    T g[D + 1];
+#pragma unroll
+                    for (int k = 0; k < (D + 1) / 2; ++k) {
+                        const T r = m_sqrt((T)-2 * m_log(u01(ww[2 * k], (T)0)));
+                        T c, sn;
+                        angle_dir(u01(ww[2 * k + 1], (T)0), c, sn);
+                        g[2 * k] = r * c;
+                        g[2 * k + 1] = r * sn;
+                    }
+                    T nrm = 0;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) nrm += g[i] * g[i];
+                    nrm = m_sqrt(nrm);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) dir[s][i] = g[i] / nrm;
+                }
+            }
+            bool any_live = false;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (alive[s]) {
+                    ++lsteps;
+                    bool inside = true;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        Y[s][i] = m_fma(J, dir[s][i], X[s][i]);
+                        inside = inside && (fabs(Y[s][i]) < (T)1);
+                    }
+                    alive[s] = inside;   // eq. indexL: the path ends when the new centre has left
+                }
+                any_live = any_live || alive[s];
+            }
+            if (__ballot(any_live) == 0ull) break;
+
+            // ---- residual at the current centre X_q and time tau_q = t_{n,l} - q Delta
+            cptr<T> S = slab0 + (int64_t)q * a.slab_stride;
+            T Ll[NS][PMAX];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const T x = X[s][D - 1];
+                Ll[s][0] = (T)1;
+                if (PMAX > 1) Ll[s][1] = x;
+#pragma unroll
+                for (int k = 1; k + 1 < PMAX; ++k)
+                    Ll[s][k + 1] = (T)((2.0 * k + 1.0) / (k + 1.0)) * x * Ll[s][k] - (T)(k / (k + 1.0)) * Ll[s][k - 1];
+            }
+            T u[NS], v[NS], W[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) { u[s] = (T)0; v[s] = (T)0; W[s] = (T)1; }
+            contract<T, D, PMAX, NS, 0>(S, a.P, a.PP, X, W, Ll, u, v, 0);
+
+            const T tau = (T)(t_prev + (span - (double)q * ddelta));
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (alive[s]) {
+                    const T r = f_of<T>(a.phys, u[s]) + source_of<T, D>(a.phys, X[s], tau) + v[s];
+                    const T y = delta * r;
+                    if constexpr (sizeof(T) == 4) {   // Kahan-compensated FP32 path sum
+                        const T yc = y - comp[s];
+                        const T tt = acc[s] + yc;
+                        comp[s] = (tt - acc[s]) - yc;
+                        acc[s] = tt;
+                    } else {
+                        acc[s] += y;
+                    }
+#pragma unroll
+                    for (int i = 0; i < D; ++i) X[s][i] = Y[s][i];
+                    ++evals;
+                }
+            }
+        }
+
+        // ---- per-chunk sums in FP64 (fixed order), optional per-sample probe
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double Sv = (double)acc[s] - (double)comp[s];
+            s1 += Sv;
+            s2 += Sv * Sv;
+            if (a.probe != nullptr && sample[s] < a.m_probe && sample[s] < a.M)
+                a.probe[(int64_t)out * a.m_probe + sample[s]] = Sv;
+        }
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        if (lane == 0) {
+            double *pp = a.part + ((int64_t)out * a.chunks_per_node + chunk) * 2;
+            pp[0] = s1;
+            pp[1] = s2;
+        }
+    }
+    evals = wave_sum_u64(evals);
+    lsteps = wave_sum_u64(lsteps);
+    if (lane == 0) {
+        atomicAdd(a.stats + 0, evals);
+        atomicAdd(a.stats + 1, lsteps);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch of the sampling kernel over (precision, dim, mode bucket, NS).
+// ---------------------------------------------------------------------------
+template <typename T, int D, int PMAX>
+static hipError_t dispatch_ns(const SampleArgs &a, int ns, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (ns) {
+    case 1: hipLaunchKernelGGL((sample_kernel<T, D, PMAX, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((sample_kernel<T, D, PMAX, 2>), grid, block, 0, s, a); break;
+    case 4:
+        if constexpr (D <= 2) { hipLaunchKernelGGL((sample_kernel<T, D, PMAX, 4>), grid, block, 0, s, a); break; }
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t dispatch_p(const SampleArgs &a, int ns, dim3 grid, dim3 block, hipStream_t s)
+{
+    if (a.P <= 12) return dispatch_ns<T, D, 12>(a, ns, grid, block, s);
+    if constexpr (D <= 4) {
+        if (a.P <= 20) return dispatch_ns<T, D, 20>(a, ns, grid, block, s);
+    }
+    if constexpr (D <= 3) {
+        if (a.P <= 28) return dispatch_ns<T, D, 28>(a, ns, grid, block, s);
+        if (a.P <= 36) return dispatch_ns<T, D, 36>(a, ns, grid, block, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t dispatch_d(const SampleArgs &a, int ns, dim3 grid, dim3 block, hipStream_t s)
+{
+    switch (a.phys.dim) {
+    case 1: return dispatch_p<T, 1>(a, ns, grid, block, s);
+    case 2: return dispatch_p<T, 2>(a, ns, grid, block, s);
+    case 3: return dispatch_p<T, 3>(a, ns, grid, block, s);
+    case 4: return dispatch_p<T, 4>(a, ns, grid, block, s);
+    case 5: return dispatch_p<T, 5>(a, ns, grid, block, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_sample(const SampleArgs &a, int fp32, int samples_per_lane, int waves_per_block,
+                         int blocks, hipStream_t s)
+{
+    dim3 block(64 * waves_per_block), grid(blocks);
+    return fp32 ? dispatch_d<float>(a, samples_per_lane, grid, block, s)
+                : dispatch_d<double>(a, samples_per_lane, grid, block, s);
+}
+
+// ---------------------------------------------------------------------------
+// Mode product: out[o][a][i] (+)= alpha * sum_b mat[a][b] in[o][b][i].
+// ---------------------------------------------------------------------------
+__global__ void mode_product_kernel(const double *__restrict__ in, double *__restrict__ out, int64_t outer,
+                                    int len_in, int len_out, int64_t inner, const double *__restrict__ mat,
+                                    double alpha, int accumulate)
+{
+    const int64_t total = outer * len_out * inner;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % inner;
+        const int64_t r = idx / inner;
+        const int aa = (int)(r % len_out);
+        const int64_t o = r / len_out;
+        const double *src = in + o * len_in * inner + i;
+        const double *m = mat + (int64_t)aa * len_in;
+        double s = 0.0;
+        for (int b = 0; b < len_in; ++b) s = fma(m[b], src[(int64_t)b * inner], s);
+        out[idx] = accumulate ? fma(alpha, s, out[idx]) : alpha * s;
+    }
+}
+
+hipError_t launch_mode_product(const double *in, double *out, int64_t outer, int len_in, int len_out,
+                               int64_t inner, const double *mat, double alpha, int accumulate, hipStream_t s)
+{
+    const int64_t total = outer * len_out * inner;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(mode_product_kernel, dim3((unsigned)blocks), dim3(256), 0, s, in, out, outer, len_in,
+                       len_out, inner, mat, alpha, accumulate);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Slabs: for group g = (inst, iv, l) and step q < N*, the spatial coefficient
+// rows of u* and v* at the reference time xi = 2 (span - q Delta)/h - 1.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void slab_kernel(SlabArgs a)
+{
+    const int g = blockIdx.y;
+    const int nstar = a.nstar[g];
+    const int T1 = a.deg[g] + 1;
+    const int64_t total = (int64_t)nstar * a.slab_stride;
+    T *table = (T *)a.slab_table;
+    const double *cu = a.cu + a.coef_off[g], *cv = a.cv + a.coef_off[g];
+    const double span = a.span[g], delta = a.delta[g], h2 = a.h2[g];
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = idx / a.slab_stride;
+        const int64_t e = idx - q * a.slab_stride;
+        const int64_t row = e / (2 * a.PP);
+        const int rem = (int)(e - row * 2 * a.PP);
+        const int uv = rem / a.PP, kl = rem - uv * a.PP;
+        double val = 0.0;
+        if (kl < a.P) {
+            const double *c = (uv ? cv : cu) + (row * a.P + kl) * T1;
+            const double xi = h2 * (span - (double)q * delta) - 1.0;
+            double lp = 0.0, lc = 1.0;
+            for (int k = 0; k < T1; ++k) {
+                val = fma(c[k], lc, val);
+                const double nx = ((2.0 * k + 1.0) * xi * lc - k * lp) / (k + 1.0);
+                lp = lc;
+                lc = nx;
+            }
+        }
+        table[a.slab_off[g] + q * a.slab_stride + e] = (T)val;
+    }
+}
+
+hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t s)
+{
+    if (a.n_groups <= 0) return hipSuccess;
+    int64_t per = (int64_t)max_nstar * a.slab_stride;
+    int64_t bx = (per + 255) / 256;
+    if (bx > 16384) bx = 16384;
+    dim3 grid((unsigned)bx, (unsigned)a.n_groups);
+    if (fp32)
+        hipLaunchKernelGGL(slab_kernel<float>, grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(slab_kernel<double>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// eps = (1/M) sum of the chunk sums in chunk order; U += eps; max|eps|.
+// ---------------------------------------------------------------------------
+__global__ void reduce_update_kernel(const double *__restrict__ part, int chunks, const NodeDesc *__restrict__ nodes,
+                                     int64_t n_nodes, int64_t M, double *__restrict__ U, double *__restrict__ eps,
+                                     double *__restrict__ sumsq, unsigned long long *maxbits)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double mx = 0.0;
+    if (i < n_nodes) {
+        const NodeDesc &nd = nodes[i];
+        const double *p = part + (int64_t)nd.out * chunks * 2;
+        double s1 = 0.0, s2 = 0.0;
+        for (int c = 0; c < chunks; ++c) { s1 += p[2 * c]; s2 += p[2 * c + 1]; }
+        const double e = s1 / (double)M;
+        eps[nd.out] = e;
+        sumsq[nd.out] = s2;
+        U[nd.u_index] += e;
+        mx = fabs(e);
+        if (!(mx == mx)) mx = __longlong_as_double(0x7ff8000000000000ll);
+    }
+    // block max, then one atomic (max is order independent)
+    __shared__ double sm[256];
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const double b = sm[threadIdx.x + o];
+            if (!(b <= sm[threadIdx.x])) sm[threadIdx.x] = b;   // NaN wins
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(sm[0]));
+}
+
+hipError_t launch_reduce_update(const double *part, int chunks, const NodeDesc *nodes, int64_t n_nodes, int64_t M,
+                                double *U, double *eps, double *sumsq, unsigned long long *maxbits, hipStream_t s)
+{
+    if (n_nodes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_update_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, part, chunks,
+                       nodes, n_nodes, M, U, eps, sumsq, maxbits);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Column 0 of an interval (and optionally every column) from a source column.
+// ---------------------------------------------------------------------------
+__global__ void start_columns_kernel(double *__restrict__ U, const double *__restrict__ src, int64_t src_stride,
+                                     int64_t src_off, int64_t dst_stride, int T1, int64_t count, int replicate)
+{
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= count) return;
+    const double v = src[r * src_stride + src_off];
+    double *d = U + r * dst_stride;
+    if (replicate)
+        for (int l = 0; l < T1; ++l) d[l] = v;
+    else
+        d[0] = v;
+}
+
+hipError_t launch_start_columns(double *U, const double *src, int64_t src_stride, int64_t src_off, int64_t dst_stride,
+                                int T1, int64_t count, int replicate, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(start_columns_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, U, src,
+                       src_stride, src_off, dst_stride, T1, count, replicate);
+    return hipGetLastError();
+}
+
+__global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Off-node evaluation of u* and v* = Lap u* - d_t u* from the Legendre tensors.
+// ---------------------------------------------------------------------------
+__global__ void eval_kernel(const double *__restrict__ cu, const double *__restrict__ cv, int dim, int P, int T1,
+                            double t_prev, double h, const double *__restrict__ pts, int64_t npts,
+                            double *__restrict__ out)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= npts) return;
+    double L[kMaxDim][kMaxP], Lt[kMaxDeg + 1];
+    for (int i = 0; i < dim; ++i) {
+        const double x = pts[k * (dim + 1) + i];
+        L[i][0] = 1.0;
+        if (P > 1) L[i][1] = x;
+        for (int m = 1; m + 1 < P; ++m) L[i][m + 1] = ((2.0 * m + 1.0) * x * L[i][m] - m * L[i][m - 1]) / (m + 1.0);
+    }
+    const double xi = 2.0 * (pts[k * (dim + 1) + dim] - t_prev) / h - 1.0;
+    Lt[0] = 1.0;
+    if (T1 > 1) Lt[1] = xi;
+    for (int m = 1; m + 1 < T1; ++m) Lt[m + 1] = ((2.0 * m + 1.0) * xi * Lt[m] - m * Lt[m - 1]) / (m + 1.0);
+    int64_t np = 1;
+    for (int i = 0; i < dim; ++i) np *= P;
+    double u = 0.0, v = 0.0;
+    for (int64_t f = 0; f < np; ++f) {
+        int64_t r = f;
+        double w = 1.0;
+        for (int i = dim - 1; i >= 0; --i) { w *= L[i][r % P]; r /= P; }
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < T1; ++q) { a = fma(cu[f * T1 + q], Lt[q], a); b = fma(cv[f * T1 + q], Lt[q], b); }
+        u = fma(w, a, u);
+        v = fma(w, b, v);
+    }
+    out[2 * k] = u;
+    out[2 * k + 1] = v;
+}
+
+hipError_t launch_eval(const double *cu, const double *cv, int dim, int P, int T1, double t_prev, double h,
+                       const double *pts, int64_t npts, double *out, hipStream_t s)
+{
+    if (npts <= 0) return hipSuccess;
+    hipLaunchKernelGGL(eval_kernel, dim3((unsigned)((npts + 63) / 64)), dim3(64), 0, s, cu, cv, dim, P, T1, t_prev,
+                       h, pts, npts, out);
+    return hipGetLastError();
+}
+
+}  // namespace hpsmc

@@ -1,0 +1,283 @@
+"""ctypes binding of libhpsmc.so (include/hpsmc.h): argument marshalling only.
+
+Every step of the hot path runs in the HIP library; this module converts
+workload descriptions and NumPy / torch buffers into the C structures and
+pointers the ABI takes.  The binding raises if the library is missing: there
+is no CPU fallback.
+
+PyTorch supplies device memory and streams: any ``stream`` argument may be a
+``torch.cuda.Stream`` (or its raw ``cuda_stream`` handle), and the
+``on_device`` copies accept CUDA tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpsmc.so")
+
+F_KINDS = {"affine": 0, "u_minus_u3": 1, "sin": 2, "u2_over_1pu2": 3, "neg_u3": 4, "u_sin_u": 5}
+SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4}
+IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
+SCHEDULES = {"sequential": 0, "sweeps": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSUP", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED"}
+
+
+class HpsmcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hpsmc_problem(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("n", C.c_int32), ("n_intervals", C.c_int32), ("n_instances", C.c_int32),
+        ("t_breaks", C.POINTER(C.c_double)), ("degree", C.POINTER(C.c_int32)), ("nstar", C.POINTER(C.c_int32)),
+        ("f_kind", C.c_int32), ("src_kind", C.c_int32), ("ic_kind", C.c_int32), ("schedule", C.c_int32),
+        ("f_param", C.c_double * 4), ("src_param", C.c_double * 8), ("ic_param", C.c_double * 4),
+        ("ic_data", C.POINTER(C.c_double)),
+        ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
+        ("precision", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class hpsmc_stats_t(C.Structure):
+    _fields_ = [("path_steps", C.c_uint64), ("lane_steps", C.c_uint64), ("node_samples", C.c_uint64),
+                ("n_records", C.c_int32), ("status_flags", C.c_int32), ("sample_launches", C.c_int32),
+                ("recon_launches", C.c_int32), ("sample_ms", C.c_double), ("recon_ms", C.c_double),
+                ("slab_ms", C.c_double), ("max_eps", C.c_double * 4096)]
+
+
+class hpsmc_launch(C.Structure):
+    _fields_ = [("samples_per_lane", C.c_int32), ("waves_per_block", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32)]
+
+
+# name: (restype, argtypes)
+_SIGS = {
+    "hpsmc_create": (C.c_int, [C.POINTER(hpsmc_problem), C.POINTER(C.c_void_p)]),
+    "hpsmc_destroy": (None, [C.c_void_p]),
+    "hpsmc_grid": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "hpsmc_solve": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hpsmc_start_interval": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_iterate": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "hpsmc_sweep": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_get_nodes": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_set_nodes": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_get_increment": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hpsmc_eval": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "hpsmc_set_probe": (C.c_int, [C.c_void_p, C.c_int64]),
+    "hpsmc_get_probe": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "hpsmc_set_launch": (C.c_int, [C.c_void_p, C.POINTER(hpsmc_launch)]),
+    "hpsmc_get_launch": (C.c_int, [C.c_void_p, C.POINTER(hpsmc_launch)]),
+    "hpsmc_tune": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64, C.c_char_p, C.c_void_p]),
+    "hpsmc_stats": (C.c_int, [C.c_void_p, C.POINTER(hpsmc_stats_t), C.c_void_p]),
+    "hpsmc_reset_stats": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "hpsmc_loss_grad_c0": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_last_error": (C.c_char_p, []),
+}
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def lib():
+    """Load libhpsmc.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_22190_amd.build`")
+        _lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(_lib, name)
+            fn.restype = res
+            fn.argtypes = args
+    return _lib
+
+
+def _check(status, what):
+    if status != 0:
+        msg = lib().hpsmc_last_error().decode()
+        raise HpsmcError(status, f"{what}: {msg}")
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def make_problem(wl):
+    """hpsmc_problem from a workload description; returns (struct, keep-alive list)."""
+    tb = np.ascontiguousarray(wl.t_breaks, dtype=np.float64)
+    deg = np.ascontiguousarray(wl.degree, dtype=np.int32)
+    ns = np.ascontiguousarray(wl.nstar, dtype=np.int32)
+    ic = None if wl.ic_data is None else np.ascontiguousarray(wl.ic_data, dtype=np.float64).reshape(-1)
+    p = hpsmc_problem()
+    p.dim, p.n, p.n_intervals, p.n_instances = wl.dim, wl.n, len(wl.degree), wl.n_instances
+    p.t_breaks = tb.ctypes.data_as(C.POINTER(C.c_double))
+    p.degree = deg.ctypes.data_as(C.POINTER(C.c_int32))
+    p.nstar = ns.ctypes.data_as(C.POINTER(C.c_int32))
+    p.f_kind, p.src_kind, p.ic_kind = F_KINDS[wl.f], SRC_KINDS[wl.src], IC_KINDS[wl.ic]
+    p.schedule = SCHEDULES[wl.schedule]
+    for i, v in enumerate(wl.f_param):
+        p.f_param[i] = v
+    for i, v in enumerate(wl.src_param):
+        p.src_param[i] = v
+    for i, v in enumerate(wl.ic_param):
+        p.ic_param[i] = v
+    p.ic_data = ic.ctypes.data_as(C.POINTER(C.c_double)) if ic is not None else C.POINTER(C.c_double)()
+    p.M, p.iters, p.fresh_per_iter, p.seed = wl.M, wl.iters, int(wl.fresh_per_iter), wl.seed
+    p.precision = PRECISIONS[wl.precision]
+    return p, [tb, deg, ns, ic]
+
+
+# ------------------------------------------------------------ C-ABI mirrors
+def hpsmc_create(wl):
+    p, keep = make_problem(wl)
+    h = C.c_void_p()
+    _check(lib().hpsmc_create(C.byref(p), C.byref(h)), "hpsmc_create")
+    return h
+
+
+def hpsmc_destroy(h):
+    lib().hpsmc_destroy(h)
+
+
+class Plan:
+    """Owns one hpsmc_plan; methods mirror the C entry points by name."""
+
+    def __init__(self, wl):
+        self.wl = wl
+        self.h = hpsmc_create(wl)
+        self.nsp = wl.n ** wl.dim
+
+    def close(self):
+        if self.h:
+            hpsmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- grid and driving
+    def hpsmc_grid(self, iv=0):
+        x = np.zeros(self.wl.n)
+        t = np.zeros(self.wl.degree[iv] + 1)
+        _check(lib().hpsmc_grid(self.h, iv, _ptr(x), _ptr(t)), "hpsmc_grid")
+        return x, t
+
+    def hpsmc_solve(self, stream=None):
+        _check(lib().hpsmc_solve(self.h, _stream(stream)), "hpsmc_solve")
+
+    def hpsmc_start_interval(self, iv, stream=None):
+        _check(lib().hpsmc_start_interval(self.h, iv, _stream(stream)), "hpsmc_start_interval")
+
+    def hpsmc_iterate(self, iv, tag, stream=None):
+        _check(lib().hpsmc_iterate(self.h, iv, tag, _stream(stream)), "hpsmc_iterate")
+
+    def hpsmc_sweep(self, tag, stream=None):
+        _check(lib().hpsmc_sweep(self.h, tag, _stream(stream)), "hpsmc_sweep")
+
+    # -- data in / out
+    def _nodes_shape(self, iv):
+        return (self.wl.n_instances, self.nsp, self.wl.degree[iv] + 1)
+
+    def hpsmc_get_nodes(self, iv, out=None, stream=None):
+        on_dev = out is not None and hasattr(out, "data_ptr")
+        if out is None:
+            out = np.zeros(self._nodes_shape(iv))
+        _check(lib().hpsmc_get_nodes(self.h, iv, _ptr(out), int(on_dev), _stream(stream)), "hpsmc_get_nodes")
+        return out
+
+    def hpsmc_set_nodes(self, iv, values, stream=None):
+        on_dev = hasattr(values, "data_ptr")
+        if not on_dev:
+            values = np.ascontiguousarray(values, dtype=np.float64).reshape(self._nodes_shape(iv))
+        _check(lib().hpsmc_set_nodes(self.h, iv, _ptr(values), int(on_dev), _stream(stream)), "hpsmc_set_nodes")
+
+    def hpsmc_get_increment(self, iv, stream=None):
+        cnt = (self.wl.n_instances, self.nsp * self.wl.degree[iv])
+        eps, ssq = np.zeros(cnt), np.zeros(cnt)
+        _check(lib().hpsmc_get_increment(self.h, iv, _ptr(eps), _ptr(ssq), _stream(stream)), "hpsmc_get_increment")
+        return eps, ssq
+
+    def hpsmc_eval(self, iv, inst, pts, stream=None):
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, self.wl.dim + 1)
+        out = np.zeros((pts.shape[0], 2))
+        _check(lib().hpsmc_eval(self.h, iv, inst, _ptr(pts), pts.shape[0], _ptr(out), _stream(stream)), "hpsmc_eval")
+        return out
+
+    def hpsmc_set_probe(self, m_probe):
+        _check(lib().hpsmc_set_probe(self.h, int(m_probe)), "hpsmc_set_probe")
+        self.m_probe = int(m_probe)
+
+    def hpsmc_get_probe(self, iv, stream=None):
+        out = np.zeros((self.wl.n_instances, self.nsp * self.wl.degree[iv], self.m_probe))
+        _check(lib().hpsmc_get_probe(self.h, iv, _ptr(out), _stream(stream)), "hpsmc_get_probe")
+        return out
+
+    # -- launch shape and tuning
+    def hpsmc_set_launch(self, samples_per_lane, waves_per_block, blocks_per_cu):
+        l = hpsmc_launch(samples_per_lane, waves_per_block, blocks_per_cu, 0)
+        _check(lib().hpsmc_set_launch(self.h, C.byref(l)), "hpsmc_set_launch")
+
+    def hpsmc_get_launch(self):
+        l = hpsmc_launch()
+        _check(lib().hpsmc_get_launch(self.h, C.byref(l)), "hpsmc_get_launch")
+        return (l.samples_per_lane, l.waves_per_block, l.blocks_per_cu)
+
+    def hpsmc_tune(self, iv=0, m_tune=0, cache_path=None, stream=None):
+        cp = cache_path.encode() if cache_path else None
+        _check(lib().hpsmc_tune(self.h, iv, int(m_tune), cp, _stream(stream)), "hpsmc_tune")
+        return self.hpsmc_get_launch()
+
+    # -- counters
+    def hpsmc_stats(self, stream=None):
+        s = hpsmc_stats_t()
+        _check(lib().hpsmc_stats(self.h, C.byref(s), _stream(stream)), "hpsmc_stats")
+        return {"path_steps": s.path_steps, "lane_steps": s.lane_steps, "node_samples": s.node_samples,
+                "max_eps": np.array(s.max_eps[:s.n_records]), "status_flags": s.status_flags,
+                "sample_launches": s.sample_launches, "recon_launches": s.recon_launches,
+                "sample_ms": s.sample_ms, "recon_ms": s.recon_ms, "slab_ms": s.slab_ms}
+
+    def hpsmc_reset_stats(self, stream=None):
+        _check(lib().hpsmc_reset_stats(self.h, _stream(stream)), "hpsmc_reset_stats")
+
+    # -- gradient
+    def hpsmc_loss_grad_c0(self, target, stream=None):
+        on_dev = hasattr(target, "data_ptr")
+        I = self.wl.n_instances
+        if on_dev:
+            import torch
+            loss = torch.zeros(I, dtype=torch.float64, device=target.device)
+            grad = torch.zeros((I, self.nsp), dtype=torch.float64, device=target.device)
+        else:
+            target = np.ascontiguousarray(target, dtype=np.float64).reshape(I, self.nsp)
+            loss, grad = np.zeros(I), np.zeros((I, self.nsp))
+        _check(lib().hpsmc_loss_grad_c0(self.h, _ptr(target), _ptr(loss), _ptr(grad), int(on_dev),
+                                        _stream(stream)), "hpsmc_loss_grad_c0")
+        return loss, grad
