@@ -41,15 +41,22 @@ def flops_per_eval(dim, P):
     return 4 * cont + 3 * dim * (P - 2)
 
 
-def run_gpu(wl, steps, warmup, launch, torch):
+def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256):
     from paper_2608_22190_amd import hpsmc
     stream = torch.cuda.Stream()
     with hpsmc.Plan(wl) as plan:
         if launch:
             plan.hpsmc_set_launch(*launch)
+        elif tune_cache:
+            t0 = time.perf_counter()
+            plan.hpsmc_tune(0, m_tune, tune_cache, stream=stream)
+            print(f"[bench] {wl.precision} launch {plan.hpsmc_get_launch()} ({time.perf_counter() - t0:.1f}s)",
+                  file=sys.stderr, flush=True)
         plan.hpsmc_start_interval(0, stream=stream)
         for w in range(warmup):
             plan.hpsmc_iterate(0, w, stream=stream)
+            stream.synchronize()
+            print(f"[bench] {wl.precision} warmup {w + 1}/{warmup}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         plan.hpsmc_reset_stats(stream=stream)
         plan.hpsmc_start_interval(0, stream=stream)
@@ -57,6 +64,10 @@ def run_gpu(wl, steps, warmup, launch, torch):
         t0 = time.perf_counter()
         for k in range(steps):
             plan.hpsmc_iterate(0, k, stream=stream)
+            if steps > 1:
+                stream.synchronize()
+                print(f"[bench] {wl.precision} step {k + 1}/{steps} {time.perf_counter() - t0:.2f}s",
+                      file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         st = plan.hpsmc_stats(stream=stream)
@@ -100,7 +111,10 @@ def main():
     ap.add_argument("--m-slice", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--launch", type=str, default="", help="samples_per_lane,waves_per_block,blocks_per_cu")
+    ap.add_argument("--launch", type=str, default="",
+                    help="samples_per_lane,waves_per_block,blocks_per_cu,round_steps (skips the tuner)")
+    ap.add_argument("--tune-cache", type=str, default=os.path.join(ROOT, "paper_2608_22190_amd", "tuned_launch.json"),
+                    help="autotuner cache (looked up; tuned and written when the entry is missing)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (one process, one device).",
@@ -118,13 +132,13 @@ def main():
     base = W.c2_long_time(M=args.m_slice, iters=args.steps, n_intervals=1)
     P = base.n + 2
     nodes = base.nsp * base.degree[0]
-    r32 = run_gpu(base.with_(precision="fp32"), args.steps, args.warmup, launch, torch)
+    r32 = run_gpu(base.with_(precision="fp32"), args.steps, args.warmup, launch, torch, args.tune_cache)
     ns_step = nodes * base.M
     value = ns_step * args.steps / r32["seconds"]
     st = r32["stats"]
     fpe = flops_per_eval(base.dim, P)
     k_ms = st["sample_ms"] / max(1, st["sample_launches"])
-    evals_per_launch = st["path_steps"] / max(1, st["sample_launches"])
+    evals_per_launch = st["path_steps"] / max(1, st["advance_launches"])
     achieved = fpe * evals_per_launch / (k_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "node-samples/s", "n_gpus": 1, "steps": args.steps,
@@ -137,20 +151,22 @@ def main():
                    "max_nstar": int(max(base.nstar)), "launch": list(r32["launch"])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "sample_kernel<float,2,28,NS>", "flops_per_eval": fpe,
+                     "kernel": "advance_kernel<float,2,28,NS>", "flops_per_eval": fpe,
                      "evals_per_launch": evals_per_launch, "avg_launch_ms": k_ms,
                      "lane_utilization": st["path_steps"] / max(1, st["lane_steps"])},
         "path_steps_per_s": st["path_steps"] / r32["seconds"],
         "mean_path_length": st["path_steps"] / max(1, st["node_samples"]),
         "reconstruction_ms_per_step": st["recon_ms"] / max(1, st["recon_launches"]),
-        "slab_ms_per_step": st["slab_ms"] / max(1, st["sample_launches"]),
+        "slab_ms_per_step": st["slab_ms"] / args.steps,
+        "sampling_span_ms_per_step": st["sampling_span_ms"] / args.steps,
+        "advance_launches_per_step": st["advance_launches"] / args.steps,
     }
     if not args.no_fp64:
-        r64 = run_gpu(base.with_(precision="fp64"), args.steps, args.warmup, launch, torch)
+        r64 = run_gpu(base.with_(precision="fp64"), args.steps, args.warmup, launch, torch, args.tune_cache)
         v64 = ns_step * args.steps / r64["seconds"]
         s64 = r64["stats"]
         k64 = s64["sample_ms"] / max(1, s64["sample_launches"])
-        a64 = fpe * s64["path_steps"] / max(1, s64["sample_launches"]) / (k64 * 1e-3) / 1e12
+        a64 = fpe * s64["path_steps"] / max(1, s64["advance_launches"]) / (k64 * 1e-3) / 1e12
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["seconds"] / args.steps,
                        "roofline_achieved_tflops": a64, "roofline_frac": a64 / FP64_PEAK_TFLOPS}
         out["fp32_over_fp64_speedup"] = value / v64

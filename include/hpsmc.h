@@ -110,21 +110,26 @@ typedef struct {
     uint64_t node_samples;     /* (node, sample) estimates                       */
     int32_t n_records;         /* entries filled in max_eps                      */
     int32_t status_flags;      /* bit 0: non-finite increment seen              */
-    int32_t sample_launches;   /* sampling-kernel launches timed                */
+    int32_t sample_launches;   /* sampling-kernel launches timed (one per round) */
     int32_t recon_launches;    /* reconstructions timed                         */
-    double sample_ms;          /* summed sampling-kernel time (HIP events on the
-                                  launching stream), milliseconds               */
+    double sample_ms;          /* summed duration of those launches (HIP events
+                                  on the launching stream), milliseconds        */
+    double sampling_span_ms;   /* summed span of whole sampling phases (rounds,
+                                  their prep kernels and launch gaps)           */
     double recon_ms;           /* summed reconstruction time (all its kernels)   */
     double slab_ms;            /* summed time-contraction (slab) kernel time     */
+    int64_t advance_launches;  /* path-advancing kernel launches, timed or not   */
     double max_eps[4096];      /* max|eps| per (interval, iteration) or sweep    */
 } hpsmc_stats_t;
 
 /* Sampling-kernel launch shape (chosen by hpsmc_tune or set directly). */
 typedef struct {
-    int32_t samples_per_lane;  /* 1, 2 or 4                                      */
-    int32_t waves_per_block;   /* 1..16                                           */
+    int32_t samples_per_lane;  /* 1, 2 or 4 (4 only for dim <= 2)               */
+    int32_t waves_per_block;   /* 1..4                                            */
     int32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu          */
-    int32_t reserved;
+    int32_t round_steps;       /* walk steps per round of the path-advancing
+                                  kernel (multiple of 4 in 64..4096; 0 keeps
+                                  the current value)                             */
 } hpsmc_launch;
 
 /* Validate the problem, compute the grid and transform matrices on the host,

@@ -219,6 +219,15 @@ struct NodeSet {               // the nodes one sampling launch covers
     double *eps = nullptr, *sumsq = nullptr, *probe = nullptr;
     int64_t probe_cap = 0;
     std::vector<int32_t> ivs;  // intervals covered
+    // round-based sampling (slabs staged in LDS)
+    bool rounds = false;
+    std::vector<GroupDesc> ghost;
+    GroupDesc *gdev = nullptr;
+    int64_t ms = 0;            // samples per slice
+    void *state[2] = {nullptr, nullptr};
+    uint32_t *live = nullptr;  // [2][n_groups]
+    int64_t *prefix = nullptr; // [n_groups + 1]
+    double *result = nullptr;  // [n][ms]
 };
 
 }  // namespace hpsmc
@@ -234,7 +243,9 @@ struct hpsmc_plan {
     std::vector<std::vector<double>> xi, tnodes;   // per interval: reference LGL nodes, t_{n,l}
     bool fp32 = false, poisoned = false;
     int cus = 0;
-    hpsmc_launch launch{2, 4, 8, 0};
+    hpsmc_launch launch{2, 4, 8, 256};
+    int32_t round_steps = 256;           // walk steps per round
+    size_t round_budget = (size_t)16 << 30;   // bytes for path states and per-sample results
 
     // device memory
     double *U = nullptr;                 // all intervals, [iv block][inst][j][l]
@@ -256,8 +267,9 @@ struct hpsmc_plan {
     int64_t node_samples = 0;
     // HIP-event timing of the sampling, slab and reconstruction kernels
     struct EvPair { hipEvent_t a = nullptr, b = nullptr; };
-    std::vector<EvPair> ev_sample, ev_slab, ev_recon;
-    size_t n_sample = 0, n_slab = 0, n_recon = 0;
+    std::vector<EvPair> ev_sample, ev_slab, ev_recon, ev_span;
+    size_t n_sample = 0, n_slab = 0, n_recon = 0, n_span = 0;
+    int64_t n_advance = 0;                   // advance-kernel launches (round mode)
     int32_t n_records = 0, sweep_count = 0;
 };
 
@@ -273,7 +285,7 @@ static int64_t ipow(int64_t b, int e)
 // next event pair of a pool (created on first use); null when the pool is full
 static hpsmc_plan::EvPair *next_pair(std::vector<hpsmc_plan::EvPair> &pool, size_t &used)
 {
-    if (used >= 4096) return nullptr;
+    if (used >= 16384) return nullptr;
     if (used == pool.size()) {
         hpsmc_plan::EvPair e;
         if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
@@ -408,10 +420,31 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     }
     set.n = (int64_t)set.host.size();
     if (set.n > (int64_t)0x7fffffff) return fail(HPSMC_EINVAL, "too many nodes");
-    // longest expected paths first (stable for determinism)
-    std::stable_sort(set.host.begin(), set.host.end(), [d](const NodeDesc &a, const NodeDesc &b) {
-        return expected_cost(a, d) > expected_cost(b, d);
-    });
+    // rounds need the slab of one step in LDS (two buffers, at most 4 vectors per thread of a 4-wave block)
+    const int64_t slab_bytes = stride * T;
+    set.rounds = d <= 3 && slab_bytes <= 16384;
+    if (set.rounds) {
+        // group descriptors: nodes were generated group by group
+        const int64_t per = plan->nsp;
+        for (size_t g = 0; g < coef_off.size(); ++g) {
+            GroupDesc gd{};
+            gd.delta = delta[g];
+            gd.jump = std::sqrt(2.0 * d * delta[g]);
+            gd.span = span[g];
+            gd.node_begin = (int32_t)(g * per);
+            gd.node_count = (int32_t)per;
+            gd.t_prev = set.host[g * per].t_prev;
+            gd.slab = slab_off[g];
+            gd.nstar = nst[g];
+            gd.c3 = set.host[g * per].c3;
+            set.ghost.push_back(gd);
+        }
+    } else {
+        // longest expected paths first (stable for determinism)
+        std::stable_sort(set.host.begin(), set.host.end(), [d](const NodeDesc &a, const NodeDesc &b) {
+            return expected_cost(a, d) > expected_cost(b, d);
+        });
+    }
     set.n_groups = (int32_t)coef_off.size();
     set.max_nstar = *std::max_element(nst.begin(), nst.end());
     set.slab_elems = slab_pos;
@@ -447,7 +480,23 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     sa.slab_stride = stride;
     if ((st = dalloc(plan, (void **)&set.eps, sizeof(double) * set.n))) return st;
     if ((st = dalloc(plan, (void **)&set.sumsq, sizeof(double) * set.n))) return st;
-    (void)T;
+    if (set.rounds) {
+        const size_t sb = path_state_bytes(plan->fp32, d);
+        const int64_t per_sample = (int64_t)(2 * sb + sizeof(double));
+        int64_t ms = (int64_t)(plan->round_budget / (size_t)(per_sample * set.n));
+        ms = std::max<int64_t>(1, std::min<int64_t>(ms, plan->pb.M));
+        set.ms = ms;
+        for (size_t g = 0; g < set.ghost.size(); ++g) set.ghost[g].path_off = (int64_t)set.ghost[g].node_begin * ms;
+        const size_t G = set.ghost.size();
+        if ((st = dalloc(plan, (void **)&set.gdev, sizeof(GroupDesc) * G))) return st;
+        if ((st = dalloc(plan, &set.state[0], sb * set.n * ms))) return st;
+        if ((st = dalloc(plan, &set.state[1], sb * set.n * ms))) return st;
+        if ((st = dalloc(plan, (void **)&set.live, sizeof(uint32_t) * 2 * G))) return st;
+        if ((st = dalloc(plan, (void **)&set.prefix, sizeof(int64_t) * (G + 1)))) return st;
+        if ((st = dalloc(plan, (void **)&set.result, sizeof(double) * set.n * ms))) return st;
+        if (hipMemcpy(set.gdev, set.ghost.data(), sizeof(GroupDesc) * G, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(HPSMC_EDEVICE, "upload of group descriptors failed");
+    }
     return HPSMC_OK;
 }
 
@@ -458,6 +507,12 @@ static void free_set(NodeSet &s)
     (void)hipFree(s.eps);
     (void)hipFree(s.sumsq);
     (void)hipFree(s.probe);
+    (void)hipFree(s.gdev);
+    (void)hipFree(s.state[0]);
+    (void)hipFree(s.state[1]);
+    (void)hipFree(s.live);
+    (void)hipFree(s.prefix);
+    (void)hipFree(s.result);
     s = NodeSet{};
 }
 
@@ -527,6 +582,82 @@ static hpsmc_status reconstruct(hpsmc_plan *plan, int iv, hipStream_t s)
     return HPSMC_OK;
 }
 
+static Physics physics_of(const hpsmc_plan *plan)
+{
+    Physics ph{};
+    ph.dim = plan->d;
+    ph.f_kind = plan->pb.f_kind;
+    ph.src_kind = plan->pb.src_kind;
+    memcpy(ph.f_param, plan->pb.f_param, sizeof(ph.f_param));
+    memcpy(ph.src_param, plan->pb.src_param, sizeof(ph.src_param));
+    return ph;
+}
+
+// Round-based sampling of one node set: slices of samples, each advanced in
+// rounds of round_steps walk steps with compaction between rounds.
+static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
+{
+    const int ns = plan->launch.samples_per_lane, waves = plan->launch.waves_per_block;
+    const int nthr = 64 * waves;
+    const int64_t nvec = set.slab.slab_stride * (plan->fp32 ? 4 : 8) / 16;
+    if (nvec > 4LL * nthr) return fail(HPSMC_EINVAL, "slab too large for this block size; use more waves per block");
+    const size_t lds = (size_t)2 * ((nvec + 1) & ~1LL) * 16;
+    const int C = plan->round_steps;
+    const int R = (set.max_nstar + C - 1) / C;
+    const int G = (int)set.ghost.size();
+    RoundArgs a{};
+    a.groups = set.gdev;
+    a.nodes = set.dev;
+    a.n_groups = G;
+    a.steps = C;
+    a.batch = nthr * ns;
+    a.batch_prefix = set.prefix;
+    a.result = set.result;
+    a.P = plan->P;
+    a.PP = plan->PP;
+    a.tag = tag;
+    a.key0 = (uint32_t)plan->pb.seed;
+    a.key1 = (uint32_t)(plan->pb.seed >> 32);
+    a.slab_table = plan->slab_table;
+    a.slab_stride = set.slab.slab_stride;
+    a.work = plan->counters;
+    a.stats = plan->counters + 1;
+    a.phys = physics_of(plan);
+    const int blocks = std::max(1, plan->cus * plan->launch.blocks_per_cu);
+    hpsmc_plan::EvPair *ek = next_pair(plan->ev_span, plan->n_span);
+    if (ek) HIP_TRY(hipEventRecord(ek->a, s));
+    int first = 1;
+    for (int64_t m0 = 0; m0 < plan->pb.M; m0 += set.ms) {
+        const int64_t mc = std::min<int64_t>(set.ms, plan->pb.M - m0);
+        a.m0 = m0;
+        a.mcount = mc;
+        for (int r = 0; r < R; ++r) {
+            a.round = r;
+            a.state_in = set.state[r & 1];
+            a.state_out = set.state[(r + 1) & 1];
+            a.live_in = set.live + (r & 1) * G;
+            a.live_out = set.live + ((r + 1) & 1) * G;
+            HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, a.live_in, a.live_out, set.prefix, plan->counters, s));
+            hpsmc_plan::EvPair *ea = next_pair(plan->ev_sample, plan->n_sample);
+            if (ea) HIP_TRY(hipEventRecord(ea->a, s));
+            HIP_TRY(launch_advance(a, plan->fp32, ns, waves, blocks, lds, s));
+            if (ea) HIP_TRY(hipEventRecord(ea->b, s));
+        }
+        HIP_TRY(launch_slice_reduce(set.result, set.n, mc, plan->part, first, s));
+        if (set.probe && plan->m_probe > 0 && m0 == 0)
+            HIP_TRY(hipMemcpy2DAsync(set.probe, plan->m_probe * 8, set.result, mc * 8,
+                                     std::min<int64_t>(plan->m_probe, mc) * 8, set.n, hipMemcpyDeviceToDevice, s));
+        first = 0;
+    }
+    if (ek) HIP_TRY(hipEventRecord(ek->b, s));
+    plan->n_advance += (int64_t)R * ((plan->pb.M + set.ms - 1) / set.ms);
+    unsigned long long *mb = plan->maxbits + std::min(record, 4095);
+    HIP_TRY(launch_reduce_update(plan->part, 1, set.dev, set.n, plan->pb.M, plan->U, set.eps, set.sumsq, mb, s));
+    plan->node_samples += set.n * plan->pb.M;
+    plan->n_records = std::max(plan->n_records, std::min(record, 4095) + 1);
+    return HPSMC_OK;
+}
+
 static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
 {
     const int ns = plan->launch.samples_per_lane;
@@ -536,6 +667,7 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
     if (es) HIP_TRY(hipEventRecord(es->a, s));
     HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
     if (es) HIP_TRY(hipEventRecord(es->b, s));
+    if (set.rounds) return sample_rounds(plan, set, tag, record, s);
     HIP_TRY(launch_fill_u64(plan->counters, 1, 0ull, s));
     SampleArgs a{};
     a.nodes = set.dev;
@@ -601,7 +733,7 @@ void hpsmc_destroy(hpsmc_plan *plan)
 {
     if (!plan) return;
     for (auto &s : plan->sets) free_set(s);
-    for (auto *pool : {&plan->ev_sample, &plan->ev_slab, &plan->ev_recon})
+    for (auto *pool : {&plan->ev_sample, &plan->ev_slab, &plan->ev_recon, &plan->ev_span})
         for (auto &e : *pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     void *ptrs[] = {plan->U, plan->cu, plan->cv, plan->tmp0, plan->tmp1, plan->ic, plan->mats,
                     plan->slab_table, plan->part, plan->counters, plan->maxbits};
@@ -932,7 +1064,11 @@ hpsmc_status hpsmc_set_launch(hpsmc_plan *plan, const hpsmc_launch *l)
     const bool ns_ok = l->samples_per_lane == 1 || l->samples_per_lane == 2 || (l->samples_per_lane == 4 && plan->d <= 2);
     if (!ns_ok || l->waves_per_block < 1 || l->waves_per_block > 4 || l->blocks_per_cu < 1 || l->blocks_per_cu > 64)
         return fail(HPSMC_EINVAL, "launch shape out of range");
+    if (l->round_steps != 0 && (l->round_steps < 64 || l->round_steps > 4096 || l->round_steps % 4 != 0))
+        return fail(HPSMC_EINVAL, "round_steps must be 0 or a multiple of 4 in 64..4096");
     plan->launch = *l;
+    if (l->round_steps) plan->round_steps = l->round_steps;
+    plan->launch.round_steps = plan->round_steps;
     return HPSMC_OK;
 }
 
@@ -956,9 +1092,11 @@ hpsmc_status hpsmc_stats(const hpsmc_plan *plan, hpsmc_stats_t *out, void *strea
         hipStreamSynchronize(s) != hipSuccess)
         return fail(HPSMC_EDEVICE, "stats copy failed");
     out->sample_ms = pool_ms(plan->ev_sample, plan->n_sample);
+    out->sampling_span_ms = pool_ms(plan->ev_span, plan->n_span);
     out->slab_ms = pool_ms(plan->ev_slab, plan->n_slab);
     out->recon_ms = pool_ms(plan->ev_recon, plan->n_recon);
     out->sample_launches = (int32_t)plan->n_sample;
+    out->advance_launches = plan->n_advance;
     out->recon_launches = (int32_t)plan->n_recon;
     out->path_steps = c[1];
     out->lane_steps = c[2];
@@ -981,15 +1119,166 @@ hpsmc_status hpsmc_reset_stats(hpsmc_plan *plan, void *stream)
     HIP_TRY(launch_fill_u64(plan->maxbits, 4096, 0ull, s));
     plan->node_samples = 0;
     plan->n_records = 0;
-    plan->n_sample = plan->n_slab = plan->n_recon = 0;
+    plan->n_sample = plan->n_slab = plan->n_recon = plan->n_span = 0;
+    plan->n_advance = 0;
     return HPSMC_OK;
+}
+
+// ---- autotuner ------------------------------------------------------------
+// Cache file: a JSON object, one entry per line,
+//   "d2_n24_P26_deg16_fp32_M1024_gfx950": [samples_per_lane, waves, blocks_per_cu, round_steps],
+static std::string tune_key(const hpsmc_plan *plan, int iv, int64_t M)
+{
+    hipDeviceProp_t prop;
+    int dev = 0;
+    std::string arch = "gpu";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        const size_t c = arch.find(':');
+        if (c != std::string::npos) arch = arch.substr(0, c);
+    }
+    char buf[256];
+    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
+             plan->fp32 ? "fp32" : "fp64", (long long)M, plan->n_inst, arch.c_str());
+    return buf;
+}
+
+static bool cache_lookup(const char *path, const std::string &key, hpsmc_launch &l)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    const std::string pat = "\"" + key + "\"";
+    while (fgets(line, sizeof(line), f)) {
+        const char *k = strstr(line, pat.c_str());
+        if (!k) continue;
+        int a, b, c, d;
+        if (sscanf(k + pat.size(), " : [%d , %d , %d , %d]", &a, &b, &c, &d) == 4) {
+            l.samples_per_lane = a; l.waves_per_block = b; l.blocks_per_cu = c; l.round_steps = d;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const char *path, const std::string &key, const hpsmc_launch &l)
+{
+    std::vector<std::string> lines;
+    if (FILE *f = fopen(path, "r")) {
+        char line[512];
+        while (fgets(line, sizeof(line), f)) {
+            std::string s(line);
+            while (!s.empty() && (s.back() == '\n' || s.back() == '\r' || s.back() == ',' || s.back() == ' ')) s.pop_back();
+            if (s.empty() || s == "{" || s == "}" || s.find("\"" + key + "\"") != std::string::npos) continue;
+            lines.push_back(s);
+        }
+        fclose(f);
+    }
+    char buf[512];
+    snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d]", key.c_str(), l.samples_per_lane, l.waves_per_block,
+             l.blocks_per_cu, l.round_steps);
+    lines.push_back(buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    for (size_t i = 0; i < lines.size(); ++i) fprintf(f, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+    rename(tmp.c_str(), path);
 }
 
 hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char *cache_path, void *stream)
 {
     CHECK_PLAN(plan);
-    (void)iv; (void)m_tune; (void)cache_path; (void)stream;
-    return fail(HPSMC_ENOTSUP, "autotuner not built yet");
+    if (iv < 0 || iv >= plan->n_iv) return fail(HPSMC_EINVAL, "interval out of range");
+    if (m_tune < 0) return fail(HPSMC_EINVAL, "m_tune must be >= 0");
+    if (plan->pb.schedule != HPSMC_SEQUENTIAL && iv != 0) return fail(HPSMC_EINVAL, "sweep plans tune interval 0");
+    const int64_t M_full = plan->pb.M;
+    const int64_t mt = m_tune == 0 ? std::min<int64_t>(M_full, 256) : std::min<int64_t>(M_full, m_tune);
+    const std::string key = tune_key(plan, iv, M_full);
+    hpsmc_launch best = plan->launch;
+    if (cache_path && cache_lookup(cache_path, key, best)) return hpsmc_set_launch(plan, &best);
+
+    hipStream_t s = (hipStream_t)stream;
+    NodeSet &set = plan->pb.schedule == HPSMC_SEQUENTIAL ? plan->sets[iv] : plan->sets[0];
+    // keep the iterate and the counters: every trial restores them
+    int64_t usz = 0;
+    for (int k = 0; k < plan->n_iv; ++k) usz += (int64_t)plan->n_inst * plan->nsp * (plan->degree[k] + 1);
+    double *Usave = nullptr;
+    if (hipMalloc(&Usave, usz * 8) != hipSuccess) { (void)hipGetLastError(); return fail(HPSMC_ENOMEM, "tune buffer"); }
+    HIP_TRY(hipMemcpyAsync(Usave, plan->U, usz * 8, hipMemcpyDeviceToDevice, s));
+    const int64_t ns_save = plan->node_samples;
+    const int32_t rec_save = plan->n_records;
+
+    std::vector<hpsmc_launch> cands;
+    const int nsv[3] = {1, 2, 4};
+    for (int a = 0; a < 3; ++a) {
+        if (nsv[a] == 4 && plan->d > 2) continue;
+        for (int w : {2, 4}) {
+            // the LDS-staged slab must fit 4 vectors per thread
+            if (set.rounds && set.slab.slab_stride * (plan->fp32 ? 4 : 8) / 16 > 4LL * 64 * w) continue;
+            for (int b : {2, 4, 8}) cands.push_back(hpsmc_launch{nsv[a], w, b, plan->round_steps});
+        }
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipFree(Usave);
+        return fail(HPSMC_EDEVICE, "tune events");
+    }
+    plan->pb.M = mt;
+    auto trial = [&](const hpsmc_launch &l, float &ms) -> hpsmc_status {
+        hpsmc_launch keep = plan->launch;
+        plan->launch = l;
+        plan->round_steps = l.round_steps;
+        hpsmc_status st = HPSMC_OK;
+        for (int rep = 0; rep < 2 && st == HPSMC_OK; ++rep) {   // first run loads the code object
+            if (hipEventRecord(e0, s) != hipSuccess) return fail(HPSMC_EDEVICE, "event");
+            st = plan->pb.schedule == HPSMC_SEQUENTIAL ? iterate_impl(plan, iv, 0, 4095, s) : sweep_impl(plan, 0, 4095, s);
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return fail(HPSMC_EDEVICE, "event");
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return fail(HPSMC_EDEVICE, "event");
+            if (hipMemcpyAsync(plan->U, Usave, usz * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return fail(HPSMC_EDEVICE, "restore");
+        }
+        plan->launch = keep;
+        plan->round_steps = keep.round_steps;
+        return st;
+    };
+    hpsmc_status st = HPSMC_OK;
+    float best_ms = 1e30f;
+    for (const auto &c : cands) {
+        float ms;
+        if ((st = trial(c, ms))) break;
+        if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    if (!st) {
+        const int rs_d1[3] = {128, 256, 512}, rs[3] = {128, 256, 512};
+        const hpsmc_launch base = best;
+        for (int k = 0; k < 3; ++k) {
+            hpsmc_launch c = base;
+            c.round_steps = plan->d == 1 ? rs_d1[k] : rs[k];
+            if (c.round_steps == base.round_steps) continue;
+            float ms;
+            if ((st = trial(c, ms))) break;
+            if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+    }
+    plan->pb.M = M_full;
+    (void)launch_fill_u64(plan->maxbits + 4095, 1, 0ull, s);
+    plan->node_samples = ns_save;
+    plan->n_records = rec_save;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(Usave);
+    (void)set;
+    if (st) return st;
+    st = hpsmc_set_launch(plan, &best);
+    if (!st && cache_path) cache_store(cache_path, key, best);
+    return st;
 }
 
 hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *loss, double *grad,

@@ -27,6 +27,18 @@ struct NodeDesc {
     int32_t out;          // row of this node in the per-launch output arrays
 };
 
+// One (instance, interval, l) group: its nodes share the slab sequence, N*,
+// Delta and J, so a block can advance any mix of their paths in lockstep.
+struct GroupDesc {
+    double delta, jump, span, t_prev;
+    int64_t slab;          // offset of the q = 0 slab in the slab table
+    int64_t path_off;      // first path slot of the group in the state buffers
+    int32_t nstar;
+    int32_t node_begin;    // the group's nodes are [node_begin, node_begin + node_count)
+    int32_t node_count;
+    uint32_t c3;           // Philox counter word 3 without the tag
+};
+
 // Problem constants every sampling lane needs.
 struct Physics {
     int32_t dim, f_kind, src_kind, pad;
@@ -51,6 +63,31 @@ struct SampleArgs {
     int64_t m_probe;
     unsigned long long *work;    // work-item counter (zeroed before launch)
     unsigned long long *stats;   // [0] residual evaluations, [1] lane steps
+    Physics phys;
+};
+
+// Arguments of one round of the path-advancing kernel: every live path of
+// every group advances by up to `steps` walk steps, the survivors are
+// compacted into the other state buffer.
+struct RoundArgs {
+    const GroupDesc *groups;
+    const NodeDesc *nodes;
+    int32_t n_groups;
+    int32_t round, steps;        // steps [round*steps, (round+1)*steps)
+    int32_t batch;               // paths per block work item (64 * waves * NS)
+    int64_t m0, mcount;          // sample slice [m0, m0 + mcount)
+    const void *state_in;
+    void *state_out;
+    const uint32_t *live_in;     // per group, paths in state_in (round > 0)
+    uint32_t *live_out;          // per group, survivors appended to state_out
+    const int64_t *batch_prefix; // [n_groups + 1] work items per group, prefix
+    double *result;              // [node out][mcount] path value S of each sample
+    int32_t P, PP, tag;
+    uint32_t key0, key1;
+    const void *slab_table;
+    int64_t slab_stride;
+    unsigned long long *work;    // block work counter (zeroed by the prep kernel)
+    unsigned long long *stats;   // [0] residual evaluations, [1] slot steps
     Physics phys;
 };
 
@@ -86,6 +123,14 @@ hipError_t launch_start_columns(double *U, const double *src, int64_t src_stride
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 hipError_t launch_eval(const double *cu, const double *cv, int dim, int P, int T1, double t_prev, double h,
                        const double *pts, int64_t npts, double *out, hipStream_t s);
+hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t round, int32_t steps,
+                             int64_t mcount, int32_t batch, const uint32_t *live_in, uint32_t *live_out,
+                             int64_t *batch_prefix, unsigned long long *work, hipStream_t s);
+hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
+                          size_t lds_bytes, hipStream_t s);
+hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mcount, double *sums, int first,
+                               hipStream_t s);
+size_t path_state_bytes(int fp32, int dim);
 hipError_t set_recurrence_tables();
 
 }  // namespace hpsmc

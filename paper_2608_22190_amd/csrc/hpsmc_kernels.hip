@@ -205,13 +205,13 @@ __device__ __forceinline__ T source_of(const Physics &ph, const T (&X)[D], T t)
 // run as loops whose L values advance by the recurrence on the fly.  Slab rows
 // are wave-uniform: [u: PP][v: PP] per multi-index of the first d-1 dims.
 // ---------------------------------------------------------------------------
-template <typename T, int D, int PMAX, int NS, int LV>
-__device__ __forceinline__ void contract(cptr<T> S, int P, int PP, const T (&X)[NS][D], const T (&W)[NS],
+template <typename T, int D, int PMAX, int NS, int LV, typename SP>
+__device__ __forceinline__ void contract(SP S, int P, int PP, const T (&X)[NS][D], const T (&W)[NS],
                                          const T (&Ll)[NS][PMAX], T (&u)[NS], T (&v)[NS], int row)
 {
     if constexpr (LV == D - 1) {
         // rows are padded with zeros to a multiple of 4 modes and read 4 at a time
-        cptr<T> srow = S + (int64_t)row * (2 * PP);
+        SP srow = S + (int64_t)row * (2 * PP);
         T tu[NS], tv[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) { tu[s] = (T)0; tv[s] = (T)0; }
@@ -244,7 +244,7 @@ __device__ __forceinline__ void contract(cptr<T> S, int P, int PP, const T (&X)[
             T W2[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) W2[s] = W[s] * Lc[s];
-            contract<T, D, PMAX, NS, LV + 1>(S, P, PP, X, W2, Ll, u, v, row * P + k);
+            contract<T, D, PMAX, NS, LV + 1, SP>(S, P, PP, X, W2, Ll, u, v, row * P + k);
             const T ak = rec_a<T>(k), bk = rec_b<T>(k);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -379,7 +379,6 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if (alive[s]) {
-                    ++lsteps;
                     bool inside = true;
 #pragma unroll
                     for (int i = 0; i < D; ++i) {
@@ -390,6 +389,7 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
                 }
                 any_live = any_live || alive[s];
             }
+            lsteps += NS;
             if (__ballot(any_live) == 0ull) break;
 
             // ---- residual at the current centre X_q and time tau_q = t_{n,l} - q Delta
@@ -407,7 +407,7 @@ __global__ void __launch_bounds__(256) sample_kernel(SampleArgs a)
             T u[NS], v[NS], W[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) { u[s] = (T)0; v[s] = (T)0; W[s] = (T)1; }
-            contract<T, D, PMAX, NS, 0>(S, a.P, a.PP, X, W, Ll, u, v, 0);
+            contract<T, D, PMAX, NS, 0, cptr<T>>(S, a.P, a.PP, X, W, Ll, u, v, 0);
 
             const T tau = (T)(t_prev + (span - (double)q * ddelta));
 #pragma unroll
@@ -717,6 +717,388 @@ hipError_t launch_eval(const double *cu, const double *cv, int dim, int P, int T
     if (npts <= 0) return hipSuccess;
     hipLaunchKernelGGL(eval_kernel, dim3((unsigned)((npts + 63) / 64)), dim3(64), 0, s, cu, cv, dim, P, T1, t_prev,
                        h, pts, npts, out);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Round-based path advancing.  A block takes a batch of live paths of one
+// (instance, interval, l) group; every path of the batch shares the group's
+// slab sequence, so the block stages the slab of each step in LDS (double
+// buffered, one barrier per step) and all lanes read it with uniform
+// (broadcast) addresses.  After `steps` steps the surviving paths are
+// appended, compacted, to the group's region of the other state buffer, so
+// every round starts with full batches whatever the spread of exit times.
+// ===========================================================================
+template <typename T, int D> struct PathState {
+    T x[D];
+    T acc, comp;
+    uint32_t node;     // node row in the set's node array
+    uint32_t sample;
+};
+
+size_t path_state_bytes(int fp32, int dim)
+{
+    switch (dim) {
+    case 1: return fp32 ? sizeof(PathState<float, 1>) : sizeof(PathState<double, 1>);
+    case 2: return fp32 ? sizeof(PathState<float, 2>) : sizeof(PathState<double, 2>);
+    case 3: return fp32 ? sizeof(PathState<float, 3>) : sizeof(PathState<double, 3>);
+    case 4: return fp32 ? sizeof(PathState<float, 4>) : sizeof(PathState<double, 4>);
+    default: return fp32 ? sizeof(PathState<float, 5>) : sizeof(PathState<double, 5>);
+    }
+}
+
+__global__ void round_prep_kernel(const GroupDesc *__restrict__ groups, int32_t n_groups, int32_t round,
+                                  int32_t steps, int64_t mcount, int32_t batch, const uint32_t *__restrict__ live_in,
+                                  uint32_t *__restrict__ live_out, int64_t *__restrict__ batch_prefix,
+                                  unsigned long long *work)
+{
+    // one block: clear the output counters, then a serial prefix over groups
+    for (int g = threadIdx.x; g < n_groups; g += blockDim.x) live_out[g] = 0u;
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        const int64_t q0 = (int64_t)round * steps;
+        for (int g = 0; g < n_groups; ++g) {
+            batch_prefix[g] = acc;
+            int64_t live = round == 0 ? (int64_t)groups[g].node_count * mcount : (int64_t)live_in[g];
+            if (q0 >= groups[g].nstar) live = 0;
+            acc += (live + batch - 1) / batch;
+        }
+        batch_prefix[n_groups] = acc;
+        *work = 0ull;
+    }
+}
+
+hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t round, int32_t steps, int64_t mcount,
+                             int32_t batch, const uint32_t *live_in, uint32_t *live_out, int64_t *batch_prefix,
+                             unsigned long long *work, hipStream_t s)
+{
+    hipLaunchKernelGGL(round_prep_kernel, dim3(1), dim3(256), 0, s, groups, n_groups, round, steps, mcount, batch,
+                       live_in, live_out, batch_prefix, work);
+    return hipGetLastError();
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMaxStageVec = 4;   // 16-byte slab vectors staged per thread and step
+
+template <typename T, int D, int PMAX, int NS>
+__global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
+{
+    extern __shared__ u32x4 lds[];
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
+    const int64_t nvec = a.slab_stride * (int64_t)sizeof(T) / 16;   // 16-byte vectors per slab
+    __shared__ long long s_item;
+    cptr<GroupDesc> groups = as_const(a.groups);
+    cptr<NodeDesc> nodes = as_const(a.nodes);
+    const int64_t total = a.batch_prefix[a.n_groups];
+    unsigned long long evals = 0, slots = 0;
+    using State = PathState<T, D>;
+    const State *sin = (const State *)a.state_in;
+    State *sout = (State *)a.state_out;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (long long)atomicAdd(a.work, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;
+        // group of this work item: last g with batch_prefix[g] <= item
+        int lo = 0, hi = a.n_groups - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.batch_prefix[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const int g = lo;
+        const int64_t b = item - a.batch_prefix[g];
+        cptr<GroupDesc> G = groups + g;
+        const int nstar = G->nstar;
+        const int q0 = a.round * a.steps;
+        const int q1 = min(q0 + a.steps, nstar);
+        const T delta = (T)G->delta, J = (T)G->jump;
+        const double span = G->span, t_prev = G->t_prev, ddelta = G->delta;
+        const uint32_t c3 = G->c3 | (uint32_t)a.tag;
+        const int64_t live = a.round == 0 ? (int64_t)G->node_count * a.mcount : (int64_t)a.live_in[g];
+        const T *gtab = (const T *)a.slab_table + G->slab;
+
+        // ---- the batch's paths
+        T X[NS][D], Y[NS][D], acc[NS], comp[NS];
+        bool alive[NS];
+        uint32_t node[NS], sample[NS], c0[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int64_t p = b * a.batch + (int64_t)s * nthr + tid;
+            alive[s] = p < live;
+            node[s] = 0; sample[s] = 0; c0[s] = 0;
+            acc[s] = (T)0; comp[s] = (T)0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) X[s][i] = (T)0;
+            if (alive[s]) {
+                if (a.round == 0) {
+                    node[s] = (uint32_t)(G->node_begin + p / a.mcount);
+                    sample[s] = (uint32_t)(a.m0 + p % a.mcount);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) X[s][i] = (T)nodes[node[s]].x0[i];
+                } else {
+                    const State st = sin[G->path_off + p];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) X[s][i] = st.x[i];
+                    acc[s] = st.acc;
+                    comp[s] = st.comp;
+                    node[s] = st.node;
+                    sample[s] = st.sample;
+                }
+                c0[s] = nodes[node[s]].c0;
+            }
+        }
+
+        // ---- slab of the first step into LDS buffer 0
+        u32x4 stage[kMaxStageVec];
+        {
+            const u32x4 *src = (const u32x4 *)(gtab + (int64_t)q0 * a.slab_stride);
+#pragma unroll
+            for (int k = 0; k < kMaxStageVec; ++k) {
+                const int64_t v = tid + (int64_t)k * nthr;
+                if (v < nvec) lds[v] = src[v];
+            }
+        }
+        __syncthreads();
+
+        uint32_t w[NS][4];
+        int q = q0;
+        for (; q < q1; ++q) {
+            const int buf = (q - q0) & 1;
+            // prefetch the next step's slab into registers
+            if (q + 1 < q1) {
+                const u32x4 *src = (const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride);
+#pragma unroll
+                for (int k = 0; k < kMaxStageVec; ++k) {
+                    const int64_t v = tid + (int64_t)k * nthr;
+                    if (v < nvec) stage[k] = src[v];
+                }
+            }
+            // ---- directions (Philox words refreshed on block boundaries of the counter)
+            T dir[NS][D];
+            if constexpr (D == 1) {
+                if ((q & 127) == 0 || q == q0) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) philox(c0[s], sample[s], (uint32_t)(q >> 7), c3, a.key0, a.key1, w[s]);
+                }
+                const int wi = (q >> 5) & 3, bb = q & 31;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const uint32_t word = wi == 0 ? w[s][0] : wi == 1 ? w[s][1] : wi == 2 ? w[s][2] : w[s][3];
+                    dir[s][0] = ((word >> bb) & 1u) ? (T)1 : (T)-1;
+                }
+            } else if constexpr (D == 2) {
+                if ((q & 3) == 0 || q == q0) {
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) philox(c0[s], sample[s], (uint32_t)(q >> 2), c3, a.key0, a.key1, w[s]);
+                }
+                const int wi = q & 3;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const uint32_t word = wi == 0 ? w[s][0] : wi == 1 ? w[s][1] : wi == 2 ? w[s][2] : w[s][3];
+                    angle_dir(u01(word, (T)0), dir[s][0], dir[s][1]);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    uint32_t ww[8];
+                    if constexpr (D <= 4) {
+                        uint32_t o[4];
+                        philox(c0[s], sample[s], (uint32_t)q, c3, a.key0, a.key1, o);
+                        ww[0] = o[0]; ww[1] = o[1]; ww[2] = o[2]; ww[3] = o[3];
+                    } else {
+                        uint32_t o[4], o2[4];
+                        philox(c0[s], sample[s], (uint32_t)(2 * q), c3, a.key0, a.key1, o);
+                        philox(c0[s], sample[s], (uint32_t)(2 * q + 1), c3, a.key0, a.key1, o2);
+                        ww[0] = o[0]; ww[1] = o[1]; ww[2] = o[2]; ww[3] = o[3];
+                        ww[4] = o2[0]; ww[5] = o2[1]; ww[6] = o2[2]; ww[7] = o2[3];
+                    }
+                    T gg[D + 1];
+#pragma unroll
+                    for (int k = 0; k < (D + 1) / 2; ++k) {
+                        const T r = m_sqrt((T)-2 * m_log(u01(ww[2 * k], (T)0)));
+                        T c, sn;
+                        angle_dir(u01(ww[2 * k + 1], (T)0), c, sn);
+                        gg[2 * k] = r * c;
+                        gg[2 * k + 1] = r * sn;
+                    }
+                    T nrm = 0;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) nrm += gg[i] * gg[i];
+                    nrm = m_sqrt(nrm);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) dir[s][i] = gg[i] / nrm;
+                }
+            }
+            // ---- jump and exit test (eq. indexL)
+            bool any_live = false;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (alive[s]) {
+                    bool inside = true;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        Y[s][i] = m_fma(J, dir[s][i], X[s][i]);
+                        inside = inside && (fabs(Y[s][i]) < (T)1);
+                    }
+                    if (!inside) {   // path ended: L = q
+                        alive[s] = false;
+                        a.result[(int64_t)nodes[node[s]].out * a.mcount + (sample[s] - a.m0)] =
+                            (double)acc[s] - (double)comp[s];
+                    }
+                }
+                any_live = any_live || alive[s];
+            }
+            slots += NS;
+            // ---- residual at X_q, time tau_q = t_{n,l} - q Delta, from the LDS slab
+            if (__ballot(any_live) != 0ull) {
+                const T *S = (const T *)(lds + (int64_t)buf * ((nvec + 1) & ~(int64_t)1));
+                T Ll[NS][PMAX];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const T x = X[s][D - 1];
+                    Ll[s][0] = (T)1;
+                    if (PMAX > 1) Ll[s][1] = x;
+#pragma unroll
+                    for (int k = 1; k + 1 < PMAX; ++k)
+                        Ll[s][k + 1] = (T)((2.0 * k + 1.0) / (k + 1.0)) * x * Ll[s][k] - (T)(k / (k + 1.0)) * Ll[s][k - 1];
+                }
+                T u[NS], v[NS], W[NS];
+#pragma unroll
+                for (int s = 0; s < NS; ++s) { u[s] = (T)0; v[s] = (T)0; W[s] = (T)1; }
+                contract<T, D, PMAX, NS, 0, const T *>(S, a.P, a.PP, X, W, Ll, u, v, 0);
+                const T tau = (T)(t_prev + (span - (double)q * ddelta));
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (alive[s]) {
+                        const T r = f_of<T>(a.phys, u[s]) + source_of<T, D>(a.phys, X[s], tau) + v[s];
+                        const T y = delta * r;
+                        if constexpr (sizeof(T) == 4) {
+                            const T yc = y - comp[s];
+                            const T tt = acc[s] + yc;
+                            comp[s] = (tt - acc[s]) - yc;
+                            acc[s] = tt;
+                        } else {
+                            acc[s] += y;
+                        }
+#pragma unroll
+                        for (int i = 0; i < D; ++i) X[s][i] = Y[s][i];
+                        ++evals;
+                    }
+                }
+            }
+            // ---- next slab into the other buffer; one barrier per step
+            if (q + 1 < q1) {
+                u32x4 *dst = lds + (int64_t)(buf ^ 1) * ((nvec + 1) & ~(int64_t)1);
+#pragma unroll
+                for (int k = 0; k < kMaxStageVec; ++k) {
+                    const int64_t v = tid + (int64_t)k * nthr;
+                    if (v < nvec) dst[v] = stage[k];
+                }
+            }
+            if (__syncthreads_or(any_live ? 1 : 0) == 0) { ++q; break; }
+        }
+
+        // ---- paths alive after the round: finished at N*, or carried to the next round
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const bool carry = alive[s] && q1 < nstar;
+            if (alive[s] && !carry)
+                a.result[(int64_t)nodes[node[s]].out * a.mcount + (sample[s] - a.m0)] = (double)acc[s] - (double)comp[s];
+            const unsigned long long mask = __ballot(carry);
+            if (mask != 0ull) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(a.live_out + g, (uint32_t)__popcll(mask));
+                base = __shfl(base, 0, 64);
+                if (carry) {
+                    const uint32_t off = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                    State st;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) st.x[i] = X[s][i];
+                    st.acc = acc[s];
+                    st.comp = comp[s];
+                    st.node = node[s];
+                    st.sample = sample[s];
+                    sout[G->path_off + off] = st;
+                }
+            }
+        }
+    }
+    evals = wave_sum_u64(evals);
+    slots = wave_sum_u64(slots);
+    if (lane == 0) {
+        atomicAdd(a.stats + 0, evals);
+        atomicAdd(a.stats + 1, slots);
+    }
+}
+
+template <typename T, int D, int PMAX>
+static hipError_t adv_ns(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    switch (ns) {
+    case 1: hipLaunchKernelGGL((advance_kernel<T, D, PMAX, 1>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((advance_kernel<T, D, PMAX, 2>), grid, block, lds, s, a); break;
+    case 4:
+        if constexpr (D <= 2) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, 4>), grid, block, lds, s, a); break; }
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t adv_p(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    if (a.P <= 12) return adv_ns<T, D, 12>(a, ns, grid, block, lds, s);
+    if constexpr (D <= 4) {
+        if (a.P <= 20) return adv_ns<T, D, 20>(a, ns, grid, block, lds, s);
+    }
+    if constexpr (D <= 3) {
+        if (a.P <= 28) return adv_ns<T, D, 28>(a, ns, grid, block, lds, s);
+        if (a.P <= 36) return adv_ns<T, D, 36>(a, ns, grid, block, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t adv_d(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    switch (a.phys.dim) {
+    case 1: return adv_p<T, 1>(a, ns, grid, block, lds, s);
+    case 2: return adv_p<T, 2>(a, ns, grid, block, lds, s);
+    case 3: return adv_p<T, 3>(a, ns, grid, block, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
+                          size_t lds_bytes, hipStream_t s)
+{
+    dim3 block(64 * waves_per_block), grid(blocks);
+    return fp32 ? adv_d<float>(a, samples_per_lane, grid, block, lds_bytes, s)
+                : adv_d<double>(a, samples_per_lane, grid, block, lds_bytes, s);
+}
+
+// sums[out][0..1] (+)= sum over the slice's samples of S and S^2, in sample order
+__global__ void slice_reduce_kernel(const double *__restrict__ result, int64_t n_nodes, int64_t mcount,
+                                    double *__restrict__ sums, int first)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    const double *r = result + i * mcount;
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t k = 0; k < mcount; ++k) { s1 += r[k]; s2 += r[k] * r[k]; }
+    if (first) { sums[2 * i] = s1; sums[2 * i + 1] = s2; }
+    else { sums[2 * i] += s1; sums[2 * i + 1] += s2; }
+}
+
+hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mcount, double *sums, int first,
+                               hipStream_t s)
+{
+    if (n_nodes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(slice_reduce_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, result, n_nodes,
+                       mcount, sums, first);
     return hipGetLastError();
 }
 

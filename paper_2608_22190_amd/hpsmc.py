@@ -48,13 +48,14 @@ class hpsmc_problem(C.Structure):
 class hpsmc_stats_t(C.Structure):
     _fields_ = [("path_steps", C.c_uint64), ("lane_steps", C.c_uint64), ("node_samples", C.c_uint64),
                 ("n_records", C.c_int32), ("status_flags", C.c_int32), ("sample_launches", C.c_int32),
-                ("recon_launches", C.c_int32), ("sample_ms", C.c_double), ("recon_ms", C.c_double),
-                ("slab_ms", C.c_double), ("max_eps", C.c_double * 4096)]
+                ("recon_launches", C.c_int32), ("sample_ms", C.c_double), ("sampling_span_ms", C.c_double),
+                ("recon_ms", C.c_double),
+                ("slab_ms", C.c_double), ("advance_launches", C.c_int64), ("max_eps", C.c_double * 4096)]
 
 
 class hpsmc_launch(C.Structure):
     _fields_ = [("samples_per_lane", C.c_int32), ("waves_per_block", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("reserved", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("round_steps", C.c_int32)]
 
 
 # name: (restype, argtypes)
@@ -241,14 +242,14 @@ class Plan:
         return out
 
     # -- launch shape and tuning
-    def hpsmc_set_launch(self, samples_per_lane, waves_per_block, blocks_per_cu):
-        l = hpsmc_launch(samples_per_lane, waves_per_block, blocks_per_cu, 0)
+    def hpsmc_set_launch(self, samples_per_lane, waves_per_block, blocks_per_cu, round_steps=0):
+        l = hpsmc_launch(samples_per_lane, waves_per_block, blocks_per_cu, round_steps)
         _check(lib().hpsmc_set_launch(self.h, C.byref(l)), "hpsmc_set_launch")
 
     def hpsmc_get_launch(self):
         l = hpsmc_launch()
         _check(lib().hpsmc_get_launch(self.h, C.byref(l)), "hpsmc_get_launch")
-        return (l.samples_per_lane, l.waves_per_block, l.blocks_per_cu)
+        return (l.samples_per_lane, l.waves_per_block, l.blocks_per_cu, l.round_steps)
 
     def hpsmc_tune(self, iv=0, m_tune=0, cache_path=None, stream=None):
         cp = cache_path.encode() if cache_path else None
@@ -262,7 +263,9 @@ class Plan:
         return {"path_steps": s.path_steps, "lane_steps": s.lane_steps, "node_samples": s.node_samples,
                 "max_eps": np.array(s.max_eps[:s.n_records]), "status_flags": s.status_flags,
                 "sample_launches": s.sample_launches, "recon_launches": s.recon_launches,
-                "sample_ms": s.sample_ms, "recon_ms": s.recon_ms, "slab_ms": s.slab_ms}
+                "sample_ms": s.sample_ms, "sampling_span_ms": s.sampling_span_ms, "recon_ms": s.recon_ms,
+                "slab_ms": s.slab_ms,
+                "advance_launches": s.advance_launches}
 
     def hpsmc_reset_stats(self, stream=None):
         _check(lib().hpsmc_reset_stats(self.h, _stream(stream)), "hpsmc_reset_stats")
