@@ -195,6 +195,19 @@ hpsmc_status hpsmc_reset_stats(hpsmc_plan *plan, void *stream);
 hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *loss, double *grad,
                                 int32_t on_device, void *stream);
 
+/* Replace the phi-coefficients of IC_PHI initial data, [instance][n^d] (host or
+ * device per on_device); the next start of interval 0 uses them.  EINVAL
+ * when the plan's initial data are not phi-coefficients. */
+hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_t on_device, void *stream);
+
+/* Named integer options:
+ *   "adjoint_mfma"      1 (default): FP32 adjoint outer products on the matrix
+ *                       cores; 0: on the vector units.
+ *   "round_budget_mb"   device memory for path states and per-sample results
+ *                       (takes effect at the next hpsmc_create; read-only here).
+ * EINVAL for an unknown name or value. */
+hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value);
+
 const char *hpsmc_last_error(void);
 
 #ifdef __cplusplus

@@ -256,6 +256,13 @@ struct hpsmc_plan {
     double *ic = nullptr;                // [inst][nsp]
     double *mats = nullptr;              // G0 (P x n), D2 (P x P), then per interval Bt, D1
     std::vector<int64_t> bt_off, d1_off;
+    int64_t g0t_off = 0, d2t_off = 0, phi_off = 0, phit_off = 0;   // transposes and the phi collocation
+    std::vector<int64_t> btt_off, d1t_off;
+    // adjoint buffers (allocated on the first gradient call)
+    double *hist_u = nullptr, *hist_v = nullptr, *lam = nullptr, *cbar_u = nullptr, *cbar_v = nullptr;
+    double *dtarget = nullptr, *dloss = nullptr, *dgrad = nullptr;
+    void *slab_bar = nullptr;
+    int32_t adj_use_mfma = 1;
     void *slab_table = nullptr;
     size_t slab_bytes = 0;
     double *part = nullptr;
@@ -736,7 +743,8 @@ void hpsmc_destroy(hpsmc_plan *plan)
     for (auto *pool : {&plan->ev_sample, &plan->ev_slab, &plan->ev_recon, &plan->ev_span})
         for (auto &e : *pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     void *ptrs[] = {plan->U, plan->cu, plan->cv, plan->tmp0, plan->tmp1, plan->ic, plan->mats,
-                    plan->slab_table, plan->part, plan->counters, plan->maxbits};
+                    plan->slab_table, plan->part, plan->counters, plan->maxbits, plan->hist_u, plan->hist_v,
+                    plan->lam, plan->cbar_u, plan->cbar_v, plan->dtarget, plan->dloss, plan->dgrad, plan->slab_bar};
     for (void *p : ptrs) (void)hipFree(p);
     delete plan;
 }
@@ -818,13 +826,43 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
     auto D2 = legendre_d2(plan->P);
     mats.insert(mats.end(), G0.begin(), G0.end());
     mats.insert(mats.end(), D2.begin(), D2.end());
+    auto transpose = [](const std::vector<double> &A, int rows, int cols) {
+        std::vector<double> T((size_t)rows * cols);
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) T[(size_t)c * rows + r] = A[(size_t)r * cols + c];
+        return T;
+    };
     for (int iv = 0; iv < plan->n_iv; ++iv) {
+        const int T1 = plan->degree[iv] + 1;
         auto Bt = temporal_to_legendre(plan->xi[iv]);
-        auto D1 = legendre_d1(plan->degree[iv] + 1);
+        auto D1 = legendre_d1(T1);
         plan->bt_off.push_back((int64_t)mats.size());
         mats.insert(mats.end(), Bt.begin(), Bt.end());
         plan->d1_off.push_back((int64_t)mats.size());
         mats.insert(mats.end(), D1.begin(), D1.end());
+        auto BtT = transpose(Bt, T1, T1), D1T = transpose(D1, T1, T1);
+        plan->btt_off.push_back((int64_t)mats.size());
+        mats.insert(mats.end(), BtT.begin(), BtT.end());
+        plan->d1t_off.push_back((int64_t)mats.size());
+        mats.insert(mats.end(), D1T.begin(), D1T.end());
+    }
+    {
+        auto G0T = transpose(G0, plan->P, plan->n), D2T = transpose(D2, plan->P, plan->P);
+        plan->g0t_off = (int64_t)mats.size();
+        mats.insert(mats.end(), G0T.begin(), G0T.end());
+        plan->d2t_off = (int64_t)mats.size();
+        mats.insert(mats.end(), D2T.begin(), D2T.end());
+        // phi collocation Phi[j][p] = phi_p(x_j) and its transpose
+        std::vector<double> Phi((size_t)plan->n * plan->n), L(plan->n + 3);
+        for (int j = 0; j < plan->n; ++j) {
+            legendre_values(plan->n + 2, plan->x[j], L.data());
+            for (int pp = 0; pp < plan->n; ++pp) Phi[(size_t)j * plan->n + pp] = phi_legendre(pp, L.data());
+        }
+        plan->phi_off = (int64_t)mats.size();
+        mats.insert(mats.end(), Phi.begin(), Phi.end());
+        auto PhiT = transpose(Phi, plan->n, plan->n);
+        plan->phit_off = (int64_t)mats.size();
+        mats.insert(mats.end(), PhiT.begin(), PhiT.end());
     }
     if ((st = dalloc(pl, (void **)&pl->mats, mats.size() * 8))) return st;
     std::vector<double> u0;
@@ -1281,12 +1319,179 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     return st;
 }
 
+// u0 = Phi c (per instance), Phi[j][p] = prod_i phi_{p_i}(x_{j_i})
+static hpsmc_status phi_apply(hpsmc_plan *plan, const double *in, double *out, int64_t mat_off, hipStream_t s)
+{
+    const int d = plan->d, n = plan->n;
+    const int64_t I = plan->n_inst;
+    const double *src = in;
+    double *bufs[2] = {plan->tmp0, plan->tmp1};
+    for (int i = 0; i < d; ++i) {
+        double *o = (i == d - 1) ? out : bufs[i & 1];
+        HIP_TRY(launch_mode_product(src, o, I * ipow(n, i), n, n, ipow(n, d - 1 - i), plan->mats + mat_off, 1.0, 0, s));
+        src = o;
+    }
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_t on_device, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (!c0) return fail(HPSMC_EINVAL, "c0 is NULL");
+    if (plan->pb.ic_kind != HPSMC_IC_PHI) return fail(HPSMC_EINVAL, "plan's initial data are not phi-coefficients");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)plan->n_inst * plan->nsp * 8;
+    // stage the coefficients in the gradient's target buffer slot (free until a gradient call)
+    double *stage = nullptr;
+    if (hipMalloc(&stage, bytes) != hipSuccess) { (void)hipGetLastError(); return fail(HPSMC_ENOMEM, "staging"); }
+    hipError_t e = hipMemcpyAsync(stage, c0, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) { (void)hipFree(stage); plan->poisoned = true; return fail(HPSMC_EDEVICE, "coefficient copy"); }
+    hpsmc_status st = phi_apply(plan, stage, plan->ic, plan->phi_off, s);
+    if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail(HPSMC_EDEVICE, "synchronize");
+    (void)hipFree(stage);
+    if (st) return st;
+    if (!on_device) plan->ic_data.assign(c0, c0 + (size_t)plan->n_inst * plan->nsp);
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value)
+{
+    CHECK_PLAN(plan);
+    if (!name) return fail(HPSMC_EINVAL, "option name is NULL");
+    if (strcmp(name, "adjoint_mfma") == 0) {
+        if (value != 0 && value != 1) return fail(HPSMC_EINVAL, "adjoint_mfma must be 0 or 1");
+        plan->adj_use_mfma = (int32_t)value;
+        return HPSMC_OK;
+    }
+    return fail(HPSMC_EINVAL, std::string("unknown option ") + name);
+}
+
+static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hipStream_t s)
+{
+    const int G = (int)set.ghost.size();
+    const int nthr = 64;
+    const size_t lds = adjoint_lds_bytes(plan->fp32, plan->d, plan->P, nthr, set.slab.slab_stride);
+    const int64_t nvec = set.slab.slab_stride * (plan->fp32 ? 4 : 8) / 16;
+    if (nvec > 4LL * nthr || lds > 65536) return fail(HPSMC_ENOTSUP, "slab too large for the adjoint kernel");
+    const int C = plan->round_steps;
+    const int R = (set.max_nstar + C - 1) / C;
+    AdjointArgs aa{};
+    RoundArgs &a = aa.r;
+    a.groups = set.gdev;
+    a.nodes = set.dev;
+    a.n_groups = G;
+    a.steps = C;
+    a.batch = nthr;
+    a.batch_prefix = set.prefix;
+    a.P = plan->P;
+    a.PP = plan->PP;
+    a.tag = tag;
+    a.key0 = (uint32_t)plan->pb.seed;
+    a.key1 = (uint32_t)(plan->pb.seed >> 32);
+    a.slab_table = plan->slab_table;
+    a.slab_stride = set.slab.slab_stride;
+    a.work = plan->counters;
+    a.stats = plan->counters + 1;
+    a.phys = physics_of(plan);
+    aa.lambda = plan->lam;
+    aa.slab_bar = plan->slab_bar;
+    aa.inv_M = 1.0 / (double)plan->pb.M;
+    aa.use_mfma = plan->fp32 && plan->adj_use_mfma;
+    const int blocks = std::max(1, plan->cus * 8);
+    for (int64_t m0 = 0; m0 < plan->pb.M; m0 += set.ms) {
+        const int64_t mc = std::min<int64_t>(set.ms, plan->pb.M - m0);
+        a.m0 = m0;
+        a.mcount = mc;
+        for (int r = 0; r < R; ++r) {
+            a.round = r;
+            a.state_in = set.state[r & 1];
+            a.state_out = set.state[(r + 1) & 1];
+            a.live_in = set.live + (r & 1) * G;
+            a.live_out = set.live + ((r + 1) & 1) * G;
+            HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, a.live_in, a.live_out, set.prefix, plan->counters, s));
+            HIP_TRY(launch_adjoint(aa, plan->fp32, 1, blocks, lds, s));
+        }
+    }
+    return HPSMC_OK;
+}
+
 hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *loss, double *grad,
                                 int32_t on_device, void *stream)
 {
     CHECK_PLAN(plan);
-    (void)target; (void)loss; (void)grad; (void)on_device; (void)stream;
-    return fail(HPSMC_ENOTSUP, "adjoint not built yet");
+    if (!target || !loss || !grad) return fail(HPSMC_EINVAL, "NULL argument");
+    if (plan->n_iv != 1 || plan->pb.ic_kind != HPSMC_IC_PHI || plan->pb.schedule != HPSMC_SEQUENTIAL)
+        return fail(HPSMC_EINVAL, "the gradient needs one interval, phi-coefficient initial data, sequential schedule");
+    if (plan->d > 2 || plan->P > 32 || !plan->sets[0].rounds)
+        return fail(HPSMC_ENOTSUP, "the adjoint kernel covers dim <= 2 and n <= 30");
+    hipStream_t s = (hipStream_t)stream;
+    const int d = plan->d, n = plan->n, P = plan->P, K = plan->pb.iters, T1 = plan->degree[0] + 1;
+    const int64_t I = plan->n_inst, nsp = plan->nsp, psp = plan->psp;
+    const int64_t usz = I * nsp * T1, csz = I * psp * T1;
+    NodeSet &set = plan->sets[0];
+    hpsmc_status st;
+    if (!plan->lam) {
+        if ((st = dalloc(plan, (void **)&plan->hist_u, (size_t)K * csz * 8)) ||
+            (st = dalloc(plan, (void **)&plan->hist_v, (size_t)K * csz * 8)) ||
+            (st = dalloc(plan, (void **)&plan->lam, (size_t)usz * 8)) ||
+            (st = dalloc(plan, (void **)&plan->cbar_u, (size_t)csz * 8)) ||
+            (st = dalloc(plan, (void **)&plan->cbar_v, (size_t)csz * 8)) ||
+            (st = dalloc(plan, (void **)&plan->dtarget, (size_t)I * nsp * 8)) ||
+            (st = dalloc(plan, (void **)&plan->dloss, (size_t)I * 8)) ||
+            (st = dalloc(plan, (void **)&plan->dgrad, (size_t)I * nsp * 8)) ||
+            (st = dalloc(plan, &plan->slab_bar, plan->slab_bytes)))
+            return st;
+    }
+    HIP_TRY(hipMemcpyAsync(plan->dtarget, target, (size_t)I * nsp * 8,
+                           on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+    // forward, keeping every iteration's Legendre tensors
+    if ((st = start_interval(plan, 0, 1, s))) return st;
+    for (int k = 0; k < K; ++k) {
+        if ((st = reconstruct(plan, 0, s))) return st;
+        HIP_TRY(hipMemcpyAsync(plan->hist_u + (size_t)k * csz, plan->cu, csz * 8, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(plan->hist_v + (size_t)k * csz, plan->cv, csz * 8, hipMemcpyDeviceToDevice, s));
+        if ((st = sample_set(plan, set, plan->pb.fresh_per_iter ? k : 0, plan->n_records, s))) return st;
+    }
+    // terminal misfit and its nodal adjoint
+    HIP_TRY(launch_fill_u64((unsigned long long *)plan->lam, usz, 0ull, s));
+    HIP_TRY(launch_loss_lambda(plan->U, plan->dtarget, (int)I, nsp, T1, plan->lam, plan->dloss, s));
+    const double h = plan->t_breaks[1] - plan->t_breaks[0];
+    const double *M = plan->mats;
+    for (int k = K - 1; k >= 0; --k) {
+        HIP_TRY(hipMemcpyAsync(plan->cu, plan->hist_u + (size_t)k * csz, csz * 8, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(plan->cv, plan->hist_v + (size_t)k * csz, csz * 8, hipMemcpyDeviceToDevice, s));
+        SlabArgs sa = set.slab;
+        sa.slab_table = plan->slab_table;
+        HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
+        HIP_TRY(launch_fill_u64((unsigned long long *)plan->slab_bar, (int64_t)(plan->slab_bytes / 8), 0ull, s));
+        if ((st = adjoint_sampling(plan, set, plan->pb.fresh_per_iter ? k : 0, s))) return st;
+        SlabArgs sb = set.slab;
+        sb.slab_table = plan->slab_bar;
+        HIP_TRY(launch_slab_adjoint(sb, plan->degree[0], (int)I, plan->fp32, plan->cbar_u, plan->cbar_v, psp * T1, s));
+        // cbar_u += (c^u -> c^v)^T cbar_v
+        for (int i = 0; i < d; ++i)
+            HIP_TRY(launch_mode_product(plan->cbar_v, plan->cbar_u, I * ipow(P, i), P, P, ipow(P, d - 1 - i) * T1,
+                                        M + plan->d2t_off, 1.0, 1, s));
+        HIP_TRY(launch_mode_product(plan->cbar_v, plan->cbar_u, I * psp, T1, T1, 1, M + plan->d1t_off[0], -2.0 / h, 1, s));
+        // Ubar = cbar_u x_t Bt^T x_1 G0^T ... x_d G0^T;  lambda += Ubar
+        HIP_TRY(launch_mode_product(plan->cbar_u, plan->tmp0, I * psp, T1, T1, 1, M + plan->btt_off[0], 1.0, 0, s));
+        const double *in = plan->tmp0;
+        double *bufs[2] = {plan->tmp1, plan->tmp0};
+        for (int i = 0; i < d; ++i) {
+            double *o = bufs[i & 1];
+            HIP_TRY(launch_mode_product(in, o, I * ipow(n, i), P, n, ipow(P, d - 1 - i) * T1, M + plan->g0t_off, 1.0, 0, s));
+            in = o;
+        }
+        HIP_TRY(launch_axpy(plan->lam, in, usz, s));
+    }
+    // dL/dc = Phi^T sum_l lambda[:, l]
+    HIP_TRY(launch_column_sum(plan->lam, I * nsp, T1, plan->cbar_v, s));
+    if ((st = phi_apply(plan, plan->cbar_v, plan->dgrad, plan->phit_off, s))) return st;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIP_TRY(hipMemcpyAsync(loss, plan->dloss, (size_t)I * 8, kind, s));
+    HIP_TRY(hipMemcpyAsync(grad, plan->dgrad, (size_t)I * nsp * 8, kind, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return HPSMC_OK;
 }
 
 }  // extern "C"

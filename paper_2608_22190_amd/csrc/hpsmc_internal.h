@@ -91,6 +91,17 @@ struct RoundArgs {
     Physics phys;
 };
 
+// Arguments of one round of the adjoint kernel: the forward paths of one
+// iteration are regenerated and every residual evaluation scatters its
+// weighted basis values into the slab-adjoint table.
+struct AdjointArgs {
+    RoundArgs r;                 // paths, slabs, counters (result unused)
+    const double *lambda;        // nodal adjoint, U layout
+    void *slab_bar;              // slab-adjoint table, slab layout, type T
+    double inv_M;                // 1/M
+    int32_t use_mfma;            // FP32 only: outer products on the matrix cores
+};
+
 // Time contraction of the modal coefficients into per-step spatial slabs.
 // One group = one (instance, interval, node time l).
 struct SlabArgs {
@@ -131,6 +142,15 @@ hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, in
 hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mcount, double *sums, int first,
                                hipStream_t s);
 size_t path_state_bytes(int fp32, int dim);
+hipError_t launch_adjoint(const AdjointArgs &a, int fp32, int waves_per_block, int blocks, size_t lds_bytes,
+                          hipStream_t s);
+size_t adjoint_lds_bytes(int fp32, int dim, int P, int nthr, int64_t slab_stride);
+hipError_t launch_slab_adjoint(const SlabArgs &a, int32_t groups_per_inst, int32_t n_inst, int fp32, double *cbar_u,
+                               double *cbar_v, int64_t coef_inst_stride, hipStream_t s);
+hipError_t launch_loss_lambda(const double *U, const double *target, int n_inst, int64_t nsp, int T1, double *lambda,
+                              double *loss, hipStream_t s);
+hipError_t launch_column_sum(const double *lambda, int64_t rows, int T1, double *out, hipStream_t s);
+hipError_t launch_axpy(double *y, const double *x, int64_t n, hipStream_t s);
 hipError_t set_recurrence_tables();
 
 }  // namespace hpsmc

@@ -79,6 +79,8 @@ _SIGS = {
     "hpsmc_stats": (C.c_int, [C.c_void_p, C.POINTER(hpsmc_stats_t), C.c_void_p]),
     "hpsmc_reset_stats": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hpsmc_loss_grad_c0": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_set_initial_coeffs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
     "hpsmc_last_error": (C.c_char_p, []),
 }
 EXPORTED = tuple(_SIGS)
@@ -270,7 +272,17 @@ class Plan:
     def hpsmc_reset_stats(self, stream=None):
         _check(lib().hpsmc_reset_stats(self.h, _stream(stream)), "hpsmc_reset_stats")
 
+    def hpsmc_set_option(self, name, value):
+        _check(lib().hpsmc_set_option(self.h, name.encode(), int(value)), "hpsmc_set_option")
+
     # -- gradient
+    def hpsmc_set_initial_coeffs(self, c0, stream=None):
+        on_dev = hasattr(c0, "data_ptr")
+        if not on_dev:
+            c0 = np.ascontiguousarray(c0, dtype=np.float64).reshape(self.wl.n_instances, self.nsp)
+        _check(lib().hpsmc_set_initial_coeffs(self.h, _ptr(c0), int(on_dev), _stream(stream)),
+               "hpsmc_set_initial_coeffs")
+
     def hpsmc_loss_grad_c0(self, target, stream=None):
         on_dev = hasattr(target, "data_ptr")
         I = self.wl.n_instances
@@ -284,3 +296,27 @@ class Plan:
         _check(lib().hpsmc_loss_grad_c0(self.h, _ptr(target), _ptr(loss), _ptr(grad), int(on_dev),
                                         _stream(stream)), "hpsmc_loss_grad_c0")
         return loss, grad
+
+
+def smc_loss_function():
+    """torch.autograd.Function whose forward is the terminal misfit of a
+    single-interval solve from phi-coefficients c0 ([instances, n^d], float64,
+    on the GPU) and whose backward is the library's hand-written adjoint under
+    common random numbers (the gradient is computed with the forward)."""
+    import torch
+
+    class SMCLoss(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, c0, plan, target, stream=None):
+            c0 = c0.detach().contiguous()
+            plan.hpsmc_set_initial_coeffs(c0, stream=stream)
+            loss, grad = plan.hpsmc_loss_grad_c0(target.detach().contiguous(), stream=stream)
+            ctx.save_for_backward(grad)
+            return loss
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            return gout[:, None] * grad, None, None, None
+
+    return SMCLoss
