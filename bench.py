@@ -78,6 +78,77 @@ def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256):
     return {"seconds": t1 - t0, "stats": st, "U": U, "sigma": sig, "launch": lau}
 
 
+def run_other(name, args, torch):
+    """Measured line for the other workload shapes (one step each):
+    c1 a whole solve (graph-captured), c3 one sweep over all 12 intervals,
+    c4 one iteration, c5 forward + adjoint of the batched misfit."""
+    from paper_2608_22190_amd import hpsmc, workloads as W
+    stream = torch.cuda.Stream()
+    m = args.m_slice
+    if name == "c1":
+        wl = W.c1_single_step()
+    elif name == "c3":
+        wl = W.c3_initial_singularity(M=m, sweeps=args.steps + args.warmup)
+    elif name == "c4":
+        wl = W.c4_five_dim(M=m, iters=args.steps + args.warmup)
+    else:
+        wl = W.c5_batched_gradient(M=m)
+    nodes = wl.nodes_per_sweep * wl.n_instances
+    with hpsmc.Plan(wl) as plan:
+        if args.launch:
+            plan.hpsmc_set_launch(*(int(v) for v in args.launch.split(",")))
+        def step(k):
+            if name == "c1":
+                plan.hpsmc_solve(stream=stream)
+            elif name == "c3":
+                plan.hpsmc_sweep(k, stream=stream)
+            elif name == "c4":
+                plan.hpsmc_iterate(0, k, stream=stream)
+            else:
+                plan.hpsmc_loss_grad_c0(W.c5_target(wl.n_instances, wl.nsp, seed=1), stream=stream)
+        if name == "c1":
+            plan.hpsmc_set_option("graph", 1)
+        for w in range(args.warmup):
+            step(w)
+            stream.synchronize()
+            print(f"[bench] {name} warmup {w + 1}", file=sys.stderr, flush=True)
+        plan.hpsmc_reset_stats(stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(args.warmup + k)
+            stream.synchronize()
+            print(f"[bench] {name} step {k + 1} {time.perf_counter() - t0:.2f}s", file=sys.stderr, flush=True)
+        sec = time.perf_counter() - t0
+        st = plan.hpsmc_stats(stream=stream)
+    per_step = nodes * wl.M * (wl.iters if name in ("c1", "c5") else 1)
+    P = wl.n + 2
+    fpe = flops_per_eval(wl.dim, P)
+    k_ms = st["sample_ms"] / max(1, st["sample_launches"])
+    launches = max(1, st["advance_launches"] or st["sample_launches"])
+    desc = {"c1": "c1_1d_single_step: whole solve (5 iterations, 256 nodes x M=4096), FP64, hipGraph replay",
+            "c3": f"c3_2d_initial_singularity: one sweep over all 12 geometric intervals ({nodes} nodes, "
+                  f"degrees 4..26) x samples 0..{m - 1} of M=32768, FP32",
+            "c4": f"c4_5d: one residual iteration, {nodes} nodes (8^5 x 8) x samples 0..{m - 1} of M=16384, FP32",
+            "c5": f"c5_2d_batched_gradient: forward (6 iterations) + adjoint, 256 instances x {wl.nsp * 12} nodes "
+                  f"x samples 0..{m - 1} of M=8192, FP32"}[name]
+    out = {"metric": METRIC, "value": per_step * args.steps / sec, "unit": "node-samples/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * sec / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if wl.precision == "fp64" else "f32",
+           "data": "synthetic", "config": {"workload": desc, "max_nstar": int(max(wl.nstar)), "launch": None}}
+    if name != "c5":
+        out["roofline"] = {"bound": "alu", "achieved": fpe * st["path_steps"] / launches / max(1e-9, k_ms * 1e-3) / 1e12
+                           if st["sample_launches"] else None,
+                           "peak": FP64_PEAK_TFLOPS if wl.precision == "fp64" else FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "avg_launch_ms": k_ms, "flops_per_eval": fpe,
+                           "lane_utilization": st["path_steps"] / max(1, st["lane_steps"])}
+        if out["roofline"]["achieved"] is not None:
+            out["roofline"]["frac"] = out["roofline"]["achieved"] / out["roofline"]["peak"]
+    out["path_steps_per_s"] = st["path_steps"] / sec
+    out["mean_path_length"] = st["path_steps"] / max(1, st["node_samples"])
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(wl, budget_s=20.0):
     """The FP64 oracle on a bounded sample: random nodes of the same interval,
     the first samples of each, one residual iteration from the same iterate."""
@@ -111,6 +182,9 @@ def main():
     ap.add_argument("--m-slice", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--launch", type=str, default="",
                     help="samples_per_lane,waves_per_block,blocks_per_cu,round_steps (skips the tuner)")
     ap.add_argument("--tune-cache", type=str, default=os.path.join(ROOT, "paper_2608_22190_amd", "tuned_launch.json"),
@@ -128,6 +202,16 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload != "c2":
+        run_other(args.workload, args, torch)
+        return
 
     base = W.c2_long_time(M=args.m_slice, iters=args.steps, n_intervals=1)
     P = base.n + 2

@@ -203,8 +203,10 @@ hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_
 /* Named integer options:
  *   "adjoint_mfma"      1 (default): FP32 adjoint outer products on the matrix
  *                       cores; 0: on the vector units.
- *   "round_budget_mb"   device memory for path states and per-sample results
- *                       (takes effect at the next hpsmc_create; read-only here).
+ *   "graph"             1: hpsmc_solve captures the whole solve into a hipGraph
+ *                       on its first call (on a stream of the plan) and replays
+ *                       it on this and later calls; 0 (default): eager launches.
+ *                       A new launch shape discards the captured graph.
  * EINVAL for an unknown name or value. */
 hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value);
 

@@ -19,6 +19,7 @@ namespace hpsmc {
 // Errors
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
+static thread_local bool g_capturing = false;   // no event records inside a stream capture
 
 static hpsmc_status fail(hpsmc_status st, const std::string &msg)
 {
@@ -263,6 +264,14 @@ struct hpsmc_plan {
     double *dtarget = nullptr, *dloss = nullptr, *dgrad = nullptr;
     void *slab_bar = nullptr;
     int32_t adj_use_mfma = 1;
+    // hipGraph of a whole solve (captured on the first graph solve, replayed after)
+    int32_t use_graph = 0;
+    bool capturing = false;
+    hipStream_t own_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int64_t graph_node_samples = 0;
+    int32_t graph_records = 0;
     void *slab_table = nullptr;
     size_t slab_bytes = 0;
     double *part = nullptr;
@@ -292,7 +301,7 @@ static int64_t ipow(int64_t b, int e)
 // next event pair of a pool (created on first use); null when the pool is full
 static hpsmc_plan::EvPair *next_pair(std::vector<hpsmc_plan::EvPair> &pool, size_t &used)
 {
-    if (used >= 16384) return nullptr;
+    if (used >= 16384 || g_capturing) return nullptr;
     if (used == pool.size()) {
         hpsmc_plan::EvPair e;
         if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
@@ -739,6 +748,9 @@ const char *hpsmc_last_error(void) { return g_err.c_str(); }
 void hpsmc_destroy(hpsmc_plan *plan)
 {
     if (!plan) return;
+    if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->own_stream) (void)hipStreamDestroy(plan->own_stream);
     for (auto &s : plan->sets) free_set(s);
     for (auto *pool : {&plan->ev_sample, &plan->ev_slab, &plan->ev_recon, &plan->ev_span})
         for (auto &e : *pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
@@ -967,10 +979,8 @@ hpsmc_status hpsmc_sweep(hpsmc_plan *plan, int32_t tag, void *stream)
     return sweep_impl(plan, tag, plan->n_records, (hipStream_t)stream);
 }
 
-hpsmc_status hpsmc_solve(hpsmc_plan *plan, void *stream)
+static hpsmc_status solve_body(hpsmc_plan *plan, hipStream_t s)
 {
-    CHECK_PLAN(plan);
-    hipStream_t s = (hipStream_t)stream;
     hpsmc_status st;
     const int K = plan->pb.iters;
     if (plan->pb.schedule == HPSMC_SEQUENTIAL) {
@@ -986,6 +996,41 @@ hpsmc_status hpsmc_solve(hpsmc_plan *plan, void *stream)
         for (int k = 0; k < K; ++k)
             if ((st = sweep_impl(plan, plan->pb.fresh_per_iter ? k : 0, k, s))) return st;
     }
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_solve(hpsmc_plan *plan, void *stream)
+{
+    CHECK_PLAN(plan);
+    hipStream_t s = (hipStream_t)stream;
+    if (!plan->use_graph) return solve_body(plan, s);
+    if (!plan->graph_exec) {
+        // capture on a stream of the plan (the legacy default stream cannot be captured)
+        if (!plan->own_stream) HIP_TRY(hipStreamCreateWithFlags(&plan->own_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamSynchronize(s));
+        const int64_t ns0 = plan->node_samples;
+        const int32_t rec0 = plan->n_records;
+        HIP_TRY(hipStreamBeginCapture(plan->own_stream, hipStreamCaptureModeThreadLocal));
+        g_capturing = true;
+        hpsmc_status st = solve_body(plan, plan->own_stream);
+        g_capturing = false;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(plan->own_stream, &graph);
+        if (st) { if (graph) (void)hipGraphDestroy(graph); return st; }
+        if (e != hipSuccess) { plan->poisoned = true; return fail(HPSMC_EDEVICE, std::string("capture: ") + hipGetErrorString(e)); }
+        plan->graph = graph;
+        HIP_TRY(hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0));
+        plan->graph_node_samples = plan->node_samples - ns0;
+        plan->graph_records = plan->n_records;
+        plan->node_samples = ns0;   // counted again at each launch below
+        plan->n_records = rec0;
+    }
+    hpsmc_plan::EvPair *ek = next_pair(plan->ev_span, plan->n_span);
+    if (ek) HIP_TRY(hipEventRecord(ek->a, s));
+    HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
+    if (ek) HIP_TRY(hipEventRecord(ek->b, s));
+    plan->node_samples += plan->graph_node_samples;
+    plan->n_records = std::max(plan->n_records, plan->graph_records);
     return HPSMC_OK;
 }
 
@@ -1069,6 +1114,12 @@ hpsmc_status hpsmc_set_probe(hpsmc_plan *plan, int64_t m_probe)
 {
     CHECK_PLAN(plan);
     if (m_probe < 0 || m_probe > plan->pb.M) return fail(HPSMC_EINVAL, "m_probe must be 0..M");
+    if (plan->graph_exec) {   // the captured graph holds the old probe buffers
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph_exec = nullptr;
+        plan->graph = nullptr;
+    }
     for (auto &s : plan->sets) {
         (void)hipFree(s.probe);
         s.probe = nullptr;
@@ -1106,6 +1157,12 @@ hpsmc_status hpsmc_set_launch(hpsmc_plan *plan, const hpsmc_launch *l)
         return fail(HPSMC_EINVAL, "round_steps must be 0 or a multiple of 4 in 64..4096");
     plan->launch = *l;
     if (l->round_steps) plan->round_steps = l->round_steps;
+    if (plan->graph_exec) {   // the captured launches used the previous shape
+        (void)hipGraphExecDestroy(plan->graph_exec);
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph_exec = nullptr;
+        plan->graph = nullptr;
+    }
     plan->launch.round_steps = plan->round_steps;
     return HPSMC_OK;
 }
@@ -1272,7 +1329,8 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
         plan->launch = l;
         plan->round_steps = l.round_steps;
         hpsmc_status st = HPSMC_OK;
-        for (int rep = 0; rep < 2 && st == HPSMC_OK; ++rep) {   // first run loads the code object
+        for (int rep = 0; rep < 2 && st == HPSMC_OK; ++rep) {   // a short first run may be dominated by code loading
+            if (rep == 1 && ms > 200.f) break;
             if (hipEventRecord(e0, s) != hipSuccess) return fail(HPSMC_EDEVICE, "event");
             st = plan->pb.schedule == HPSMC_SEQUENTIAL ? iterate_impl(plan, iv, 0, 4095, s) : sweep_impl(plan, 0, 4095, s);
             if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
@@ -1358,6 +1416,11 @@ hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value)
 {
     CHECK_PLAN(plan);
     if (!name) return fail(HPSMC_EINVAL, "option name is NULL");
+    if (strcmp(name, "graph") == 0) {
+        if (value != 0 && value != 1) return fail(HPSMC_EINVAL, "graph must be 0 or 1");
+        plan->use_graph = (int32_t)value;
+        return HPSMC_OK;
+    }
     if (strcmp(name, "adjoint_mfma") == 0) {
         if (value != 0 && value != 1) return fail(HPSMC_EINVAL, "adjoint_mfma must be 0 or 1");
         plan->adj_use_mfma = (int32_t)value;

@@ -16,6 +16,7 @@
 #include "hpsmc_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace hpsmc {
 
@@ -221,8 +222,16 @@ __device__ __forceinline__ void contract(SP S, int P, int PP, const T (&X)[NS][D
         for (int kb = 0; kb < PMAX / 4; ++kb) {
             if (kb * 4 < P) {
                 T cu[4], cv[4];
+                if constexpr (std::is_same<SP, const T *>::value) {
+                    // rows and half-rows start on multiples of 4 elements: one vector read each
+                    typedef T v4 __attribute__((ext_vector_type(4)));
+                    const v4 qu = *(const v4 *)(srow + 4 * kb), qv = *(const v4 *)(srow + PP + 4 * kb);
+                    cu[0] = qu.x; cu[1] = qu.y; cu[2] = qu.z; cu[3] = qu.w;
+                    cv[0] = qv.x; cv[1] = qv.y; cv[2] = qv.z; cv[3] = qv.w;
+                } else {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) { cu[c] = srow[4 * kb + c]; cv[c] = srow[PP + 4 * kb + c]; }
+                    for (int c = 0; c < 4; ++c) { cu[c] = srow[4 * kb + c]; cv[c] = srow[PP + 4 * kb + c]; }
+                }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
 #pragma unroll

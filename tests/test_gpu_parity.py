@@ -231,3 +231,27 @@ def test_fp32_sampling_against_fp64_and_exact():
     print(f"e64={e64:.3e} e32={e32:.3e} |u32-u64|={d:.3e} sigma={sig:.3e}")
     assert e32 <= e64 + 3 * sig
     assert d <= 3 * sig + 1e-5
+
+
+def test_graph_replays_match_eager_solve():
+    """hipGraph of a whole solve: every replay (with eager work and
+    synchronizations in between) equals the eager solve bit for bit."""
+    import torch
+    H = _hp()
+    _say("graph")
+    for wl in [W.small(dim=2, n=4, M_deg=3, M=100, iters=2, precision="fp32"),
+               W.small(dim=1, n=5, M_deg=[2, 3], M=80, iters=2, T=0.8, n_intervals=2)]:
+        with H.Plan(wl) as plan:
+            plan.hpsmc_solve()
+            ref = [plan.hpsmc_get_nodes(iv) for iv in range(wl.n_intervals)]
+        with H.Plan(wl) as plan:
+            plan.hpsmc_set_option("graph", 1)
+            for rep in range(3):
+                plan.hpsmc_solve()
+                torch.cuda.synchronize()
+                got = [plan.hpsmc_get_nodes(iv) for iv in range(wl.n_intervals)]
+                for a, b in zip(got, ref):
+                    assert np.array_equal(a, b), rep
+                x = torch.randn(1 << 20, device="cuda")          # eager work between replays
+                (x * 2).sum().item()
+                plan.hpsmc_set_nodes(0, np.zeros_like(ref[0]))   # clobber: the replay re-initializes
