@@ -22,11 +22,18 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every source (incremental=True skips objects newer than their
+    source and the shared headers)."""
     objs = []
+    headers = [os.path.join(CSRC, "hpsmc_internal.h"), os.path.join(ROOT, "include", "hpsmc.h")]
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
+        deps = [os.path.join(CSRC, src)] + headers
+        if incremental and os.path.exists(obj) and all(os.path.getmtime(obj) > os.path.getmtime(d) for d in deps):
+            objs.append(obj)
+            continue
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
         cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -40,4 +47,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="-i" in sys.argv))

@@ -324,6 +324,28 @@ static double pool_ms(const std::vector<hpsmc_plan::EvPair> &pool, size_t used)
     return tot;
 }
 
+// LDS chunking of a slab: the first cf dimensions fixed per chunk.  The two
+// options per dimension are those the kernel is instantiated for.  Returns
+// false when no option fits four 16-byte vectors per thread.
+static bool pick_chunking(const hpsmc_plan *plan, int nthr, int *cf, int64_t *chunk_elems, int *n_chunks)
+{
+    const int d = plan->d;
+    const int opts[2] = {d <= 3 ? 0 : d - 3, d <= 1 ? 0 : (d <= 3 ? 1 : d - 2)};
+    const int T = plan->fp32 ? 4 : 8;
+    for (int o = 0; o < 2; ++o) {
+        const int c = opts[o];
+        const int64_t rows = ipow(plan->P, d - 1 - c);
+        const int64_t elems = rows * 2 * plan->PP;
+        if (elems * T / 16 <= 4LL * nthr) {
+            *cf = c;
+            *chunk_elems = elems;
+            *n_chunks = (int)ipow(plan->P, c);
+            return true;
+        }
+    }
+    return false;
+}
+
 static hpsmc_status validate(const hpsmc_problem *pb)
 {
     if (!pb) return fail(HPSMC_EINVAL, "problem is NULL");
@@ -436,9 +458,12 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     }
     set.n = (int64_t)set.host.size();
     if (set.n > (int64_t)0x7fffffff) return fail(HPSMC_EINVAL, "too many nodes");
-    // rounds need the slab of one step in LDS (two buffers, at most 4 vectors per thread of a 4-wave block)
-    const int64_t slab_bytes = stride * T;
-    set.rounds = d <= 3 && slab_bytes <= 16384;
+    // rounds stream the slab of a step through LDS in chunks of at most 4 vectors per thread
+    {
+        int cf, nc;
+        int64_t ce;
+        set.rounds = pick_chunking(plan, 256, &cf, &ce, &nc);
+    }
     if (set.rounds) {
         // group descriptors: nodes were generated group by group
         const int64_t per = plan->nsp;
@@ -615,8 +640,11 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
 {
     const int ns = plan->launch.samples_per_lane, waves = plan->launch.waves_per_block;
     const int nthr = 64 * waves;
-    const int64_t nvec = set.slab.slab_stride * (plan->fp32 ? 4 : 8) / 16;
-    if (nvec > 4LL * nthr) return fail(HPSMC_EINVAL, "slab too large for this block size; use more waves per block");
+    int cf, n_chunks;
+    int64_t chunk_elems;
+    if (!pick_chunking(plan, nthr, &cf, &chunk_elems, &n_chunks))
+        return fail(HPSMC_EINVAL, "slab chunk too large for this block size; use more waves per block");
+    const int64_t nvec = chunk_elems * (plan->fp32 ? 4 : 8) / 16;
     const size_t lds = (size_t)2 * ((nvec + 1) & ~1LL) * 16;
     const int C = plan->round_steps;
     const int R = (set.max_nstar + C - 1) / C;
@@ -629,6 +657,9 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     a.batch = nthr * ns;
     a.batch_prefix = set.prefix;
     a.result = set.result;
+    a.cf = cf;
+    a.n_chunks = n_chunks;
+    a.chunk_elems = chunk_elems;
     a.P = plan->P;
     a.PP = plan->PP;
     a.tag = tag;
@@ -1313,8 +1344,10 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     for (int a = 0; a < 3; ++a) {
         if (nsv[a] == 4 && plan->d > 2) continue;
         for (int w : {2, 4}) {
-            // the LDS-staged slab must fit 4 vectors per thread
-            if (set.rounds && set.slab.slab_stride * (plan->fp32 ? 4 : 8) / 16 > 4LL * 64 * w) continue;
+            // the LDS-staged slab chunk must fit 4 vectors per thread
+            int cf, nc;
+            int64_t ce;
+            if (set.rounds && !pick_chunking(plan, 64 * w, &cf, &ce, &nc)) continue;
             for (int b : {2, 4, 8}) cands.push_back(hpsmc_launch{nsv[a], w, b, plan->round_steps});
         }
     }

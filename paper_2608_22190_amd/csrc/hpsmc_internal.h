@@ -82,6 +82,9 @@ struct RoundArgs {
     uint32_t *live_out;          // per group, survivors appended to state_out
     const int64_t *batch_prefix; // [n_groups + 1] work items per group, prefix
     double *result;              // [node out][mcount] path value S of each sample
+    int32_t n_chunks;            // LDS chunks per slab: P^cf, the first cf dimensions fixed per chunk
+    int32_t cf;
+    int64_t chunk_elems;         // slab elements per chunk (P^{d-1-cf} rows)
     int32_t P, PP, tag;
     uint32_t key0, key1;
     const void *slab_table;

@@ -791,12 +791,14 @@ hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxStageVec = 4;   // 16-byte slab vectors staged per thread and step
 
-template <typename T, int D, int PMAX, int NS>
+template <typename T, int D, int PMAX, int NS, int CF>
 __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
 {
     extern __shared__ u32x4 lds[];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
-    const int64_t nvec = a.slab_stride * (int64_t)sizeof(T) / 16;   // 16-byte vectors per slab
+    const int NC = a.n_chunks;
+    const int64_t nvec = a.chunk_elems * (int64_t)sizeof(T) / 16;   // 16-byte vectors per chunk
+    const int64_t cvec = (nvec + 1) & ~(int64_t)1;                   // LDS buffer stride in vectors
     __shared__ long long s_item;
     cptr<GroupDesc> groups = as_const(a.groups);
     cptr<NodeDesc> nodes = as_const(a.nodes);
@@ -861,7 +863,7 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
             }
         }
 
-        // ---- slab of the first step into LDS buffer 0
+        // ---- first chunk of the first step's slab into LDS buffer 0
         u32x4 stage[kMaxStageVec];
         {
             const u32x4 *src = (const u32x4 *)(gtab + (int64_t)q0 * a.slab_stride);
@@ -876,16 +878,6 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
         uint32_t w[NS][4];
         int q = q0;
         for (; q < q1; ++q) {
-            const int buf = (q - q0) & 1;
-            // prefetch the next step's slab into registers
-            if (q + 1 < q1) {
-                const u32x4 *src = (const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride);
-#pragma unroll
-                for (int k = 0; k < kMaxStageVec; ++k) {
-                    const int64_t v = tid + (int64_t)k * nthr;
-                    if (v < nvec) stage[k] = src[v];
-                }
-            }
             // ---- directions (Philox words refreshed on block boundaries of the counter)
             T dir[NS][D];
             if constexpr (D == 1) {
@@ -962,23 +954,72 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
                 any_live = any_live || alive[s];
             }
             slots += NS;
-            // ---- residual at X_q, time tau_q = t_{n,l} - q Delta, from the LDS slab
-            if (__ballot(any_live) != 0ull) {
-                const T *S = (const T *)(lds + (int64_t)buf * ((nvec + 1) & ~(int64_t)1));
-                T Ll[NS][PMAX];
+            // ---- residual at X_q, time tau_q = t_{n,l} - q Delta: the slab of step q
+            // streams through LDS in NC chunks (double buffered along the chunk sequence)
+            const bool wave_live = __ballot(any_live) != 0ull;
+            T Ll[NS][PMAX], u[NS], v[NS];
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    const T x = X[s][D - 1];
-                    Ll[s][0] = (T)1;
-                    if (PMAX > 1) Ll[s][1] = x;
+            for (int s = 0; s < NS; ++s) {
+                const T x = X[s][D - 1];
+                Ll[s][0] = (T)1;
+                if (PMAX > 1) Ll[s][1] = x;
 #pragma unroll
-                    for (int k = 1; k + 1 < PMAX; ++k)
-                        Ll[s][k + 1] = (T)((2.0 * k + 1.0) / (k + 1.0)) * x * Ll[s][k] - (T)(k / (k + 1.0)) * Ll[s][k - 1];
+                for (int k = 1; k + 1 < PMAX; ++k)
+                    Ll[s][k + 1] = (T)((2.0 * k + 1.0) / (k + 1.0)) * x * Ll[s][k] - (T)(k / (k + 1.0)) * Ll[s][k - 1];
+                u[s] = (T)0;
+                v[s] = (T)0;
+            }
+            for (int c = 0; c < NC; ++c) {
+                const int64_t tseq = (int64_t)(q - q0) * NC + c;
+                const int buf = (int)(tseq & 1);
+                int qn = q, cn = c + 1;
+                if (cn == NC) { cn = 0; qn = q + 1; }
+                const bool has_next = qn < q1;
+                if (has_next) {
+                    const u32x4 *src = (const u32x4 *)(gtab + (int64_t)qn * a.slab_stride + (int64_t)cn * a.chunk_elems);
+#pragma unroll
+                    for (int k = 0; k < kMaxStageVec; ++k) {
+                        const int64_t vv = tid + (int64_t)k * nthr;
+                        if (vv < nvec) stage[k] = src[vv];
+                    }
                 }
-                T u[NS], v[NS], W[NS];
+                if (wave_live) {
+                    const T *S = (const T *)(lds + (int64_t)buf * cvec);
+                    T Wc[NS];
 #pragma unroll
-                for (int s = 0; s < NS; ++s) { u[s] = (T)0; v[s] = (T)0; W[s] = (T)1; }
-                contract<T, D, PMAX, NS, 0, const T *>(S, a.P, a.PP, X, W, Ll, u, v, 0);
+                    for (int s = 0; s < NS; ++s) Wc[s] = (T)1;
+                    if constexpr (CF > 0) {
+                        // weight of the chunk: prod over the fixed dims of L_{k_i}(X_i)
+                        int rem = c;
+#pragma unroll
+                        for (int i = CF - 1; i >= 0; --i) {
+                            const int ki = rem % a.P;
+                            rem /= a.P;
+#pragma unroll
+                            for (int s = 0; s < NS; ++s) {
+                                T lp = (T)0, lc = (T)1;
+                                for (int m = 0; m < ki; ++m) {
+                                    const T nx = rec_a<T>(m) * X[s][i] * lc - rec_b<T>(m) * lp;
+                                    lp = lc;
+                                    lc = nx;
+                                }
+                                Wc[s] *= lc;
+                            }
+                        }
+                    }
+                    contract<T, D, PMAX, NS, CF, const T *>(S, a.P, a.PP, X, Wc, Ll, u, v, 0);
+                }
+                if (has_next) {
+                    u32x4 *dst = lds + (int64_t)(buf ^ 1) * cvec;
+#pragma unroll
+                    for (int k = 0; k < kMaxStageVec; ++k) {
+                        const int64_t vv = tid + (int64_t)k * nthr;
+                        if (vv < nvec) dst[vv] = stage[k];
+                    }
+                }
+                if (c + 1 < NC) __syncthreads();
+            }
+            if (wave_live) {
                 const T tau = (T)(t_prev + (span - (double)q * ddelta));
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
@@ -997,15 +1038,6 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
                         for (int i = 0; i < D; ++i) X[s][i] = Y[s][i];
                         ++evals;
                     }
-                }
-            }
-            // ---- next slab into the other buffer; one barrier per step
-            if (q + 1 < q1) {
-                u32x4 *dst = lds + (int64_t)(buf ^ 1) * ((nvec + 1) & ~(int64_t)1);
-#pragma unroll
-                for (int k = 0; k < kMaxStageVec; ++k) {
-                    const int64_t v = tid + (int64_t)k * nthr;
-                    if (v < nvec) dst[v] = stage[k];
                 }
             }
             if (__syncthreads_or(any_live ? 1 : 0) == 0) { ++q; break; }
@@ -1044,18 +1076,29 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
     }
 }
 
+template <typename T, int D, int PMAX, int NS>
+static hipError_t adv_cf(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    // chunking options per dimension: whole slab or one fixed dimension for d <= 3,
+    // two or three fixed dimensions for d = 4, 5
+    constexpr int C0 = D <= 3 ? 0 : D - 3;
+    constexpr int C1 = D <= 1 ? 0 : (D <= 3 ? 1 : D - 2);
+    if (a.cf == C0) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C0>), grid, block, lds, s, a); return hipGetLastError(); }
+    if (a.cf == C1) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C1>), grid, block, lds, s, a); return hipGetLastError(); }
+    return hipErrorInvalidValue;
+}
+
 template <typename T, int D, int PMAX>
 static hipError_t adv_ns(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_t lds, hipStream_t s)
 {
     switch (ns) {
-    case 1: hipLaunchKernelGGL((advance_kernel<T, D, PMAX, 1>), grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((advance_kernel<T, D, PMAX, 2>), grid, block, lds, s, a); break;
+    case 1: return adv_cf<T, D, PMAX, 1>(a, grid, block, lds, s);
+    case 2: return adv_cf<T, D, PMAX, 2>(a, grid, block, lds, s);
     case 4:
-        if constexpr (D <= 2) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, 4>), grid, block, lds, s, a); break; }
+        if constexpr (D <= 2) return adv_cf<T, D, PMAX, 4>(a, grid, block, lds, s);
         return hipErrorInvalidValue;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <typename T, int D>
@@ -1079,6 +1122,8 @@ static hipError_t adv_d(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_
     case 1: return adv_p<T, 1>(a, ns, grid, block, lds, s);
     case 2: return adv_p<T, 2>(a, ns, grid, block, lds, s);
     case 3: return adv_p<T, 3>(a, ns, grid, block, lds, s);
+    case 4: return adv_p<T, 4>(a, ns, grid, block, lds, s);
+    case 5: return adv_p<T, 5>(a, ns, grid, block, lds, s);
     }
     return hipErrorInvalidValue;
 }

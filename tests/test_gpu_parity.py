@@ -55,6 +55,25 @@ def test_one_iteration_increment_fp64(dim, n, deg, M, ns):
     assert np.max(np.abs(U_g[0].reshape(-1) - U_o)) <= TOL * scale
 
 
+def test_one_iteration_chunked_slabs_fp64():
+    """Slabs larger than one LDS chunk (d = 3 with 12 modes in FP64, d = 4, 5)
+    stream through LDS in chunks with the leading dimensions fixed."""
+    H = _hp()
+    for dim, n, deg, M, ns in [(3, 10, 2, 40, 1), (4, 4, 2, 20, 2), (5, 3, 2, 17, 1), (3, 10, 2, 40, 2)]:
+        wl = W.small(dim=dim, n=n, M_deg=deg, M=M, T=0.5, f="sin", src="longtime", nstar=30)
+        _say("chunked", dim, n, deg, M, ns)
+        U = _random_nodes(wl, seed=dim + 10)
+        with H.Plan(wl) as plan:
+            plan.hpsmc_set_launch(ns, 4, 4)
+            plan.hpsmc_set_nodes(0, U)
+            plan.hpsmc_iterate(0, 0)
+            eps_g, _ = plan.hpsmc_get_increment(0)
+            st = plan.hpsmc_stats()
+        eps_o, _, steps_o = O.Problem(wl).estimate(U[0].reshape(-1), iter_tag=0)
+        assert np.max(np.abs(eps_g[0] - eps_o)) <= TOL * np.max(np.abs(U)), (dim, n)
+        assert st["path_steps"] == int(np.sum(steps_o)), (dim, n)
+
+
 @pytest.mark.parametrize("dim,n,deg,M,iters", [(1, 6, 4, 100, 3), (2, 4, 3, 64, 2)])
 def test_solve_single_interval_fp64(dim, n, deg, M, iters):
     H = _hp()
