@@ -24,12 +24,32 @@ import time
 
 import numpy as np
 
+os.environ.setdefault("HPSMC_TUNE_VERBOSE", "1")   # the tuner reports each trial on stderr
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3   # published MI355X vector FP32 (counts packed FMA)
 FP64_PEAK_TFLOPS = 78.6    # published MI355X vector FP64
 METRIC = "node-samples/sec at fixed error vs exact; FP32-batched vs FP64 speedup"
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "advance_kernel_c2_fp32_m1024_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2608_22190_amd", "csrc", "hpsmc_kernels.hip")
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch of the sampling kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (scaled by the copy-kernel calibration),
+    or None when the kernel source or launch shape changed since they were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != sha or list(rec.get("launch", [])) != list(launch):
+        return None
+    return 1024.0 * (rec["fetch_kib_per_launch"] * rec["fetch_factor"] + rec["write_kib_per_launch"] * rec["write_factor"])
 
 
 def flops_per_eval(dim, P):
@@ -97,6 +117,11 @@ def run_other(name, args, torch):
     with hpsmc.Plan(wl) as plan:
         if args.launch:
             plan.hpsmc_set_launch(*(int(v) for v in args.launch.split(",")))
+        elif args.tune_cache and name in ("c3", "c4"):
+            t0 = time.perf_counter()
+            plan.hpsmc_tune(0, min(wl.M, 4), args.tune_cache, stream=stream)
+            print(f"[bench] {name} launch {plan.hpsmc_get_launch()} ({time.perf_counter() - t0:.1f}s)",
+                  file=sys.stderr, flush=True)
         def step(k):
             if name == "c1":
                 plan.hpsmc_solve(stream=stream)
@@ -121,6 +146,7 @@ def run_other(name, args, torch):
             print(f"[bench] {name} step {k + 1} {time.perf_counter() - t0:.2f}s", file=sys.stderr, flush=True)
         sec = time.perf_counter() - t0
         st = plan.hpsmc_stats(stream=stream)
+        plan_launch = plan.hpsmc_get_launch()
     per_step = nodes * wl.M * (wl.iters if name in ("c1", "c5") else 1)
     P = wl.n + 2
     fpe = flops_per_eval(wl.dim, P)
@@ -135,7 +161,8 @@ def run_other(name, args, torch):
     out = {"metric": METRIC, "value": per_step * args.steps / sec, "unit": "node-samples/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * sec / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if wl.precision == "fp64" else "f32",
-           "data": "synthetic", "config": {"workload": desc, "max_nstar": int(max(wl.nstar)), "launch": None}}
+           "data": "synthetic", "config": {"workload": desc, "max_nstar": int(max(wl.nstar)),
+                                           "launch": list(plan_launch)}}
     if name != "c5":
         out["roofline"] = {"bound": "alu", "achieved": fpe * st["path_steps"] / launches / max(1e-9, k_ms * 1e-3) / 1e12
                            if st["sample_launches"] else None,
@@ -234,7 +261,7 @@ def main():
                    "dim": 2, "n": 24, "temporal_degree": 16, "nodes": nodes, "samples_per_node": base.M,
                    "max_nstar": int(max(base.nstar)), "launch": list(r32["launch"])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(r32["launch"]),
                      "kernel": "advance_kernel<float,2,28,NS>", "flops_per_eval": fpe,
                      "evals_per_launch": evals_per_launch, "avg_launch_ms": k_ms,
                      "lane_utilization": st["path_steps"] / max(1, st["lane_steps"])},

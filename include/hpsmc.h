@@ -128,7 +128,7 @@ typedef struct {
     int32_t waves_per_block;   /* 1..4                                            */
     int32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu          */
     int32_t round_steps;       /* walk steps per round of the path-advancing
-                                  kernel (multiple of 4 in 64..4096; 0 keeps
+                                  kernel (multiple of 4 in 16..4096; 0 keeps
                                   the current value)                             */
 } hpsmc_launch;
 

@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -1184,8 +1185,8 @@ hpsmc_status hpsmc_set_launch(hpsmc_plan *plan, const hpsmc_launch *l)
     const bool ns_ok = l->samples_per_lane == 1 || l->samples_per_lane == 2 || (l->samples_per_lane == 4 && plan->d <= 2);
     if (!ns_ok || l->waves_per_block < 1 || l->waves_per_block > 4 || l->blocks_per_cu < 1 || l->blocks_per_cu > 64)
         return fail(HPSMC_EINVAL, "launch shape out of range");
-    if (l->round_steps != 0 && (l->round_steps < 64 || l->round_steps > 4096 || l->round_steps % 4 != 0))
-        return fail(HPSMC_EINVAL, "round_steps must be 0 or a multiple of 4 in 64..4096");
+    if (l->round_steps != 0 && (l->round_steps < 16 || l->round_steps > 4096 || l->round_steps % 4 != 0))
+        return fail(HPSMC_EINVAL, "round_steps must be 0 or a multiple of 4 in 16..4096");
     plan->launch = *l;
     if (l->round_steps) plan->round_steps = l->round_steps;
     if (plan->graph_exec) {   // the captured launches used the previous shape
@@ -1378,20 +1379,28 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     };
     hpsmc_status st = HPSMC_OK;
     float best_ms = 1e30f;
+    const bool verbose = getenv("HPSMC_TUNE_VERBOSE") != nullptr;
+    auto report = [&](const hpsmc_launch &c, float ms) {
+        if (verbose)
+            fprintf(stderr, "[tune] %s ns=%d waves=%d blocks/cu=%d steps=%d: %.3f ms\n", key.c_str(), c.samples_per_lane,
+                    c.waves_per_block, c.blocks_per_cu, c.round_steps, ms);
+    };
     for (const auto &c : cands) {
         float ms;
         if ((st = trial(c, ms))) break;
+        report(c, ms);
         if (ms < best_ms) { best_ms = ms; best = c; }
     }
     if (!st) {
-        const int rs_d1[3] = {128, 256, 512}, rs[3] = {128, 256, 512};
+        const int rs_d1[5] = {128, 256, 512, 1024, 128}, rs[5] = {32, 64, 128, 256, 512};
         const hpsmc_launch base = best;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 5; ++k) {
             hpsmc_launch c = base;
             c.round_steps = plan->d == 1 ? rs_d1[k] : rs[k];
             if (c.round_steps == base.round_steps) continue;
             float ms;
             if ((st = trial(c, ms))) break;
+            report(c, ms);
             if (ms < best_ms) { best_ms = ms; best = c; }
         }
     }
