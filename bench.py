@@ -28,7 +28,7 @@ os.environ.setdefault("HPSMC_TUNE_VERBOSE", "1")   # the tuner reports each tria
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_PEAK_TFLOPS = 157.3   # published MI355X vector FP32 (counts packed FMA)
+FP32_PEAK_TFLOPS = 157.3   # published MI355X FP32: dense matrix cores, and the vector units with packed FMA
 FP64_PEAK_TFLOPS = 78.6    # published MI355X vector FP64
 METRIC = "node-samples/sec at fixed error vs exact; FP32-batched vs FP64 speedup"
 
@@ -94,8 +94,9 @@ def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256):
         U = plan.hpsmc_get_nodes(0, stream=stream)
         eps, ssq = plan.hpsmc_get_increment(0, stream=stream)
         lau = plan.hpsmc_get_launch()
+        mma = plan.hpsmc_get_option("sample_mfma_active")
     sig = float(np.sqrt(np.maximum(ssq / wl.M - eps ** 2, 0.0) / wl.M).max())
-    return {"seconds": t1 - t0, "stats": st, "U": U, "sigma": sig, "launch": lau}
+    return {"seconds": t1 - t0, "stats": st, "U": U, "sigma": sig, "launch": lau, "mma": mma}
 
 
 def run_other(name, args, torch):
@@ -117,7 +118,7 @@ def run_other(name, args, torch):
     with hpsmc.Plan(wl) as plan:
         if args.launch:
             plan.hpsmc_set_launch(*(int(v) for v in args.launch.split(",")))
-        elif args.tune_cache and name in ("c3", "c4"):
+        elif args.tune_cache and name in ("c3", "c4", "c5"):
             t0 = time.perf_counter()
             plan.hpsmc_tune(0, min(wl.M, 4), args.tune_cache, stream=stream)
             print(f"[bench] {name} launch {plan.hpsmc_get_launch()} ({time.perf_counter() - t0:.1f}s)",
@@ -147,6 +148,7 @@ def run_other(name, args, torch):
         sec = time.perf_counter() - t0
         st = plan.hpsmc_stats(stream=stream)
         plan_launch = plan.hpsmc_get_launch()
+        mma = plan.hpsmc_get_option("sample_mfma_active")
     per_step = nodes * wl.M * (wl.iters if name in ("c1", "c5") else 1)
     P = wl.n + 2
     fpe = flops_per_eval(wl.dim, P)
@@ -164,7 +166,7 @@ def run_other(name, args, torch):
            "data": "synthetic", "config": {"workload": desc, "max_nstar": int(max(wl.nstar)),
                                            "launch": list(plan_launch)}}
     if name != "c5":
-        out["roofline"] = {"bound": "alu", "achieved": fpe * st["path_steps"] / launches / max(1e-9, k_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma" if mma else "alu", "achieved": fpe * st["path_steps"] / launches / max(1e-9, k_ms * 1e-3) / 1e12
                            if st["sample_launches"] else None,
                            "peak": FP64_PEAK_TFLOPS if wl.precision == "fp64" else FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "avg_launch_ms": k_ms, "flops_per_eval": fpe,
@@ -260,9 +262,12 @@ def main():
                                f"of M=65536; FP32 sampling, FP64 reconstruction/update",
                    "dim": 2, "n": 24, "temporal_degree": 16, "nodes": nodes, "samples_per_node": base.M,
                    "max_nstar": int(max(base.nstar)), "launch": list(r32["launch"])},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(r32["launch"]),
-                     "kernel": "advance_kernel<float,2,28,NS>", "flops_per_eval": fpe,
+        "roofline": {"bound": "mfma" if r32["mma"] else "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": measured_traffic(r32["launch"]),
+                     "kernel": (f"advance_kernel<float,2,{P},1,0,{(P + 1) // 2}> (v_mfma_f32_32x32x2f32)"
+                                if r32["mma"] else "advance_kernel<float,2,28,NS,0,0> (vector units)"),
+                     "flops_per_eval": fpe,
                      "evals_per_launch": evals_per_launch, "avg_launch_ms": k_ms,
                      "lane_utilization": st["path_steps"] / max(1, st["lane_steps"])},
         "path_steps_per_s": st["path_steps"] / r32["seconds"],

@@ -203,12 +203,24 @@ hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_
 /* Named integer options:
  *   "adjoint_mfma"      1 (default): FP32 adjoint outer products on the matrix
  *                       cores; 0: on the vector units.
+ *   "sample_mfma"       1 (default): 2-D FP32 plans with P = n + 2 <= 32 and one
+ *                       sample per lane run the path-advancing kernel with the
+ *                       slab contraction of eq. ufg_ep1 on the matrix cores
+ *                       (v_mfma_f32_32x32x2f32); 0: always on the vector units.
+ *                       Same walks and exit steps either way; the FP32 sums
+ *                       differ only by rounding order.  Changing it discards a
+ *                       captured graph.
  *   "graph"             1: hpsmc_solve captures the whole solve into a hipGraph
  *                       on its first call (on a stream of the plan) and replays
  *                       it on this and later calls; 0 (default): eager launches.
  *                       A new launch shape discards the captured graph.
  * EINVAL for an unknown name or value. */
 hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value);
+
+/* Read a named option into *value: the names above, and the read-only
+ * "sample_mfma_active" = 1 when the current launch shape runs the matrix-core
+ * path-advancing kernel for some interval.  EINVAL for an unknown name. */
+hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t *value);
 
 const char *hpsmc_last_error(void);
 

@@ -267,6 +267,7 @@ struct hpsmc_plan {
     int32_t adj_use_mfma = 1;
     // hipGraph of a whole solve (captured on the first graph solve, replayed after)
     int32_t use_graph = 0;
+    int32_t sample_mma = 1;     // 2-D FP32 round kernel on the matrix cores where eligible
     bool capturing = false;
     hipStream_t own_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -646,7 +647,8 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     if (!pick_chunking(plan, nthr, &cf, &chunk_elems, &n_chunks))
         return fail(HPSMC_EINVAL, "slab chunk too large for this block size; use more waves per block");
     const int64_t nvec = chunk_elems * (plan->fp32 ? 4 : 8) / 16;
-    const size_t lds = (size_t)2 * ((nvec + 1) & ~1LL) * 16;
+    const int mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, ns);
+    const size_t lds = mma ? advance_mma_lds_bytes(plan->PP) : (size_t)2 * ((nvec + 1) & ~1LL) * 16;
     const int C = plan->round_steps;
     const int R = (set.max_nstar + C - 1) / C;
     const int G = (int)set.ghost.size();
@@ -688,7 +690,7 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
             HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, a.live_in, a.live_out, set.prefix, plan->counters, s));
             hpsmc_plan::EvPair *ea = next_pair(plan->ev_sample, plan->n_sample);
             if (ea) HIP_TRY(hipEventRecord(ea->a, s));
-            HIP_TRY(launch_advance(a, plan->fp32, ns, waves, blocks, lds, s));
+            HIP_TRY(launch_advance(a, plan->fp32, ns, waves, blocks, lds, mma, s));
             if (ea) HIP_TRY(hipEventRecord(ea->b, s));
         }
         HIP_TRY(launch_slice_reduce(set.result, set.n, mc, plan->part, first, s));
@@ -1264,9 +1266,11 @@ static std::string tune_key(const hpsmc_plan *plan, int iv, int64_t M)
         const size_t c = arch.find(':');
         if (c != std::string::npos) arch = arch.substr(0, c);
     }
+    // plans that may run the matrix-core round kernel tune separately from those that may not
+    const bool mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1);
     char buf[256];
-    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
-             plan->fp32 ? "fp32" : "fp64", (long long)M, plan->n_inst, arch.c_str());
+    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
+             plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", (long long)M, plan->n_inst, arch.c_str());
     return buf;
 }
 
@@ -1466,6 +1470,44 @@ hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value)
     if (strcmp(name, "adjoint_mfma") == 0) {
         if (value != 0 && value != 1) return fail(HPSMC_EINVAL, "adjoint_mfma must be 0 or 1");
         plan->adj_use_mfma = (int32_t)value;
+        return HPSMC_OK;
+    }
+    if (strcmp(name, "sample_mfma") == 0) {
+        if (value != 0 && value != 1) return fail(HPSMC_EINVAL, "sample_mfma must be 0 or 1");
+        if (plan->sample_mma != (int32_t)value && plan->graph_exec) {   // the captured launches used the other kernel
+            (void)hipGraphExecDestroy(plan->graph_exec);
+            (void)hipGraphDestroy(plan->graph);
+            plan->graph_exec = nullptr;
+            plan->graph = nullptr;
+        }
+        plan->sample_mma = (int32_t)value;
+        return HPSMC_OK;
+    }
+    return fail(HPSMC_EINVAL, std::string("unknown option ") + name);
+}
+
+// whether the round kernel of interval iv runs on the matrix cores with the current launch shape
+static int mma_active(const hpsmc_plan *plan, int iv)
+{
+    const NodeSet &set = plan->pb.schedule == HPSMC_SEQUENTIAL ? plan->sets[iv] : plan->sets[0];
+    if (!set.rounds || !plan->sample_mma) return 0;
+    int cf, nc;
+    int64_t ce;
+    if (!pick_chunking(plan, 64 * plan->launch.waves_per_block, &cf, &ce, &nc)) return 0;
+    return advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, plan->launch.samples_per_lane) ? 1 : 0;
+}
+
+hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t *value)
+{
+    CHECK_PLAN(plan);
+    if (!name || !value) return fail(HPSMC_EINVAL, "NULL argument");
+    if (strcmp(name, "graph") == 0) { *value = plan->use_graph; return HPSMC_OK; }
+    if (strcmp(name, "adjoint_mfma") == 0) { *value = plan->adj_use_mfma; return HPSMC_OK; }
+    if (strcmp(name, "sample_mfma") == 0) { *value = plan->sample_mma; return HPSMC_OK; }
+    if (strcmp(name, "sample_mfma_active") == 0) {
+        *value = 0;
+        for (int iv = 0; iv < (plan->pb.schedule == HPSMC_SEQUENTIAL ? plan->n_iv : 1); ++iv)
+            *value |= mma_active(plan, iv);
         return HPSMC_OK;
     }
     return fail(HPSMC_EINVAL, std::string("unknown option ") + name);

@@ -789,17 +789,105 @@ hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t 
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kMaxStageVec = 4;   // 16-byte slab vectors staged per thread and step
+constexpr int kMmaRS = 33;        // LDS column stride (floats) of the transposed slab: odd, so
+                                  // the 32 rows a half-wave reads fall in distinct banks
 
-template <typename T, int D, int PMAX, int NS, int CF>
+// ---------------------------------------------------------------------------
+// Matrix-core contraction of one step's 2-D slab for the 64 paths of a wave.
+// For 32 paths s at points (x0_s, x1_s) and either coefficient table S (u or v):
+//     T[k0][s] = sum_{k1} S[k0][k1] L_{k1}(x1_s)     -- a (32 x K) (K x 32) product
+//     u_s      = sum_{k0} L_{k0}(x0_s) T[k0][s]
+// The product runs on v_mfma_f32_32x32x2f32 (A: lane l holds A[l%32][l/32], B:
+// B[l/32][l%32], D register r: D[8(r/4) + 4(l/32) + r%4][l%32]) with the mode
+// axis k1 split into halves of KH = ceil(P/2): at step kk lanes 0-31 supply mode
+// kk, lanes 32-63 mode KH + kk.  Paths 0-31 of the wave form one product and
+// paths 32-63 the other; permlane32 swaps move each lane's own Legendre values
+// into the operand layout and bring the rows of T back to the lane that owns
+// the path, so no lane duplicates another's work.
+// Sb: slab in LDS, transposed: Sb[c * kMmaRS + k0], c = k1 (u) or PP + k1 (v);
+// rows k0 in [P, 32) hold zeros, columns k1 in [P, PP) the slab's zero padding.
+// ---------------------------------------------------------------------------
+template <int KH>
+__device__ __forceinline__ void mma_contract(const float *Sb, int P, int PP, float x0, float x1, int lane,
+                                             float &u, float &v)
+{
+    static_assert(KH >= 2 && KH <= 16, "one 32-row tile, at least 4 modes");
+    constexpr int K2 = 2 * KH;
+    float L[K2];
+    L[0] = 1.f;
+    L[1] = x1;
+#pragma unroll
+    for (int k = 1; k + 1 < K2; ++k)
+        L[k + 1] = (float)((2.0 * k + 1.0) / (k + 1.0)) * x1 * L[k] - (float)(k / (k + 1.0)) * L[k - 1];
+    if (P < K2) L[K2 - 1] = 0.f;   // odd P: mode P does not exist
+    float b0[KH], b1[KH];
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(L[kk]), __float_as_uint(L[KH + kk]), false, false);
+        b0[kk] = __uint_as_float(r[0]);   // paths 0-31: lanes 0-31 modes kk, lanes 32-63 modes KH + kk
+        b1[kk] = __uint_as_float(r[1]);   // paths 32-63, same split
+    }
+    const float *Au = Sb + (lane >> 5) * KH * kMmaRS + (lane & 31);
+    const float *Av = Au + PP * kMmaRS;
+    f32x16 du0 = {}, dv0 = {}, du1 = {}, dv1 = {};
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) {
+        const float au = Au[kk * kMmaRS], av = Av[kk * kMmaRS];
+        du0 = __builtin_amdgcn_mfma_f32_32x32x2f32(au, b0[kk], du0, 0, 0, 0);
+        dv0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0[kk], dv0, 0, 0, 0);
+        du1 = __builtin_amdgcn_mfma_f32_32x32x2f32(au, b1[kk], du1, 0, 0, 0);
+        dv1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1[kk], dv1, 0, 0, 0);
+    }
+    // Legendre values in x0 (rows >= P of T are zero)
+    L[1] = x0;
+#pragma unroll
+    for (int k = 1; k + 1 < K2; ++k)
+        L[k + 1] = (float)((2.0 * k + 1.0) / (k + 1.0)) * x0 * L[k] - (float)(k / (k + 1.0)) * L[k - 1];
+    float su = 0.f, sv = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int ia = 8 * (r / 4) + (r % 4), ib = ia + 4;   // rows held before / after the swap
+        if (ia < K2) {
+            const auto pu = __builtin_amdgcn_permlane32_swap(__float_as_uint(du0[r]), __float_as_uint(du1[r]), false, false);
+            const auto pv = __builtin_amdgcn_permlane32_swap(__float_as_uint(dv0[r]), __float_as_uint(dv1[r]), false, false);
+            su = fmaf(L[ia], __uint_as_float(pu[0]), su);
+            sv = fmaf(L[ia], __uint_as_float(pv[0]), sv);
+            if (ib < K2) {
+                su = fmaf(L[ib], __uint_as_float(pu[1]), su);
+                sv = fmaf(L[ib], __uint_as_float(pv[1]), sv);
+            }
+        }
+    }
+    u = su;
+    v = sv;
+}
+
+template <typename T, int D, int PMAX, int NS, int CF, int KH>
 __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
 {
+    // KH > 0: 2-D FP32 slab contraction on the matrix cores (mma_contract)
+    static_assert(KH == 0 || (std::is_same<T, float>::value && D == 2 && NS == 1 && CF == 0), "matrix-core form");
     extern __shared__ u32x4 lds[];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
     const int NC = a.n_chunks;
     const int64_t nvec = a.chunk_elems * (int64_t)sizeof(T) / 16;   // 16-byte vectors per chunk
     const int64_t cvec = (nvec + 1) & ~(int64_t)1;                   // LDS buffer stride in vectors
     __shared__ long long s_item;
+    // matrix-core form: LDS buffers of 2 PP columns x kMmaRS rows, filled transposed
+    const int mbuf = 2 * a.PP * kMmaRS;
+    int sdst[kMaxStageVec];
+    if constexpr (KH > 0) {
+        float *ldsf = (float *)lds;
+        for (int i = tid; i < 2 * mbuf; i += nthr) ldsf[i] = 0.f;
+        const int rowvec = a.PP >> 1;   // 16-byte vectors per slab row [u: PP][v: PP]
+#pragma unroll
+        for (int k = 0; k < kMaxStageVec; ++k) {
+            const int vv = tid + k * nthr;
+            sdst[k] = vv / rowvec + 4 * (vv % rowvec) * kMmaRS;
+        }
+    }
     cptr<GroupDesc> groups = as_const(a.groups);
     cptr<NodeDesc> nodes = as_const(a.nodes);
     const int64_t total = a.batch_prefix[a.n_groups];
@@ -870,7 +958,18 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
 #pragma unroll
             for (int k = 0; k < kMaxStageVec; ++k) {
                 const int64_t v = tid + (int64_t)k * nthr;
-                if (v < nvec) lds[v] = src[v];
+                if (v < nvec) {
+                    if constexpr (KH > 0) {
+                        const u32x4 w4 = src[v];
+                        float *dst = (float *)lds + sdst[k];
+                        dst[0] = __uint_as_float(w4.x);
+                        dst[kMmaRS] = __uint_as_float(w4.y);
+                        dst[2 * kMmaRS] = __uint_as_float(w4.z);
+                        dst[3 * kMmaRS] = __uint_as_float(w4.w);
+                    } else {
+                        lds[v] = src[v];
+                    }
+                }
             }
         }
         __syncthreads();
@@ -957,7 +1056,40 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
             // ---- residual at X_q, time tau_q = t_{n,l} - q Delta: the slab of step q
             // streams through LDS in NC chunks (double buffered along the chunk sequence)
             const bool wave_live = __ballot(any_live) != 0ull;
-            T Ll[NS][PMAX], u[NS], v[NS];
+            T u[NS], v[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) { u[s] = (T)0; v[s] = (T)0; }
+            if constexpr (KH > 0) {
+                // whole slab per step: stage step q+1 while the matrix cores contract step q
+                const int buf = (q - q0) & 1;
+                const bool has_next = q + 1 < q1;
+                if (has_next) {
+                    const u32x4 *src = (const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride);
+#pragma unroll
+                    for (int k = 0; k < kMaxStageVec; ++k) {
+                        const int64_t vv = tid + (int64_t)k * nthr;
+                        if (vv < nvec) stage[k] = src[vv];
+                    }
+                }
+                if (wave_live)
+                    mma_contract<KH>((const float *)lds + buf * mbuf, a.P, a.PP, (float)X[0][0], (float)X[0][1], lane,
+                                     u[0], v[0]);
+                if (has_next) {
+                    float *dstb = (float *)lds + (buf ^ 1) * mbuf;
+#pragma unroll
+                    for (int k = 0; k < kMaxStageVec; ++k) {
+                        const int64_t vv = tid + (int64_t)k * nthr;
+                        if (vv < nvec) {
+                            float *dst = dstb + sdst[k];
+                            dst[0] = __uint_as_float(stage[k].x);
+                            dst[kMmaRS] = __uint_as_float(stage[k].y);
+                            dst[2 * kMmaRS] = __uint_as_float(stage[k].z);
+                            dst[3 * kMmaRS] = __uint_as_float(stage[k].w);
+                        }
+                    }
+                }
+            } else {
+            T Ll[NS][PMAX];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const T x = X[s][D - 1];
@@ -966,8 +1098,6 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
 #pragma unroll
                 for (int k = 1; k + 1 < PMAX; ++k)
                     Ll[s][k + 1] = (T)((2.0 * k + 1.0) / (k + 1.0)) * x * Ll[s][k] - (T)(k / (k + 1.0)) * Ll[s][k - 1];
-                u[s] = (T)0;
-                v[s] = (T)0;
             }
             for (int c = 0; c < NC; ++c) {
                 const int64_t tseq = (int64_t)(q - q0) * NC + c;
@@ -1018,6 +1148,7 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
                     }
                 }
                 if (c + 1 < NC) __syncthreads();
+            }
             }
             if (wave_live) {
                 const T tau = (T)(t_prev + (span - (double)q * ddelta));
@@ -1083,8 +1214,8 @@ static hipError_t adv_cf(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, 
     // two or three fixed dimensions for d = 4, 5
     constexpr int C0 = D <= 3 ? 0 : D - 3;
     constexpr int C1 = D <= 1 ? 0 : (D <= 3 ? 1 : D - 2);
-    if (a.cf == C0) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C0>), grid, block, lds, s, a); return hipGetLastError(); }
-    if (a.cf == C1) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C1>), grid, block, lds, s, a); return hipGetLastError(); }
+    if (a.cf == C0) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C0, 0>), grid, block, lds, s, a); return hipGetLastError(); }
+    if (a.cf == C1) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C1, 0>), grid, block, lds, s, a); return hipGetLastError(); }
     return hipErrorInvalidValue;
 }
 
@@ -1128,10 +1259,33 @@ static hipError_t adv_d(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_
     return hipErrorInvalidValue;
 }
 
+template <int KH>
+static hipError_t adv_mma(const RoundArgs &a, int kh, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    if constexpr (KH > 16) {
+        return hipErrorInvalidValue;
+    } else {
+        if (kh != KH) return adv_mma<KH + 1>(a, kh, grid, block, lds, s);
+        hipLaunchKernelGGL((advance_kernel<float, 2, 2 * KH, 1, 0, KH>), grid, block, lds, s, a);
+        return hipGetLastError();
+    }
+}
+
+bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane)
+{
+    return fp32 && dim == 2 && P >= 3 && P <= 32 && cf == 0 && samples_per_lane == 1;
+}
+
+size_t advance_mma_lds_bytes(int PP) { return (size_t)2 * 2 * PP * kMmaRS * sizeof(float); }
+
 hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
-                          size_t lds_bytes, hipStream_t s)
+                          size_t lds_bytes, int mma, hipStream_t s)
 {
     dim3 block(64 * waves_per_block), grid(blocks);
+    if (mma) {
+        if (!advance_mma_eligible(fp32, a.phys.dim, a.P, a.cf, samples_per_lane)) return hipErrorInvalidValue;
+        return adv_mma<2>(a, (a.P + 1) / 2, grid, block, lds_bytes, s);
+    }
     return fp32 ? adv_d<float>(a, samples_per_lane, grid, block, lds_bytes, s)
                 : adv_d<double>(a, samples_per_lane, grid, block, lds_bytes, s);
 }

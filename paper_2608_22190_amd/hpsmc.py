@@ -81,6 +81,7 @@ _SIGS = {
     "hpsmc_loss_grad_c0": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "hpsmc_set_initial_coeffs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "hpsmc_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
+    "hpsmc_get_option": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int64)]),
     "hpsmc_last_error": (C.c_char_p, []),
 }
 EXPORTED = tuple(_SIGS)
@@ -274,6 +275,11 @@ class Plan:
 
     def hpsmc_set_option(self, name, value):
         _check(lib().hpsmc_set_option(self.h, name.encode(), int(value)), "hpsmc_set_option")
+
+    def hpsmc_get_option(self, name):
+        v = C.c_int64(0)
+        _check(lib().hpsmc_get_option(self.h, name.encode(), C.byref(v)), "hpsmc_get_option")
+        return int(v.value)
 
     # -- gradient
     def hpsmc_set_initial_coeffs(self, c0, stream=None):
