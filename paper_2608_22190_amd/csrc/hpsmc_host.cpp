@@ -647,7 +647,7 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     if (!pick_chunking(plan, nthr, &cf, &chunk_elems, &n_chunks))
         return fail(HPSMC_EINVAL, "slab chunk too large for this block size; use more waves per block");
     const int64_t nvec = chunk_elems * (plan->fp32 ? 4 : 8) / 16;
-    const int mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, ns);
+    const int mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, ns, waves);
     const size_t lds = mma ? advance_mma_lds_bytes(plan->PP) : (size_t)2 * ((nvec + 1) & ~1LL) * 16;
     const int C = plan->round_steps;
     const int R = (set.max_nstar + C - 1) / C;
@@ -1267,7 +1267,7 @@ static std::string tune_key(const hpsmc_plan *plan, int iv, int64_t M)
         if (c != std::string::npos) arch = arch.substr(0, c);
     }
     // plans that may run the matrix-core round kernel tune separately from those that may not
-    const bool mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1);
+    const bool mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
     char buf[256];
     snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
              plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", (long long)M, plan->n_inst, arch.c_str());
@@ -1353,7 +1353,7 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
             int cf, nc;
             int64_t ce;
             if (set.rounds && !pick_chunking(plan, 64 * w, &cf, &ce, &nc)) continue;
-            for (int b : {2, 4, 8}) cands.push_back(hpsmc_launch{nsv[a], w, b, plan->round_steps});
+            for (int b : {2, 3, 4, 8}) cands.push_back(hpsmc_launch{nsv[a], w, b, plan->round_steps});
         }
     }
     hipEvent_t e0, e1;
@@ -1494,7 +1494,8 @@ static int mma_active(const hpsmc_plan *plan, int iv)
     int cf, nc;
     int64_t ce;
     if (!pick_chunking(plan, 64 * plan->launch.waves_per_block, &cf, &ce, &nc)) return 0;
-    return advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, plan->launch.samples_per_lane) ? 1 : 0;
+    return advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, plan->launch.samples_per_lane,
+                                plan->launch.waves_per_block) ? 1 : 0;
 }
 
 hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t *value)

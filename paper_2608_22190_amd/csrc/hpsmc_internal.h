@@ -143,8 +143,8 @@ hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t 
 hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
                           size_t lds_bytes, int mma, hipStream_t s);
 // matrix-core form of the round kernel: FP32, d = 2, P <= 32, whole slab per
-// LDS buffer, one path per lane
-bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane);
+// LDS buffer, one path per lane, four waves per block
+bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane, int waves_per_block);
 size_t advance_mma_lds_bytes(int PP);
 hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mcount, double *sums, int first,
                                hipStream_t s);

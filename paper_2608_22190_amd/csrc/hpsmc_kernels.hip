@@ -135,22 +135,80 @@ __device__ __forceinline__ T fprime_of(const Physics &ph, T u)
     return (T)0;
 }
 
-// s = u_t - Lap u - f(u) at the manufactured exact solution
-template <typename T, int D>
-__device__ __forceinline__ T source_of(const Physics &ph, const T (&X)[D], T t)
+// s = u_t - Lap u - f(u) at the manufactured exact solution, split into the
+// factors that depend on time only (the same for every path of a group at one
+// walk step) and the spatial evaluation that combines them.
+template <typename T> struct SrcTime {
+    T a, b;
+};
+
+template <typename T>
+__device__ __forceinline__ SrcTime<T> source_time(const Physics &ph, T t)
+{
+    switch (ph.src_kind) {
+    case 1:
+    case 2:
+        return {m_exp(-t), (T)0};
+    case 3: {
+        const T q = (T)1 + t * t;
+        const T Tt = m_exp(m_cos(t)) / q;
+        return {Tt, Tt * (-m_sin(t) - (T)2 * t / q)};
+    }
+    case 4: {
+        const T c0 = (T)ph.src_param[0], c1 = (T)ph.src_param[1], c2 = (T)ph.src_param[2];
+        return {c0 + c1 * t + c2 * t * t, c1 + (T)2 * c2 * t};
+    }
+    }
+    return {(T)0, (T)0};
+}
+
+__device__ __forceinline__ void m_sincos(double x, double &s, double &c) { sincos(x, &s, &c); }
+__device__ __forceinline__ void m_sincos(float x, float &s, float &c) { sincosf(x, &s, &c); }
+
+// sin and cos of |x| <= 2 by their Maclaurin series in Horner form (terms to
+// x^17/17! and x^18/18!; the truncation error is below 4e-10 there): no range
+// reduction and no branch
+__device__ __forceinline__ void sincos_small(float x, float &s, float &c)
+{
+    const float z = x * x;
+    float ps = (float)(1.0 / 355687428096000.0);         // +1/17!
+    ps = fmaf(ps, z, (float)(-1.0 / 1307674368000.0));   // -1/15!
+    ps = fmaf(ps, z, (float)(1.0 / 6227020800.0));       // +1/13!
+    ps = fmaf(ps, z, (float)(-1.0 / 39916800.0));        // -1/11!
+    ps = fmaf(ps, z, (float)(1.0 / 362880.0));           // +1/9!
+    ps = fmaf(ps, z, (float)(-1.0 / 5040.0));            // -1/7!
+    ps = fmaf(ps, z, (float)(1.0 / 120.0));              // +1/5!
+    ps = fmaf(ps, z, (float)(-1.0 / 6.0));               // -1/3!
+    s = fmaf(ps * z, x, x);
+    float pc = (float)(-1.0 / 6402373705728000.0);      // -1/18!
+    pc = fmaf(pc, z, (float)(1.0 / 20922789888000.0));   // +1/16!
+    pc = fmaf(pc, z, (float)(-1.0 / 87178291200.0));     // -1/14!
+    pc = fmaf(pc, z, (float)(1.0 / 479001600.0));       // +1/12!
+    pc = fmaf(pc, z, (float)(-1.0 / 3628800.0));         // -1/10!
+    pc = fmaf(pc, z, (float)(1.0 / 40320.0));            // +1/8!
+    pc = fmaf(pc, z, (float)(-1.0 / 720.0));             // -1/6!
+    pc = fmaf(pc, z, (float)(1.0 / 24.0));               // +1/4!
+    pc = fmaf(pc, z, -0.5f);                             // -1/2!
+    c = fmaf(pc, z, 1.0f);
+}
+
+// BOUNDED: the point lies in (-1,1)^2 (d = 2, FP32), so sin/cos of x0 + x1 use
+// the branch-free series above
+template <typename T, int D, bool BOUNDED = false>
+__device__ __forceinline__ T source_space(const Physics &ph, const T (&X)[D], SrcTime<T> tf)
 {
     const T pi = (T)3.14159265358979323846;
     T u, ut, lap;
     switch (ph.src_kind) {
     case 1: {
-        T p = m_exp(-t);
+        T p = tf.a;
 #pragma unroll
         for (int i = 0; i < D; ++i) p *= m_sin(pi * X[i]);
         u = p; ut = -p; lap = -(T)D * pi * pi * p;
         break;
     }
     case 2: {
-        T p = m_exp(-t);
+        T p = tf.a;
 #pragma unroll
         for (int i = 0; i < D; ++i) p *= m_cos((T)0.5 * pi * X[i]);
         u = p; ut = -p; lap = (T)(-0.25 * D) * pi * pi * p;
@@ -169,13 +227,14 @@ __device__ __forceinline__ T source_of(const Physics &ph, const T (&X)[D], T t)
             lapa += (T)-2 * rest;
             grada += (T)-2 * X[i] * rest;
         }
-        const T S = m_sin(sig), C = m_cos(sig);
-        const T q = (T)1 + t * t;
-        const T Tt = m_exp(m_cos(t)) / q;
-        const T Tp = Tt * (-m_sin(t) - (T)2 * t / q);
-        u = a * S * Tt;
-        ut = a * S * Tp;
-        lap = Tt * (S * lapa + (T)2 * C * grada - (T)D * a * S);
+        T S, C;
+        if constexpr (BOUNDED && D == 2 && std::is_same<T, float>::value)
+            sincos_small(sig, S, C);
+        else
+            m_sincos(sig, S, C);
+        u = a * S * tf.a;
+        ut = a * S * tf.b;
+        lap = tf.a * (S * lapa + (T)2 * C * grada - (T)D * a * S);
         break;
     }
     case 4: {
@@ -190,15 +249,19 @@ __device__ __forceinline__ T source_of(const Physics &ph, const T (&X)[D], T t)
             for (int m = 0; m < D; ++m) if (m != i) rest *= om[m];
             lapa += (T)-2 * rest;
         }
-        const T c0 = (T)ph.src_param[0], c1 = (T)ph.src_param[1], c2 = (T)ph.src_param[2];
-        const T g = c0 + c1 * t + c2 * t * t, gp = c1 + (T)2 * c2 * t;
-        u = a * g; ut = a * gp; lap = lapa * g;
+        u = a * tf.a; ut = a * tf.b; lap = lapa * tf.a;
         break;
     }
     default:
         return (T)0;
     }
     return ut - lap - f_of<T>(ph, u);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T source_of(const Physics &ph, const T (&X)[D], T t)
+{
+    return source_space<T, D>(ph, X, source_time<T>(ph, t));
 }
 
 // ---------------------------------------------------------------------------
@@ -815,6 +878,15 @@ __device__ __forceinline__ void mma_contract(const float *Sb, int P, int PP, flo
 {
     static_assert(KH >= 2 && KH <= 16, "one 32-row tile, at least 4 modes");
     constexpr int K2 = 2 * KH;
+    // A operands first: the LDS reads overlap the recurrences below
+    const float *Au = Sb + (lane >> 5) * KH * kMmaRS + (lane & 31);
+    const float *Av = Au + PP * kMmaRS;
+    float au[KH], av[KH];
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) {
+        au[kk] = Au[kk * kMmaRS];
+        av[kk] = Av[kk * kMmaRS];
+    }
     float L[K2];
     L[0] = 1.f;
     L[1] = x1;
@@ -829,16 +901,13 @@ __device__ __forceinline__ void mma_contract(const float *Sb, int P, int PP, flo
         b0[kk] = __uint_as_float(r[0]);   // paths 0-31: lanes 0-31 modes kk, lanes 32-63 modes KH + kk
         b1[kk] = __uint_as_float(r[1]);   // paths 32-63, same split
     }
-    const float *Au = Sb + (lane >> 5) * KH * kMmaRS + (lane & 31);
-    const float *Av = Au + PP * kMmaRS;
     f32x16 du0 = {}, dv0 = {}, du1 = {}, dv1 = {};
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
-        const float au = Au[kk * kMmaRS], av = Av[kk * kMmaRS];
-        du0 = __builtin_amdgcn_mfma_f32_32x32x2f32(au, b0[kk], du0, 0, 0, 0);
-        dv0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0[kk], dv0, 0, 0, 0);
-        du1 = __builtin_amdgcn_mfma_f32_32x32x2f32(au, b1[kk], du1, 0, 0, 0);
-        dv1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1[kk], dv1, 0, 0, 0);
+        du0 = __builtin_amdgcn_mfma_f32_32x32x2f32(au[kk], b0[kk], du0, 0, 0, 0);
+        dv0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b0[kk], dv0, 0, 0, 0);
+        du1 = __builtin_amdgcn_mfma_f32_32x32x2f32(au[kk], b1[kk], du1, 0, 0, 0);
+        dv1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b1[kk], dv1, 0, 0, 0);
     }
     // Legendre values in x0 (rows >= P of T are zero)
     L[1] = x0;
@@ -865,25 +934,28 @@ __device__ __forceinline__ void mma_contract(const float *Sb, int P, int PP, flo
 }
 
 template <typename T, int D, int PMAX, int NS, int CF, int KH>
-__global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
+__device__ __forceinline__ void advance_body(const RoundArgs &a)
 {
-    // KH > 0: 2-D FP32 slab contraction on the matrix cores (mma_contract)
+    // KH > 0: 2-D FP32 slab contraction on the matrix cores (mma_contract),
+    // 256 threads per block
     static_assert(KH == 0 || (std::is_same<T, float>::value && D == 2 && NS == 1 && CF == 0), "matrix-core form");
+    constexpr int NSTG = KH > 0 ? 2 : kMaxStageVec;   // P <= 32: at most 512 vectors for 256 threads
     extern __shared__ u32x4 lds[];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
     const int NC = a.n_chunks;
     const int64_t nvec = a.chunk_elems * (int64_t)sizeof(T) / 16;   // 16-byte vectors per chunk
     const int64_t cvec = (nvec + 1) & ~(int64_t)1;                   // LDS buffer stride in vectors
     __shared__ long long s_item;
+    __shared__ SrcTime<T> s_tf[256];   // source time factors of a window of blockDim.x steps
     // matrix-core form: LDS buffers of 2 PP columns x kMmaRS rows, filled transposed
     const int mbuf = 2 * a.PP * kMmaRS;
-    int sdst[kMaxStageVec];
+    int sdst[NSTG];
     if constexpr (KH > 0) {
         float *ldsf = (float *)lds;
         for (int i = tid; i < 2 * mbuf; i += nthr) ldsf[i] = 0.f;
         const int rowvec = a.PP >> 1;   // 16-byte vectors per slab row [u: PP][v: PP]
 #pragma unroll
-        for (int k = 0; k < kMaxStageVec; ++k) {
+        for (int k = 0; k < NSTG; ++k) {
             const int vv = tid + k * nthr;
             sdst[k] = vv / rowvec + 4 * (vv % rowvec) * kMmaRS;
         }
@@ -951,12 +1023,19 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
             }
         }
 
+        // ---- source time factors of steps [q0, q0 + nthr), one per thread
+        auto fill_time = [&](int qs) {
+            const int qq = qs + tid;
+            if (qq < q1) s_tf[tid] = source_time<T>(a.phys, (T)(t_prev + (span - (double)qq * ddelta)));
+        };
+        fill_time(q0);
+
         // ---- first chunk of the first step's slab into LDS buffer 0
-        u32x4 stage[kMaxStageVec];
+        u32x4 stage[NSTG];
         {
             const u32x4 *src = (const u32x4 *)(gtab + (int64_t)q0 * a.slab_stride);
 #pragma unroll
-            for (int k = 0; k < kMaxStageVec; ++k) {
+            for (int k = 0; k < NSTG; ++k) {
                 const int64_t v = tid + (int64_t)k * nthr;
                 if (v < nvec) {
                     if constexpr (KH > 0) {
@@ -975,8 +1054,13 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
         __syncthreads();
 
         uint32_t w[NS][4];
-        int q = q0;
-        for (; q < q1; ++q) {
+        int q = q0, tslot = 0;
+        for (; q < q1; ++q, ++tslot) {
+            if (tslot == nthr) {   // the previous step's barrier ended every read of the old window
+                tslot = 0;
+                fill_time(q);
+                __syncthreads();
+            }
             // ---- directions (Philox words refreshed on block boundaries of the counter)
             T dir[NS][D];
             if constexpr (D == 1) {
@@ -1066,7 +1150,7 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
                 if (has_next) {
                     const u32x4 *src = (const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride);
 #pragma unroll
-                    for (int k = 0; k < kMaxStageVec; ++k) {
+                    for (int k = 0; k < NSTG; ++k) {
                         const int64_t vv = tid + (int64_t)k * nthr;
                         if (vv < nvec) stage[k] = src[vv];
                     }
@@ -1077,7 +1161,7 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
                 if (has_next) {
                     float *dstb = (float *)lds + (buf ^ 1) * mbuf;
 #pragma unroll
-                    for (int k = 0; k < kMaxStageVec; ++k) {
+                    for (int k = 0; k < NSTG; ++k) {
                         const int64_t vv = tid + (int64_t)k * nthr;
                         if (vv < nvec) {
                             float *dst = dstb + sdst[k];
@@ -1108,7 +1192,7 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
                 if (has_next) {
                     const u32x4 *src = (const u32x4 *)(gtab + (int64_t)qn * a.slab_stride + (int64_t)cn * a.chunk_elems);
 #pragma unroll
-                    for (int k = 0; k < kMaxStageVec; ++k) {
+                    for (int k = 0; k < NSTG; ++k) {
                         const int64_t vv = tid + (int64_t)k * nthr;
                         if (vv < nvec) stage[k] = src[vv];
                     }
@@ -1142,7 +1226,7 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
                 if (has_next) {
                     u32x4 *dst = lds + (int64_t)(buf ^ 1) * cvec;
 #pragma unroll
-                    for (int k = 0; k < kMaxStageVec; ++k) {
+                    for (int k = 0; k < NSTG; ++k) {
                         const int64_t vv = tid + (int64_t)k * nthr;
                         if (vv < nvec) dst[vv] = stage[k];
                     }
@@ -1151,11 +1235,11 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
             }
             }
             if (wave_live) {
-                const T tau = (T)(t_prev + (span - (double)q * ddelta));
+                const SrcTime<T> tf = s_tf[tslot];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (alive[s]) {
-                        const T r = f_of<T>(a.phys, u[s]) + source_of<T, D>(a.phys, X[s], tau) + v[s];
+                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D, (KH > 0)>(a.phys, X[s], tf) + v[s];
                         const T y = delta * r;
                         if constexpr (sizeof(T) == 4) {
                             const T yc = y - comp[s];
@@ -1207,6 +1291,20 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
     }
 }
 
+template <typename T, int D, int PMAX, int NS, int CF>
+__global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
+{
+    advance_body<T, D, PMAX, NS, CF, 0>(a);
+}
+
+// the matrix-core form holds 64 accumulators per lane; three waves per SIMD
+// keep one wave's vector work beside another's matrix work
+template <int KH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) advance_mma_kernel(RoundArgs a)
+{
+    advance_body<float, 2, 2 * KH, 1, 0, KH>(a);
+}
+
 template <typename T, int D, int PMAX, int NS>
 static hipError_t adv_cf(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
 {
@@ -1214,8 +1312,8 @@ static hipError_t adv_cf(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, 
     // two or three fixed dimensions for d = 4, 5
     constexpr int C0 = D <= 3 ? 0 : D - 3;
     constexpr int C1 = D <= 1 ? 0 : (D <= 3 ? 1 : D - 2);
-    if (a.cf == C0) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C0, 0>), grid, block, lds, s, a); return hipGetLastError(); }
-    if (a.cf == C1) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C1, 0>), grid, block, lds, s, a); return hipGetLastError(); }
+    if (a.cf == C0) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C0>), grid, block, lds, s, a); return hipGetLastError(); }
+    if (a.cf == C1) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C1>), grid, block, lds, s, a); return hipGetLastError(); }
     return hipErrorInvalidValue;
 }
 
@@ -1266,14 +1364,14 @@ static hipError_t adv_mma(const RoundArgs &a, int kh, dim3 grid, dim3 block, siz
         return hipErrorInvalidValue;
     } else {
         if (kh != KH) return adv_mma<KH + 1>(a, kh, grid, block, lds, s);
-        hipLaunchKernelGGL((advance_kernel<float, 2, 2 * KH, 1, 0, KH>), grid, block, lds, s, a);
+        hipLaunchKernelGGL((advance_mma_kernel<KH>), grid, block, lds, s, a);
         return hipGetLastError();
     }
 }
 
-bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane)
+bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane, int waves_per_block)
 {
-    return fp32 && dim == 2 && P >= 3 && P <= 32 && cf == 0 && samples_per_lane == 1;
+    return fp32 && dim == 2 && P >= 3 && P <= 32 && cf == 0 && samples_per_lane == 1 && waves_per_block == 4;
 }
 
 size_t advance_mma_lds_bytes(int PP) { return (size_t)2 * 2 * PP * kMmaRS * sizeof(float); }
@@ -1283,7 +1381,8 @@ hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, in
 {
     dim3 block(64 * waves_per_block), grid(blocks);
     if (mma) {
-        if (!advance_mma_eligible(fp32, a.phys.dim, a.P, a.cf, samples_per_lane)) return hipErrorInvalidValue;
+        if (!advance_mma_eligible(fp32, a.phys.dim, a.P, a.cf, samples_per_lane, waves_per_block))
+            return hipErrorInvalidValue;
         return adv_mma<2>(a, (a.P + 1) / 2, grid, block, lds_bytes, s);
     }
     return fp32 ? adv_d<float>(a, samples_per_lane, grid, block, lds_bytes, s)
