@@ -411,12 +411,15 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     const int d = plan->d, T = (int)(plan->fp32 ? sizeof(float) : sizeof(double));
     set.ivs = ivs;
     set.host.clear();
-    std::vector<int64_t> coef_off, slab_off;
+    std::vector<int64_t> coef_off, slab_off, slab_off_mma;
     std::vector<double> span, delta, h2;
     std::vector<int32_t> nst, deg;
     const int64_t rows = ipow(plan->P, d - 1);
     const int64_t stride = rows * 2 * plan->PP;
-    int64_t slab_pos = 0, out = 0;
+    // plans the matrix-core round kernel can serve also get offsets in its slab layout
+    const bool mma_ok = advance_mma_eligible(plan->fp32, d, plan->P, 0, 1, 4);
+    const int64_t mstride = mma_slab_elems(plan->PP);
+    int64_t slab_pos = 0, slab_pos_mma = 0, out = 0;
     // canonical output order: [iv][inst][node id]
     for (int32_t iv : ivs) {
         const int M = plan->degree[iv];
@@ -431,6 +434,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
                 const int g = (int)coef_off.size();
                 coef_off.push_back(plan->c_off[iv] + (int64_t)inst * plan->psp * (M + 1));
                 slab_off.push_back(slab_pos);
+                slab_off_mma.push_back(slab_pos_mma);
                 span.push_back(sp);
                 delta.push_back(dl);
                 h2.push_back(2.0 / h);
@@ -454,6 +458,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
                     set.host.push_back(nd);
                 }
                 slab_pos += (int64_t)ns * stride;
+                if (mma_ok) slab_pos_mma += (int64_t)ns * mstride;
             }
         }
         out += (int64_t)plan->n_inst * plan->nsp * M;
@@ -478,6 +483,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
             gd.node_count = (int32_t)per;
             gd.t_prev = set.host[g * per].t_prev;
             gd.slab = slab_off[g];
+            gd.slab_mma = slab_off_mma[g];
             gd.nstar = nst[g];
             gd.c3 = set.host[g * per].c3;
             set.ghost.push_back(gd);
@@ -490,11 +496,11 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     }
     set.n_groups = (int32_t)coef_off.size();
     set.max_nstar = *std::max_element(nst.begin(), nst.end());
-    set.slab_elems = slab_pos;
+    set.slab_elems = std::max(slab_pos, slab_pos_mma);   // one layout is live at a time
     hpsmc_status st;
     if ((st = dalloc(plan, (void **)&set.dev, sizeof(NodeDesc) * set.n))) return st;
     const size_t G = set.n_groups;
-    const size_t gbytes = G * (2 * sizeof(int64_t) + 3 * sizeof(double) + 2 * sizeof(int32_t));
+    const size_t gbytes = G * (3 * sizeof(int64_t) + 3 * sizeof(double) + 2 * sizeof(int32_t));
     if ((st = dalloc(plan, &set.group_mem, gbytes))) return st;
     std::vector<char> gh(gbytes);
     char *p = gh.data();
@@ -502,6 +508,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     put(coef_off.data(), G * 8); put(slab_off.data(), G * 8);
     put(span.data(), G * 8); put(delta.data(), G * 8); put(h2.data(), G * 8);
     put(nst.data(), G * 4); put(deg.data(), G * 4);
+    put(slab_off_mma.data(), G * 8);
     if (hipMemcpy(set.group_mem, gh.data(), gbytes, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(set.dev, set.host.data(), sizeof(NodeDesc) * set.n, hipMemcpyHostToDevice) != hipSuccess)
         return fail(HPSMC_EDEVICE, "upload of node descriptors failed");
@@ -516,6 +523,9 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     sa.h2 = (const double *)(gb + G * 32);
     sa.nstar = (const int32_t *)(gb + G * 40);
     sa.deg = (const int32_t *)(gb + G * 44);
+    sa.slab_off_mma = mma_ok ? (const int64_t *)(gb + G * 48) : nullptr;
+    sa.mma_stride = mstride;
+    sa.layout = 0;
     sa.n_groups = set.n_groups;
     sa.P = plan->P;
     sa.PP = plan->PP;
@@ -636,6 +646,18 @@ static Physics physics_of(const hpsmc_plan *plan)
     return ph;
 }
 
+// Whether the rounds of this set run the matrix-core kernel with the current
+// launch shape (its slabs are then written in the matrix-core layout).
+static int set_uses_mma(const hpsmc_plan *plan, const NodeSet &set)
+{
+    if (!set.rounds || !plan->sample_mma || !set.slab.slab_off_mma) return 0;
+    int cf, nc;
+    int64_t ce;
+    if (!pick_chunking(plan, 64 * plan->launch.waves_per_block, &cf, &ce, &nc)) return 0;
+    return advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, plan->launch.samples_per_lane,
+                                plan->launch.waves_per_block) ? 1 : 0;
+}
+
 // Round-based sampling of one node set: slices of samples, each advanced in
 // rounds of round_steps walk steps with compaction between rounds.
 static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
@@ -647,7 +669,7 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     if (!pick_chunking(plan, nthr, &cf, &chunk_elems, &n_chunks))
         return fail(HPSMC_EINVAL, "slab chunk too large for this block size; use more waves per block");
     const int64_t nvec = chunk_elems * (plan->fp32 ? 4 : 8) / 16;
-    const int mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, ns, waves);
+    const int mma = set_uses_mma(plan, set);
     const size_t lds = mma ? advance_mma_lds_bytes(plan->PP) : (size_t)2 * ((nvec + 1) & ~1LL) * 16;
     const int C = plan->round_steps;
     const int R = (set.max_nstar + C - 1) / C;
@@ -669,7 +691,7 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     a.key0 = (uint32_t)plan->pb.seed;
     a.key1 = (uint32_t)(plan->pb.seed >> 32);
     a.slab_table = plan->slab_table;
-    a.slab_stride = set.slab.slab_stride;
+    a.slab_stride = mma ? set.slab.mma_stride : set.slab.slab_stride;
     a.work = plan->counters;
     a.stats = plan->counters + 1;
     a.phys = physics_of(plan);
@@ -713,6 +735,7 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
     const int ns = plan->launch.samples_per_lane;
     SlabArgs sa = set.slab;
     sa.slab_table = plan->slab_table;
+    sa.layout = set_uses_mma(plan, set);
     hpsmc_plan::EvPair *es = next_pair(plan->ev_slab, plan->n_slab);
     if (es) HIP_TRY(hipEventRecord(es->a, s));
     HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
@@ -1349,6 +1372,11 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     for (int a = 0; a < 3; ++a) {
         if (nsv[a] == 4 && plan->d > 2) continue;
         for (int w : {2, 4}) {
+            // two-wave blocks of the matrix-core kernel: 1, 1.5, 2, 3, 4 waves per SIMD
+            if (w == 2 && nsv[a] == 1 && plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 2)) {
+                for (int b : {2, 3, 4, 6, 8}) cands.push_back(hpsmc_launch{1, 2, b, plan->round_steps});
+                continue;
+            }
             // the LDS-staged slab chunk must fit 4 vectors per thread
             int cf, nc;
             int64_t ce;
@@ -1489,13 +1517,7 @@ hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value)
 // whether the round kernel of interval iv runs on the matrix cores with the current launch shape
 static int mma_active(const hpsmc_plan *plan, int iv)
 {
-    const NodeSet &set = plan->pb.schedule == HPSMC_SEQUENTIAL ? plan->sets[iv] : plan->sets[0];
-    if (!set.rounds || !plan->sample_mma) return 0;
-    int cf, nc;
-    int64_t ce;
-    if (!pick_chunking(plan, 64 * plan->launch.waves_per_block, &cf, &ce, &nc)) return 0;
-    return advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, plan->launch.samples_per_lane,
-                                plan->launch.waves_per_block) ? 1 : 0;
+    return set_uses_mma(plan, plan->pb.schedule == HPSMC_SEQUENTIAL ? plan->sets[iv] : plan->sets[0]);
 }
 
 hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t *value)

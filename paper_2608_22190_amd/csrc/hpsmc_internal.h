@@ -31,7 +31,8 @@ struct NodeDesc {
 // Delta and J, so a block can advance any mix of their paths in lockstep.
 struct GroupDesc {
     double delta, jump, span, t_prev;
-    int64_t slab;          // offset of the q = 0 slab in the slab table
+    int64_t slab;          // offset of the q = 0 slab in the slab table (row layout)
+    int64_t slab_mma;      // the same in the matrix-core layout (d = 2, FP32)
     int64_t path_off;      // first path slot of the group in the state buffers
     int32_t nstar;
     int32_t node_begin;    // the group's nodes are [node_begin, node_begin + node_count)
@@ -110,7 +111,10 @@ struct AdjointArgs {
 struct SlabArgs {
     const double *cu, *cv;       // Legendre tensors, blocks of [P^d][T1]
     const int64_t *coef_off;     // per group: offset of its (inst, iv) coefficient block
-    const int64_t *slab_off;     // per group: offset of its q = 0 slab in the table
+    const int64_t *slab_off;     // per group: offset of its q = 0 slab in the table (row layout)
+    const int64_t *slab_off_mma; // the same in the matrix-core layout (null when not available)
+    int64_t mma_stride;          // elements per slab in the matrix-core layout
+    int32_t layout;              // 0: rows [k0][u: PP][v: PP]; 1: matrix-core layout
     const double *span;          // per group: t_{n,l} - t_{n-1}
     const double *delta;         // per group: Delta_{n,l}
     const double *h2;            // per group: 2 / h_n
@@ -143,9 +147,13 @@ hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t 
 hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
                           size_t lds_bytes, int mma, hipStream_t s);
 // matrix-core form of the round kernel: FP32, d = 2, P <= 32, whole slab per
-// LDS buffer, one path per lane, four waves per block
+// LDS buffer, one path per lane
 bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane, int waves_per_block);
 size_t advance_mma_lds_bytes(int PP);
+// matrix-core slab layout: 2 PP columns (u modes k1, then v modes k1) of
+// kMmaRows rows k0 (zeros past P), stored as the kernel's LDS image
+constexpr int kMmaRows = 33;
+inline int64_t mma_slab_elems(int PP) { return (int64_t)2 * PP * kMmaRows; }
 hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mcount, double *sums, int first,
                                hipStream_t s);
 size_t path_state_bytes(int fp32, int dim);

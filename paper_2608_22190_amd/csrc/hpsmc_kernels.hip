@@ -626,19 +626,32 @@ __global__ void slab_kernel(SlabArgs a)
     const int g = blockIdx.y;
     const int nstar = a.nstar[g];
     const int T1 = a.deg[g] + 1;
-    const int64_t total = (int64_t)nstar * a.slab_stride;
+    const bool mma = a.layout == 1;
+    const int64_t stride = mma ? a.mma_stride : a.slab_stride;
+    const int64_t base = mma ? a.slab_off_mma[g] : a.slab_off[g];
+    const int64_t total = (int64_t)nstar * stride;
     T *table = (T *)a.slab_table;
     const double *cu = a.cu + a.coef_off[g], *cv = a.cv + a.coef_off[g];
     const double span = a.span[g], delta = a.delta[g], h2 = a.h2[g];
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = idx / a.slab_stride;
-        const int64_t e = idx - q * a.slab_stride;
-        const int64_t row = e / (2 * a.PP);
-        const int rem = (int)(e - row * 2 * a.PP);
-        const int uv = rem / a.PP, kl = rem - uv * a.PP;
+        const int64_t q = idx / stride;
+        const int64_t e = idx - q * stride;
+        int64_t row;
+        int uv, kl;
+        if (mma) {   // column c = uv * PP + k1 of kMmaRows rows k0
+            const int c = (int)(e / kMmaRows);
+            row = e - (int64_t)c * kMmaRows;
+            uv = c / a.PP;
+            kl = c - uv * a.PP;
+        } else {
+            row = e / (2 * a.PP);
+            const int rem = (int)(e - row * 2 * a.PP);
+            uv = rem / a.PP;
+            kl = rem - uv * a.PP;
+        }
         double val = 0.0;
-        if (kl < a.P) {
+        if (kl < a.P && row < a.rows) {
             const double *c = (uv ? cv : cu) + (row * a.P + kl) * T1;
             const double xi = h2 * (span - (double)q * delta) - 1.0;
             double lp = 0.0, lc = 1.0;
@@ -649,14 +662,14 @@ __global__ void slab_kernel(SlabArgs a)
                 lc = nx;
             }
         }
-        table[a.slab_off[g] + q * a.slab_stride + e] = (T)val;
+        table[base + q * stride + e] = (T)val;
     }
 }
 
 hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t s)
 {
     if (a.n_groups <= 0) return hipSuccess;
-    int64_t per = (int64_t)max_nstar * a.slab_stride;
+    int64_t per = (int64_t)max_nstar * (a.layout == 1 ? a.mma_stride : a.slab_stride);
     int64_t bx = (per + 255) / 256;
     if (bx > 16384) bx = 16384;
     dim3 grid((unsigned)bx, (unsigned)a.n_groups);
@@ -854,8 +867,25 @@ hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kMaxStageVec = 4;   // 16-byte slab vectors staged per thread and step
-constexpr int kMmaRS = 33;        // LDS column stride (floats) of the transposed slab: odd, so
+constexpr int kMmaRS = kMmaRows;  // LDS column stride (floats) of the transposed slab: odd, so
                                   // the 32 rows a half-wave reads fall in distinct banks
+
+// Direct global -> LDS copy of a matrix-core slab image (gfx950
+// global_load_lds_dwordx4): lane i of a wave writes its 16 bytes at
+// wave_base + 16 i, so vector v of the image lands at LDS vector v.  The copy
+// completes under vmcnt; mma_stage_wait() precedes the barrier that publishes it.
+__device__ __forceinline__ void mma_stage(const u32x4 *src, u32x4 *dst, int nvec, int tid, int nthr)
+{
+    const int wbase = tid & ~63;
+    for (int k = 0; k * nthr < nvec; ++k) {
+        const int v = k * nthr + tid;
+        if (v < nvec)
+            __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)(src + v),
+                                             (void __attribute__((address_space(3))) *)(dst + k * nthr + wbase),
+                                             16, 0, 0);
+    }
+}
+__device__ __forceinline__ void mma_stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // ---------------------------------------------------------------------------
 // Matrix-core contraction of one step's 2-D slab for the 64 paths of a wave.
@@ -872,21 +902,13 @@ constexpr int kMmaRS = 33;        // LDS column stride (floats) of the transpose
 // Sb: slab in LDS, transposed: Sb[c * kMmaRS + k0], c = k1 (u) or PP + k1 (v);
 // rows k0 in [P, 32) hold zeros, columns k1 in [P, PP) the slab's zero padding.
 // ---------------------------------------------------------------------------
+
+// B operands: Legendre values in x1 of the wave's 64 points
 template <int KH>
-__device__ __forceinline__ void mma_contract(const float *Sb, int P, int PP, float x0, float x1, int lane,
-                                             float &u, float &v)
+__device__ __forceinline__ void mma_operands(float x1, int P, float (&b0)[KH], float (&b1)[KH])
 {
     static_assert(KH >= 2 && KH <= 16, "one 32-row tile, at least 4 modes");
     constexpr int K2 = 2 * KH;
-    // A operands first: the LDS reads overlap the recurrences below
-    const float *Au = Sb + (lane >> 5) * KH * kMmaRS + (lane & 31);
-    const float *Av = Au + PP * kMmaRS;
-    float au[KH], av[KH];
-#pragma unroll
-    for (int kk = 0; kk < KH; ++kk) {
-        au[kk] = Au[kk * kMmaRS];
-        av[kk] = Av[kk * kMmaRS];
-    }
     float L[K2];
     L[0] = 1.f;
     L[1] = x1;
@@ -894,38 +916,65 @@ __device__ __forceinline__ void mma_contract(const float *Sb, int P, int PP, flo
     for (int k = 1; k + 1 < K2; ++k)
         L[k + 1] = (float)((2.0 * k + 1.0) / (k + 1.0)) * x1 * L[k] - (float)(k / (k + 1.0)) * L[k - 1];
     if (P < K2) L[K2 - 1] = 0.f;   // odd P: mode P does not exist
-    float b0[KH], b1[KH];
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
         const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(L[kk]), __float_as_uint(L[KH + kk]), false, false);
         b0[kk] = __uint_as_float(r[0]);   // paths 0-31: lanes 0-31 modes kk, lanes 32-63 modes KH + kk
         b1[kk] = __uint_as_float(r[1]);   // paths 32-63, same split
     }
-    f32x16 du0 = {}, dv0 = {}, du1 = {}, dv1 = {};
+}
+
+// the four products (u and v tables, both path halves)
+template <int KH>
+__device__ __forceinline__ void mma_issue(const float *Sb, int PP, int lane, const float (&b0)[KH],
+                                          const float (&b1)[KH], f32x16 &du0, f32x16 &dv0, f32x16 &du1, f32x16 &dv1)
+{
+    const float *Au = Sb + (lane >> 5) * KH * kMmaRS + (lane & 31);
+    const float *Av = Au + PP * kMmaRS;
+    du0 = f32x16{}; dv0 = f32x16{}; du1 = f32x16{}; dv1 = f32x16{};
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
-        du0 = __builtin_amdgcn_mfma_f32_32x32x2f32(au[kk], b0[kk], du0, 0, 0, 0);
-        dv0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b0[kk], dv0, 0, 0, 0);
-        du1 = __builtin_amdgcn_mfma_f32_32x32x2f32(au[kk], b1[kk], du1, 0, 0, 0);
-        dv1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kk], b1[kk], dv1, 0, 0, 0);
+        const float au = Au[kk * kMmaRS], av = Av[kk * kMmaRS];
+        du0 = __builtin_amdgcn_mfma_f32_32x32x2f32(au, b0[kk], du0, 0, 0, 0);
+        dv0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0[kk], dv0, 0, 0, 0);
+        du1 = __builtin_amdgcn_mfma_f32_32x32x2f32(au, b1[kk], du1, 0, 0, 0);
+        dv1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1[kk], dv1, 0, 0, 0);
     }
-    // Legendre values in x0 (rows >= P of T are zero)
-    L[1] = x0;
+}
+
+// rows back to the owning lane and the contraction with L_{k0}(x0) (rows >= P
+// of T are zero).  Registers r = 4g..4g+3 hold rows 8g..8g+3 (before the swap)
+// and 8g+4..8g+7 (after it): the Legendre values in x0 advance eight at a time.
+template <int KH>
+__device__ __forceinline__ void mma_epilogue(const f32x16 &du0, const f32x16 &dv0, const f32x16 &du1,
+                                             const f32x16 &dv1, float x0, float &u, float &v)
+{
+    constexpr int K2 = 2 * KH;
+    float su = 0.f, sv = 0.f, lp = 0.f, lc = 1.f;
 #pragma unroll
-    for (int k = 1; k + 1 < K2; ++k)
-        L[k + 1] = (float)((2.0 * k + 1.0) / (k + 1.0)) * x0 * L[k] - (float)(k / (k + 1.0)) * L[k - 1];
-    float su = 0.f, sv = 0.f;
+    for (int g = 0; g < 4; ++g) {
+        if (8 * g >= K2) break;
+        float Lb[8];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int ia = 8 * (r / 4) + (r % 4), ib = ia + 4;   // rows held before / after the swap
-        if (ia < K2) {
-            const auto pu = __builtin_amdgcn_permlane32_swap(__float_as_uint(du0[r]), __float_as_uint(du1[r]), false, false);
-            const auto pv = __builtin_amdgcn_permlane32_swap(__float_as_uint(dv0[r]), __float_as_uint(dv1[r]), false, false);
-            su = fmaf(L[ia], __uint_as_float(pu[0]), su);
-            sv = fmaf(L[ia], __uint_as_float(pv[0]), sv);
-            if (ib < K2) {
-                su = fmaf(L[ib], __uint_as_float(pu[1]), su);
-                sv = fmaf(L[ib], __uint_as_float(pv[1]), sv);
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * g + j;
+            Lb[j] = lc;
+            const float nx = (float)((2.0 * k + 1.0) / (k + 1.0)) * x0 * lc - (float)(k / (k + 1.0)) * lp;
+            lp = lc;
+            lc = nx;
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int r = 4 * g + rr, ia = 8 * g + rr, ib = ia + 4;
+            if (ia < K2) {
+                const auto pu = __builtin_amdgcn_permlane32_swap(__float_as_uint(du0[r]), __float_as_uint(du1[r]), false, false);
+                const auto pv = __builtin_amdgcn_permlane32_swap(__float_as_uint(dv0[r]), __float_as_uint(dv1[r]), false, false);
+                su = fmaf(Lb[rr], __uint_as_float(pu[0]), su);
+                sv = fmaf(Lb[rr], __uint_as_float(pv[0]), sv);
+                if (ib < K2) {
+                    su = fmaf(Lb[4 + rr], __uint_as_float(pu[1]), su);
+                    sv = fmaf(Lb[4 + rr], __uint_as_float(pv[1]), sv);
+                }
             }
         }
     }
@@ -933,13 +982,10 @@ __device__ __forceinline__ void mma_contract(const float *Sb, int P, int PP, flo
     v = sv;
 }
 
-template <typename T, int D, int PMAX, int NS, int CF, int KH>
+template <typename T, int D, int PMAX, int NS, int CF>
 __device__ __forceinline__ void advance_body(const RoundArgs &a)
 {
-    // KH > 0: 2-D FP32 slab contraction on the matrix cores (mma_contract),
-    // 256 threads per block
-    static_assert(KH == 0 || (std::is_same<T, float>::value && D == 2 && NS == 1 && CF == 0), "matrix-core form");
-    constexpr int NSTG = KH > 0 ? 2 : kMaxStageVec;   // P <= 32: at most 512 vectors for 256 threads
+    constexpr int NSTG = kMaxStageVec;
     extern __shared__ u32x4 lds[];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
     const int NC = a.n_chunks;
@@ -947,19 +993,6 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
     const int64_t cvec = (nvec + 1) & ~(int64_t)1;                   // LDS buffer stride in vectors
     __shared__ long long s_item;
     __shared__ SrcTime<T> s_tf[256];   // source time factors of a window of blockDim.x steps
-    // matrix-core form: LDS buffers of 2 PP columns x kMmaRS rows, filled transposed
-    const int mbuf = 2 * a.PP * kMmaRS;
-    int sdst[NSTG];
-    if constexpr (KH > 0) {
-        float *ldsf = (float *)lds;
-        for (int i = tid; i < 2 * mbuf; i += nthr) ldsf[i] = 0.f;
-        const int rowvec = a.PP >> 1;   // 16-byte vectors per slab row [u: PP][v: PP]
-#pragma unroll
-        for (int k = 0; k < NSTG; ++k) {
-            const int vv = tid + k * nthr;
-            sdst[k] = vv / rowvec + 4 * (vv % rowvec) * kMmaRS;
-        }
-    }
     cptr<GroupDesc> groups = as_const(a.groups);
     cptr<NodeDesc> nodes = as_const(a.nodes);
     const int64_t total = a.batch_prefix[a.n_groups];
@@ -1037,18 +1070,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
 #pragma unroll
             for (int k = 0; k < NSTG; ++k) {
                 const int64_t v = tid + (int64_t)k * nthr;
-                if (v < nvec) {
-                    if constexpr (KH > 0) {
-                        const u32x4 w4 = src[v];
-                        float *dst = (float *)lds + sdst[k];
-                        dst[0] = __uint_as_float(w4.x);
-                        dst[kMmaRS] = __uint_as_float(w4.y);
-                        dst[2 * kMmaRS] = __uint_as_float(w4.z);
-                        dst[3 * kMmaRS] = __uint_as_float(w4.w);
-                    } else {
-                        lds[v] = src[v];
-                    }
-                }
+                if (v < nvec) lds[v] = src[v];
             }
         }
         __syncthreads();
@@ -1143,36 +1165,6 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
             T u[NS], v[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) { u[s] = (T)0; v[s] = (T)0; }
-            if constexpr (KH > 0) {
-                // whole slab per step: stage step q+1 while the matrix cores contract step q
-                const int buf = (q - q0) & 1;
-                const bool has_next = q + 1 < q1;
-                if (has_next) {
-                    const u32x4 *src = (const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride);
-#pragma unroll
-                    for (int k = 0; k < NSTG; ++k) {
-                        const int64_t vv = tid + (int64_t)k * nthr;
-                        if (vv < nvec) stage[k] = src[vv];
-                    }
-                }
-                if (wave_live)
-                    mma_contract<KH>((const float *)lds + buf * mbuf, a.P, a.PP, (float)X[0][0], (float)X[0][1], lane,
-                                     u[0], v[0]);
-                if (has_next) {
-                    float *dstb = (float *)lds + (buf ^ 1) * mbuf;
-#pragma unroll
-                    for (int k = 0; k < NSTG; ++k) {
-                        const int64_t vv = tid + (int64_t)k * nthr;
-                        if (vv < nvec) {
-                            float *dst = dstb + sdst[k];
-                            dst[0] = __uint_as_float(stage[k].x);
-                            dst[kMmaRS] = __uint_as_float(stage[k].y);
-                            dst[2 * kMmaRS] = __uint_as_float(stage[k].z);
-                            dst[3 * kMmaRS] = __uint_as_float(stage[k].w);
-                        }
-                    }
-                }
-            } else {
             T Ll[NS][PMAX];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -1233,13 +1225,12 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                 }
                 if (c + 1 < NC) __syncthreads();
             }
-            }
             if (wave_live) {
                 const SrcTime<T> tf = s_tf[tslot];
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (alive[s]) {
-                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D, (KH > 0)>(a.phys, X[s], tf) + v[s];
+                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D>(a.phys, X[s], tf) + v[s];
                         const T y = delta * r;
                         if constexpr (sizeof(T) == 4) {
                             const T yc = y - comp[s];
@@ -1294,15 +1285,181 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
 template <typename T, int D, int PMAX, int NS, int CF>
 __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
 {
-    advance_body<T, D, PMAX, NS, CF, 0>(a);
+    advance_body<T, D, PMAX, NS, CF>(a);
 }
 
-// the matrix-core form holds 64 accumulators per lane; three waves per SIMD
-// keep one wave's vector work beside another's matrix work
+// ===========================================================================
+// Round kernel, matrix-core form: d = 2, FP32, one path per lane, the whole
+// slab of a step in LDS (its image copied straight from the table).  The step
+// loop is software-pipelined so that a wave's vector work runs under its own
+// products: at step q the wave issues the 4 KH products of the residual at X_q
+// and meanwhile draws the direction of step q, takes the jump and the exit
+// test (eq. indexL) and forms the operands of the next point; the epilogue
+// then completes u and v, and the residual enters the path sum (eq. interIQ)
+// only for paths whose jump stayed inside -- the same walk, exit steps and
+// quadrature as the vector-unit kernel.
+// ===========================================================================
+template <int KH>
+__device__ __forceinline__ void advance_mma_body(const RoundArgs &a)
+{
+    extern __shared__ u32x4 lds[];
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
+    __shared__ long long s_item;
+    __shared__ SrcTime<float> s_tf[256];   // source time factors of a window of blockDim.x steps
+    const int mbuf = 2 * a.PP * kMmaRS;   // floats per LDS buffer (slab image)
+    const int mvec = mbuf / 4;            // 16-byte vectors per buffer
+    cptr<GroupDesc> groups = as_const(a.groups);
+    cptr<NodeDesc> nodes = as_const(a.nodes);
+    const int64_t total = a.batch_prefix[a.n_groups];
+    unsigned long long evals = 0, slots = 0;
+    using State = PathState<float, 2>;
+    const State *sin = (const State *)a.state_in;
+    State *sout = (State *)a.state_out;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (long long)atomicAdd(a.work, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;
+        int lo = 0, hi = a.n_groups - 1;   // last g with batch_prefix[g] <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.batch_prefix[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const int g = lo;
+        const int64_t b = item - a.batch_prefix[g];
+        cptr<GroupDesc> G = groups + g;
+        const int nstar = G->nstar;
+        const int q0 = a.round * a.steps;
+        const int q1 = min(q0 + a.steps, nstar);
+        const float delta = (float)G->delta, J = (float)G->jump;
+        const double span = G->span, t_prev = G->t_prev, ddelta = G->delta;
+        const uint32_t c3 = G->c3 | (uint32_t)a.tag;
+        const int64_t live = a.round == 0 ? (int64_t)G->node_count * a.mcount : (int64_t)a.live_in[g];
+        const float *gtab = (const float *)a.slab_table + G->slab_mma;
+
+        // ---- this lane's path
+        const int64_t p = b * a.batch + tid;
+        bool alive = p < live;
+        uint32_t node = 0, sample = 0, c0 = 0;
+        float x0 = 0.f, x1 = 0.f, acc = 0.f, comp = 0.f;
+        if (alive) {
+            if (a.round == 0) {
+                node = (uint32_t)(G->node_begin + p / a.mcount);
+                sample = (uint32_t)(a.m0 + p % a.mcount);
+                x0 = (float)nodes[node].x0[0];
+                x1 = (float)nodes[node].x0[1];
+            } else {
+                const State st = sin[G->path_off + p];
+                x0 = st.x[0];
+                x1 = st.x[1];
+                acc = st.acc;
+                comp = st.comp;
+                node = st.node;
+                sample = st.sample;
+            }
+            c0 = nodes[node].c0;
+        }
+        auto fill_time = [&](int qs) {
+            const int qq = qs + tid;
+            if (qq < q1) s_tf[tid] = source_time<float>(a.phys, (float)(t_prev + (span - (double)qq * ddelta)));
+        };
+        fill_time(q0);
+        mma_stage((const u32x4 *)(gtab + (int64_t)q0 * a.slab_stride), lds, mvec, tid, nthr);
+        float b0[KH], b1[KH];
+        mma_operands<KH>(x1, a.P, b0, b1);
+        mma_stage_wait();
+        __syncthreads();
+
+        uint32_t w[4];
+        int q = q0, tslot = 0;
+        for (; q < q1; ++q, ++tslot) {
+            if (tslot == nthr) {   // the previous step's barrier ended every read of the old window
+                tslot = 0;
+                fill_time(q);
+                __syncthreads();
+            }
+            if ((q & 3) == 0 || q == q0) philox(c0, sample, (uint32_t)(q >> 2), c3, a.key0, a.key1, w);
+            const int wi = q & 3;
+            const uint32_t word = wi == 0 ? w[0] : wi == 1 ? w[1] : wi == 2 ? w[2] : w[3];
+            const int buf = (q - q0) & 1;
+            if (q + 1 < q1)
+                mma_stage((const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride), lds + (buf ^ 1) * mvec, mvec, tid,
+                          nthr);
+            float u = 0.f, v = 0.f, y0 = x0, y1 = x1;
+            bool inside = false;
+            if (__ballot(alive) != 0ull) {
+                f32x16 du0, dv0, du1, dv1;
+                mma_issue<KH>((const float *)lds + buf * mbuf, a.PP, lane, b0, b1, du0, dv0, du1, dv1);
+                // under the products: direction, jump, exit test, next operands
+                float d0, d1;
+                angle_dir(u01(word, 0.f), d0, d1);
+                y0 = fmaf(J, d0, x0);
+                y1 = fmaf(J, d1, x1);
+                inside = fabsf(y0) < 1.f && fabsf(y1) < 1.f;
+                float nb0[KH], nb1[KH];
+                mma_operands<KH>(y1, a.P, nb0, nb1);
+                mma_epilogue<KH>(du0, dv0, du1, dv1, x0, u, v);
+#pragma unroll
+                for (int kk = 0; kk < KH; ++kk) { b0[kk] = nb0[kk]; b1[kk] = nb1[kk]; }
+            }
+            ++slots;
+            if (alive) {
+                if (inside) {   // residual at X_q, time tau_q = t_{n,l} - q Delta
+                    const float X[2] = {x0, x1};
+                    const float r = f_of<float>(a.phys, u) + source_space<float, 2, true>(a.phys, X, s_tf[tslot]) + v;
+                    const float y = delta * r;
+                    const float yc = y - comp;
+                    const float tt = acc + yc;
+                    comp = (tt - acc) - yc;
+                    acc = tt;
+                    x0 = y0;
+                    x1 = y1;
+                    ++evals;
+                } else {        // path ended: L = q
+                    alive = false;
+                    a.result[(int64_t)nodes[node].out * a.mcount + (sample - a.m0)] = (double)acc - (double)comp;
+                }
+            }
+            mma_stage_wait();
+            if (__syncthreads_or(alive ? 1 : 0) == 0) { ++q; break; }
+        }
+
+        // ---- paths alive after the round: finished at N*, or carried to the next round
+        const bool carry = alive && q1 < nstar;
+        if (alive && !carry)
+            a.result[(int64_t)nodes[node].out * a.mcount + (sample - a.m0)] = (double)acc - (double)comp;
+        const unsigned long long mask = __ballot(carry);
+        if (mask != 0ull) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(a.live_out + g, (uint32_t)__popcll(mask));
+            base = __shfl(base, 0, 64);
+            if (carry) {
+                const uint32_t off = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                State st;
+                st.x[0] = x0;
+                st.x[1] = x1;
+                st.acc = acc;
+                st.comp = comp;
+                st.node = node;
+                st.sample = sample;
+                sout[G->path_off + off] = st;
+            }
+        }
+    }
+    evals = wave_sum_u64(evals);
+    slots = wave_sum_u64(slots);
+    if (lane == 0) {
+        atomicAdd(a.stats + 0, evals);
+        atomicAdd(a.stats + 1, slots);
+    }
+}
+
 template <int KH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) advance_mma_kernel(RoundArgs a)
 {
-    advance_body<float, 2, 2 * KH, 1, 0, KH>(a);
+    advance_mma_body<KH>(a);
 }
 
 template <typename T, int D, int PMAX, int NS>
@@ -1371,7 +1528,8 @@ static hipError_t adv_mma(const RoundArgs &a, int kh, dim3 grid, dim3 block, siz
 
 bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane, int waves_per_block)
 {
-    return fp32 && dim == 2 && P >= 3 && P <= 32 && cf == 0 && samples_per_lane == 1 && waves_per_block == 4;
+    return fp32 && dim == 2 && P >= 3 && P <= 32 && cf == 0 && samples_per_lane == 1 && waves_per_block >= 1 &&
+           waves_per_block <= 4;
 }
 
 size_t advance_mma_lds_bytes(int PP) { return (size_t)2 * 2 * PP * kMmaRS * sizeof(float); }

@@ -117,7 +117,7 @@ def test_mma_exact_fixed_point(n):
         for l in range(3):
             U[0, jf, l] = pb.exact(X, t[l])
     with H.Plan(wl) as plan:
-        plan.hpsmc_set_launch(1, 4, 3)
+        plan.hpsmc_set_launch(1, 2, 6)
         assert plan.hpsmc_get_option("sample_mfma_active") == 1
         plan.hpsmc_set_nodes(0, U)
         plan.hpsmc_iterate(0, 0)
@@ -135,8 +135,8 @@ def test_mma_option_and_eligibility():
         assert plan.hpsmc_get_option("sample_mfma_active") == 0
         plan.hpsmc_set_launch(1, 4, 4)
         assert plan.hpsmc_get_option("sample_mfma_active") == 1
-        plan.hpsmc_set_launch(1, 2, 4)           # the matrix-core kernel runs four waves per block
-        assert plan.hpsmc_get_option("sample_mfma_active") == 0
+        plan.hpsmc_set_launch(1, 2, 6)           # two-wave blocks
+        assert plan.hpsmc_get_option("sample_mfma_active") == 1
         with pytest.raises(H.HpsmcError):
             plan.hpsmc_set_option("sample_mfma", 2)
         with pytest.raises(H.HpsmcError):
