@@ -33,7 +33,7 @@ FP64_PEAK_TFLOPS = 78.6    # published MI355X vector FP64
 METRIC = "node-samples/sec at fixed error vs exact; FP32-batched vs FP64 speedup"
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "advance_kernel_c2_fp32_m1024_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "advance_mma_kernel_c2_fp32_m1024_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2608_22190_amd", "csrc", "hpsmc_kernels.hip")
 
 
