@@ -19,7 +19,8 @@
  *   - Pointers marked "host" are host memory owned by the caller; "device"
  *     pointers are device memory owned by the caller; on_device selects which
  *     for the copy-in / copy-out calls.  The plan owns all other device memory
- *     (allocated with hipMalloc in hpsmc_create, freed in hpsmc_destroy).
+ *     (allocated in hpsmc_create with hipMalloc or the hpsmc_set_allocator
+ *     hooks, freed in hpsmc_destroy).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
  *     work and return; copy-out calls to host memory synchronize the stream.
  *   - Spatial nodes: the n-point Jacobi-Gauss (1,1) rule per dimension
@@ -48,7 +49,11 @@ typedef enum {
     HPSMC_ENOTSUP = -2,    /* valid but unsupported (e.g. nonzero boundary data) */
     HPSMC_ENOMEM = -3,     /* device or host allocation failed                  */
     HPSMC_EDEVICE = -4,    /* a HIP call failed; the plan is poisoned           */
-    HPSMC_EDIVERGED = -5   /* max|eps| non-finite, or grew 3 times in a row     */
+    HPSMC_EDIVERGED = -5,  /* tolerance mode: max|eps| non-finite, or grew in
+                              three consecutive iterations; iterates readable   */
+    HPSMC_ENOTCONVERGED = -6 /* tolerance mode: some interval used all `iters`
+                              iterations with max|eps| >= tol (informational:
+                              the results are valid)                            */
 } hpsmc_status;
 
 /* nonlinearity f(u) of eq. mainproblem */
@@ -100,16 +105,30 @@ typedef struct {
     uint64_t seed;
     int32_t precision;         /* HPSMC_FP64 or HPSMC_FP32_SAMPLING            */
     int32_t reserved;
+    double tol;                /* 0: exactly `iters` iterations per interval (or
+                                  sweeps), asynchronous.  > 0: Algorithm 1's loop
+                                  condition -- an interval stops once max|eps| <
+                                  tol (at most `iters`); the host reads max|eps|
+                                  after every iteration, so hpsmc_solve runs
+                                  eagerly even with the "graph" option          */
 } hpsmc_problem;
 
 typedef struct hpsmc_plan hpsmc_plan;
+
+/* Device-memory hooks (hpsmc_set_allocator): bytes >= 1; stream is the stream
+ * the plan is created or used on (NULL: the default stream); ctx is passed
+ * through.  alloc returns NULL on failure. */
+typedef void *(*hpsmc_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*hpsmc_free_fn)(void *ptr, void *stream, void *ctx);
 
 typedef struct {
     uint64_t path_steps;       /* residual evaluations (sum of L over paths)     */
     uint64_t lane_steps;       /* walk steps executed by all sample slots        */
     uint64_t node_samples;     /* (node, sample) estimates                       */
     int32_t n_records;         /* entries filled in max_eps                      */
-    int32_t status_flags;      /* bit 0: non-finite increment seen              */
+    int32_t status_flags;      /* bit 0: non-finite increment seen; bit 1: max|eps|
+                                  grew in three consecutive iterations of one
+                                  interval (divergence, any mode)                */
     int32_t sample_launches;   /* sampling-kernel launches timed (one per round) */
     int32_t recon_launches;    /* reconstructions timed                         */
     double sample_ms;          /* summed duration of those launches (HIP events
@@ -132,6 +151,13 @@ typedef struct {
                                   the current value)                             */
 } hpsmc_launch;
 
+/* Install the allocator that plans created afterwards use for every device
+ * workspace they own (for example a framework's caching allocator); both
+ * NULL restores hipMalloc / hipFree.  A plan keeps the hooks it was created
+ * with until hpsmc_destroy.  EINVAL when exactly one hook is NULL.
+ * Process-wide; thread-safe. */
+hpsmc_status hpsmc_set_allocator(hpsmc_alloc_fn alloc, hpsmc_free_fn free_, void *ctx);
+
 /* Validate the problem, compute the grid and transform matrices on the host,
  * allocate device memory, and write the initial iterate (the initial column
  * replicated in time, for interval 0 or for all intervals under SWEEPS).
@@ -142,7 +168,9 @@ void hpsmc_destroy(hpsmc_plan *plan);
 /* Spatial nodes (n, host) and temporal nodes of interval iv (M_iv+1, host). */
 hpsmc_status hpsmc_grid(const hpsmc_plan *plan, int32_t iv, double *x_nodes, double *t_nodes);
 
-/* Whole solve: Algorithm 1 (or the sweeps), `iters` iterations each. */
+/* Whole solve: Algorithm 1 (or the sweeps), `iters` iterations each, or with
+ * tol > 0 until max|eps| < tol per interval (then EDIVERGED / ENOTCONVERGED
+ * as described at hpsmc_status). */
 hpsmc_status hpsmc_solve(hpsmc_plan *plan, void *stream);
 
 /* Start interval iv (SEQUENTIAL): column 0 = initial data (iv = 0) or the last
@@ -194,6 +222,19 @@ hpsmc_status hpsmc_reset_stats(hpsmc_plan *plan, void *stream);
  * target, loss, grad: host or device per on_device.  Runs the forward solve. */
 hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *loss, double *grad,
                                 int32_t on_device, void *stream);
+
+/* Replace the initial data by nodal values u0 [instance][n^d] at the spatial
+ * nodes (host or device per on_device); the next start of interval 0 (or of
+ * every interval under SWEEPS) uses them.  EINVAL for IC_PHI plans (use
+ * hpsmc_set_initial_coeffs there).  Synchronizes the stream. */
+hpsmc_status hpsmc_set_initial_nodes(hpsmc_plan *plan, const double *u0, int32_t on_device, void *stream);
+
+/* The current iterate of interval iv in the basis of Sec. 2.3 (eq. u_N):
+ * out [instance][p_1..p_d][q] = coefficient of prod_i phi_{p_i}(x_i) L_q(xi),
+ * p_i in 0..n-1, q in 0..M_iv, i.e. U x_i A x_t B with the nodal-to-modal
+ * matrices of eqs. spacelag / timeLag.  out: host or device per on_device;
+ * synchronizes the stream. */
+hpsmc_status hpsmc_get_coeffs(hpsmc_plan *plan, int32_t iv, double *out, int32_t on_device, void *stream);
 
 /* Replace the phi-coefficients of IC_PHI initial data, [instance][n^d] (host or
  * device per on_device); the next start of interval 0 uses them.  EINVAL

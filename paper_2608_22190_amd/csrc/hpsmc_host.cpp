@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,11 @@ namespace hpsmc {
 // Errors
 // ---------------------------------------------------------------------------
 static thread_local std::string g_err;
+// allocator installed by hpsmc_set_allocator (copied into each new plan)
+static std::mutex g_alloc_mutex;
+static hpsmc_alloc_fn g_alloc_fn = nullptr;
+static hpsmc_free_fn g_free_fn = nullptr;
+static void *g_alloc_ctx = nullptr;
 static thread_local bool g_capturing = false;   // no event records inside a stream capture
 
 static hpsmc_status fail(hpsmc_status st, const std::string &msg)
@@ -236,6 +242,10 @@ struct NodeSet {               // the nodes one sampling launch covers
 
 struct hpsmc_plan {
     hpsmc_problem pb{};
+    hpsmc_alloc_fn alloc_fn = nullptr;   // device workspaces (null: hipMalloc / hipFree)
+    hpsmc_free_fn free_fn = nullptr;
+    void *alloc_ctx = nullptr;
+    int64_t ainv_off = 0;                // nodal -> phi-coefficient matrix A = Phi^{-1} (n x n)
     std::vector<double> t_breaks;
     std::vector<int32_t> degree, nstar;
     std::vector<double> ic_data;
@@ -373,6 +383,7 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     if (pb->ic_kind < 0 || pb->ic_kind > 3) return fail(HPSMC_EINVAL, "unknown ic_kind");
     if (pb->schedule < 0 || pb->schedule > 1) return fail(HPSMC_EINVAL, "unknown schedule");
     if (pb->precision < 0 || pb->precision > 1) return fail(HPSMC_EINVAL, "unknown precision");
+    if (!std::isfinite(pb->tol) || pb->tol < 0.0) return fail(HPSMC_EINVAL, "tol must be finite and >= 0");
     if ((pb->ic_kind == HPSMC_IC_PHI || pb->ic_kind == HPSMC_IC_NODAL) && !pb->ic_data)
         return fail(HPSMC_EINVAL, "ic_data is NULL");
     if (pb->ic_kind == HPSMC_IC_EXACT && pb->src_kind == HPSMC_SRC_NONE)
@@ -383,17 +394,30 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     return HPSMC_OK;
 }
 
+// device workspaces: hipMalloc/hipFree, or the allocator installed by
+// hpsmc_set_allocator when the plan was created
 static hpsmc_status dalloc(hpsmc_plan *plan, void **p, size_t bytes)
 {
     if (bytes == 0) bytes = 8;
+    if (plan->alloc_fn) {
+        *p = plan->alloc_fn(bytes, nullptr, plan->alloc_ctx);
+        if (!*p) return fail(HPSMC_ENOMEM, "allocator hook returned NULL for " + std::to_string(bytes) + " bytes");
+        return HPSMC_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
         (void)hipGetLastError();
         return fail(HPSMC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
-    (void)plan;
     return HPSMC_OK;
+}
+
+static void dfree(const hpsmc_plan *plan, void *p)
+{
+    if (!p) return;
+    if (plan->free_fn) plan->free_fn(p, nullptr, plan->alloc_ctx);
+    else (void)hipFree(p);
 }
 
 // Expected path length used to order work (longest first): the walk leaves
@@ -553,19 +577,11 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     return HPSMC_OK;
 }
 
-static void free_set(NodeSet &s)
+static void free_set(const hpsmc_plan *plan, NodeSet &s)
 {
-    (void)hipFree(s.dev);
-    (void)hipFree(s.group_mem);
-    (void)hipFree(s.eps);
-    (void)hipFree(s.sumsq);
-    (void)hipFree(s.probe);
-    (void)hipFree(s.gdev);
-    (void)hipFree(s.state[0]);
-    (void)hipFree(s.state[1]);
-    (void)hipFree(s.live);
-    (void)hipFree(s.prefix);
-    (void)hipFree(s.result);
+    for (void *p : {(void *)s.dev, s.group_mem, (void *)s.eps, (void *)s.sumsq, (void *)s.probe, (void *)s.gdev,
+                    s.state[0], s.state[1], (void *)s.live, (void *)s.prefix, (void *)s.result})
+        dfree(plan, p);
     s = NodeSet{};
 }
 
@@ -808,13 +824,13 @@ void hpsmc_destroy(hpsmc_plan *plan)
     if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->own_stream) (void)hipStreamDestroy(plan->own_stream);
-    for (auto &s : plan->sets) free_set(s);
+    for (auto &s : plan->sets) free_set(plan, s);
     for (auto *pool : {&plan->ev_sample, &plan->ev_slab, &plan->ev_recon, &plan->ev_span})
         for (auto &e : *pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     void *ptrs[] = {plan->U, plan->cu, plan->cv, plan->tmp0, plan->tmp1, plan->ic, plan->mats,
                     plan->slab_table, plan->part, plan->counters, plan->maxbits, plan->hist_u, plan->hist_v,
                     plan->lam, plan->cbar_u, plan->cbar_v, plan->dtarget, plan->dloss, plan->dgrad, plan->slab_bar};
-    for (void *p : ptrs) (void)hipFree(p);
+    for (void *p : ptrs) dfree(plan, p);
     delete plan;
 }
 
@@ -825,6 +841,12 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
     hpsmc_status st = validate(pb);
     if (st) return st;
     std::unique_ptr<hpsmc_plan, void (*)(hpsmc_plan *)> plan(new hpsmc_plan, hpsmc_destroy);
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mutex);
+        plan->alloc_fn = g_alloc_fn;
+        plan->free_fn = g_free_fn;
+        plan->alloc_ctx = g_alloc_ctx;
+    }
     plan->pb = *pb;
     plan->d = pb->dim;
     plan->n = pb->n;
@@ -932,6 +954,35 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
         auto PhiT = transpose(Phi, plan->n, plan->n);
         plan->phit_off = (int64_t)mats.size();
         mats.insert(mats.end(), PhiT.begin(), PhiT.end());
+        // A[p][j] with sum_j A[p][j] phi_q(x_j) = delta_pq: nodal values -> phi-coefficients
+        const int n = plan->n;
+        std::vector<double> W(Phi), Ainv((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i) Ainv[(size_t)i * n + i] = 1.0;
+        // Gauss-Jordan with partial pivoting on W = Phi (rows j, columns p): Ainv becomes
+        // Phi^{-1}, rows p and columns j
+        for (int c = 0; c < n; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < n; ++r)
+                if (std::fabs(W[(size_t)r * n + c]) > std::fabs(W[(size_t)piv * n + c])) piv = r;
+            if (piv != c)
+                for (int k = 0; k < n; ++k) {
+                    std::swap(W[(size_t)c * n + k], W[(size_t)piv * n + k]);
+                    std::swap(Ainv[(size_t)c * n + k], Ainv[(size_t)piv * n + k]);
+                }
+            const double inv = 1.0 / W[(size_t)c * n + c];
+            for (int k = 0; k < n; ++k) { W[(size_t)c * n + k] *= inv; Ainv[(size_t)c * n + k] *= inv; }
+            for (int r = 0; r < n; ++r) {
+                if (r == c) continue;
+                const double f = W[(size_t)r * n + c];
+                if (f == 0.0) continue;
+                for (int k = 0; k < n; ++k) {
+                    W[(size_t)r * n + k] -= f * W[(size_t)c * n + k];
+                    Ainv[(size_t)r * n + k] -= f * Ainv[(size_t)c * n + k];
+                }
+            }
+        }
+        plan->ainv_off = (int64_t)mats.size();
+        mats.insert(mats.end(), Ainv.begin(), Ainv.end());
     }
     if ((st = dalloc(pl, (void **)&pl->mats, mats.size() * 8))) return st;
     std::vector<double> u0;
@@ -1036,23 +1087,73 @@ hpsmc_status hpsmc_sweep(hpsmc_plan *plan, int32_t tag, void *stream)
     return sweep_impl(plan, tag, plan->n_records, (hipStream_t)stream);
 }
 
+// max|eps| of one record (synchronizes the stream)
+static hpsmc_status read_record(hpsmc_plan *plan, int record, double *v, hipStream_t s)
+{
+    unsigned long long bits = 0;
+    if (hipMemcpyAsync(&bits, plan->maxbits + std::min(record, 4095), 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "record copy failed");
+    memcpy(v, &bits, 8);
+    return HPSMC_OK;
+}
+
+// divergence: the latest max|eps| is not finite, or it grew in each of the last three iterations
+static bool diverged(const std::vector<double> &h)
+{
+    const size_t n = h.size();
+    if (n > 0 && !std::isfinite(h[n - 1])) return true;
+    return n >= 4 && h[n - 1] > h[n - 2] && h[n - 2] > h[n - 3] && h[n - 3] > h[n - 4];
+}
+
+// Algorithm 1 (or the sweeps).  tol = 0: exactly `iters` iterations, asynchronous.
+// tol > 0: after each iteration the host reads max|eps| (Algorithm 1's loop
+// condition), stops the interval below tol, returns EDIVERGED on divergence and
+// ENOTCONVERGED when some interval used all `iters` iterations.
 static hpsmc_status solve_body(hpsmc_plan *plan, hipStream_t s)
 {
     hpsmc_status st;
     const int K = plan->pb.iters;
+    const double tol = plan->pb.tol;
+    bool unconverged = false;
     if (plan->pb.schedule == HPSMC_SEQUENTIAL) {
         for (int iv = 0; iv < plan->n_iv; ++iv) {
             if ((st = start_interval(plan, iv, 1, s))) return st;
-            for (int k = 0; k < K; ++k)
+            std::vector<double> hist;
+            int k = 0;
+            for (; k < K; ++k) {
                 if ((st = iterate_impl(plan, iv, plan->pb.fresh_per_iter ? k : 0, iv * K + k, s))) return st;
+                if (tol > 0.0) {
+                    double e;
+                    if ((st = read_record(plan, iv * K + k, &e, s))) return st;
+                    hist.push_back(e);
+                    if (diverged(hist))
+                        return fail(HPSMC_EDIVERGED, "max|eps| diverged in interval " + std::to_string(iv) +
+                                                         ", iteration " + std::to_string(k));
+                    if (e < tol) break;
+                }
+            }
+            if (tol > 0.0 && k == K) unconverged = true;
         }
     } else {
         for (int iv = 0; iv < plan->n_iv; ++iv)
             HIP_TRY(launch_start_columns(plan->U + plan->u_off[iv], plan->ic, 1, 0, plan->degree[iv] + 1,
                                          plan->degree[iv] + 1, (int64_t)plan->n_inst * plan->nsp, 1, s));
-        for (int k = 0; k < K; ++k)
+        std::vector<double> hist;
+        int k = 0;
+        for (; k < K; ++k) {
             if ((st = sweep_impl(plan, plan->pb.fresh_per_iter ? k : 0, k, s))) return st;
+            if (tol > 0.0) {
+                double e;
+                if ((st = read_record(plan, k, &e, s))) return st;
+                hist.push_back(e);
+                if (diverged(hist)) return fail(HPSMC_EDIVERGED, "max|eps| diverged at sweep " + std::to_string(k));
+                if (e < tol) break;
+            }
+        }
+        if (tol > 0.0 && k == K) unconverged = true;
     }
+    if (unconverged) return fail(HPSMC_ENOTCONVERGED, "max|eps| stayed above tol after iters iterations");
     return HPSMC_OK;
 }
 
@@ -1060,7 +1161,7 @@ hpsmc_status hpsmc_solve(hpsmc_plan *plan, void *stream)
 {
     CHECK_PLAN(plan);
     hipStream_t s = (hipStream_t)stream;
-    if (!plan->use_graph) return solve_body(plan, s);
+    if (!plan->use_graph || plan->pb.tol > 0.0) return solve_body(plan, s);   // the stop test needs the host
     if (!plan->graph_exec) {
         // capture on a stream of the plan (the legacy default stream cannot be captured)
         if (!plan->own_stream) HIP_TRY(hipStreamCreateWithFlags(&plan->own_stream, hipStreamNonBlocking));
@@ -1149,8 +1250,8 @@ hpsmc_status hpsmc_eval(hpsmc_plan *plan, int32_t iv, int32_t inst, const double
     hipStream_t s = (hipStream_t)stream;
     double *dp = nullptr, *dout = nullptr;
     const size_t pb = (size_t)npts * (plan->d + 1) * 8, ob = (size_t)npts * 2 * 8;
-    if (hipMalloc(&dp, pb) != hipSuccess || hipMalloc(&dout, ob) != hipSuccess) {
-        (void)hipFree(dp);
+    if (dalloc(plan, (void **)&dp, pb) != HPSMC_OK || dalloc(plan, (void **)&dout, ob) != HPSMC_OK) {
+        dfree(plan, dp);
         return fail(HPSMC_ENOMEM, "eval buffers");
     }
     const int T1 = plan->degree[iv] + 1;
@@ -1161,8 +1262,8 @@ hpsmc_status hpsmc_eval(hpsmc_plan *plan, int32_t iv, int32_t inst, const double
                         plan->t_breaks[iv + 1] - plan->t_breaks[iv], dp, npts, dout, s);
     if (e == hipSuccess) e = hipMemcpyAsync(out, dout, ob, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(dp);
-    (void)hipFree(dout);
+    dfree(plan, dp);
+    dfree(plan, dout);
     if (e != hipSuccess) return fail(HPSMC_EDEVICE, std::string("eval: ") + hipGetErrorString(e));
     return HPSMC_OK;
 }
@@ -1178,7 +1279,7 @@ hpsmc_status hpsmc_set_probe(hpsmc_plan *plan, int64_t m_probe)
         plan->graph = nullptr;
     }
     for (auto &s : plan->sets) {
-        (void)hipFree(s.probe);
+        dfree(plan, s.probe);
         s.probe = nullptr;
         if (m_probe > 0) {
             hpsmc_status st = dalloc(plan, (void **)&s.probe, (size_t)s.n * m_probe * 8);
@@ -1254,11 +1355,16 @@ hpsmc_status hpsmc_stats(const hpsmc_plan *plan, hpsmc_stats_t *out, void *strea
     out->lane_steps = c[2];
     out->node_samples = (uint64_t)plan->node_samples;
     out->n_records = plan->n_records;
+    const int K = std::max(1, plan->pb.iters);
     for (int r = 0; r < plan->n_records; ++r) {
         double v;
         memcpy(&v, &mb[r], 8);
         out->max_eps[r] = v;
         if (!std::isfinite(v)) out->status_flags |= 1;
+        // records r-3..r of one interval (blocks of `iters` records) grew each time
+        if (r % K >= 3 && out->max_eps[r] > out->max_eps[r - 1] && out->max_eps[r - 1] > out->max_eps[r - 2] &&
+            out->max_eps[r - 2] > out->max_eps[r - 3])
+            out->status_flags |= 2;
     }
     return HPSMC_OK;
 }
@@ -1362,7 +1468,7 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     int64_t usz = 0;
     for (int k = 0; k < plan->n_iv; ++k) usz += (int64_t)plan->n_inst * plan->nsp * (plan->degree[k] + 1);
     double *Usave = nullptr;
-    if (hipMalloc(&Usave, usz * 8) != hipSuccess) { (void)hipGetLastError(); return fail(HPSMC_ENOMEM, "tune buffer"); }
+    if (dalloc(plan, (void **)&Usave, usz * 8) != HPSMC_OK) return fail(HPSMC_ENOMEM, "tune buffer");
     HIP_TRY(hipMemcpyAsync(Usave, plan->U, usz * 8, hipMemcpyDeviceToDevice, s));
     const int64_t ns_save = plan->node_samples;
     const int32_t rec_save = plan->n_records;
@@ -1386,7 +1492,7 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        (void)hipFree(Usave);
+        dfree(plan, Usave);
         return fail(HPSMC_EDEVICE, "tune events");
     }
     plan->pb.M = mt;
@@ -1443,7 +1549,7 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(s);
-    (void)hipFree(Usave);
+    dfree(plan, Usave);
     (void)set;
     if (st) return st;
     st = hpsmc_set_launch(plan, &best);
@@ -1475,14 +1581,66 @@ hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_
     const size_t bytes = (size_t)plan->n_inst * plan->nsp * 8;
     // stage the coefficients in the gradient's target buffer slot (free until a gradient call)
     double *stage = nullptr;
-    if (hipMalloc(&stage, bytes) != hipSuccess) { (void)hipGetLastError(); return fail(HPSMC_ENOMEM, "staging"); }
+    if (dalloc(plan, (void **)&stage, bytes) != HPSMC_OK) return fail(HPSMC_ENOMEM, "staging");
     hipError_t e = hipMemcpyAsync(stage, c0, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) { (void)hipFree(stage); plan->poisoned = true; return fail(HPSMC_EDEVICE, "coefficient copy"); }
+    if (e != hipSuccess) { dfree(plan, stage); plan->poisoned = true; return fail(HPSMC_EDEVICE, "coefficient copy"); }
     hpsmc_status st = phi_apply(plan, stage, plan->ic, plan->phi_off, s);
     if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail(HPSMC_EDEVICE, "synchronize");
-    (void)hipFree(stage);
+    dfree(plan, stage);
     if (st) return st;
     if (!on_device) plan->ic_data.assign(c0, c0 + (size_t)plan->n_inst * plan->nsp);
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_set_initial_nodes(hpsmc_plan *plan, const double *u0, int32_t on_device, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (!u0) return fail(HPSMC_EINVAL, "u0 is NULL");
+    if (plan->pb.ic_kind == HPSMC_IC_PHI)
+        return fail(HPSMC_EINVAL, "the plan's initial data are phi-coefficients: use hpsmc_set_initial_coeffs");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = (size_t)plan->n_inst * plan->nsp * 8;
+    if (hipMemcpyAsync(plan->ic, u0, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        plan->poisoned = true;
+        return fail(HPSMC_EDEVICE, "initial node copy failed");
+    }
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_get_coeffs(hpsmc_plan *plan, int32_t iv, double *out, int32_t on_device, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (iv < 0 || iv >= plan->n_iv || !out) return fail(HPSMC_EINVAL, "bad interval or output");
+    hipStream_t s = (hipStream_t)stream;
+    const int d = plan->d, n = plan->n, T1 = plan->degree[iv] + 1;
+    const int64_t I = plan->n_inst;
+    // U x_1 A ... x_d A x_t Bt: phi-coefficients in space, Legendre coefficients in time
+    const double *in = plan->U + plan->u_off[iv];
+    double *bufs[2] = {plan->tmp0, plan->tmp1};
+    for (int i = 0; i < d; ++i) {
+        double *o = bufs[i & 1];
+        HIP_TRY(launch_mode_product(in, o, I * ipow(n, i), n, n, ipow(n, d - 1 - i) * T1, plan->mats + plan->ainv_off,
+                                    1.0, 0, s));
+        in = o;
+    }
+    double *o = bufs[d & 1];
+    HIP_TRY(launch_mode_product(in, o, I * plan->nsp, T1, T1, 1, plan->mats + plan->bt_off[iv], 1.0, 0, s));
+    const size_t bytes = (size_t)I * plan->nsp * T1 * 8;
+    if (hipMemcpyAsync(out, o, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "coefficient copy failed");
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_set_allocator(hpsmc_alloc_fn alloc, hpsmc_free_fn free_, void *ctx)
+{
+    if ((alloc == nullptr) != (free_ == nullptr)) return fail(HPSMC_EINVAL, "alloc and free must both be set or both NULL");
+    std::lock_guard<std::mutex> lk(g_alloc_mutex);
+    g_alloc_fn = alloc;
+    g_free_fn = free_;
+    g_alloc_ctx = ctx;
     return HPSMC_OK;
 }
 

@@ -24,7 +24,8 @@ SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4
 IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
 SCHEDULES = {"sequential": 0, "sweeps": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
-STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSUP", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED"}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSUP", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED", -6: "ENOTCONVERGED"}
+ENOTCONVERGED = -6
 
 
 class HpsmcError(RuntimeError):
@@ -41,7 +42,7 @@ class hpsmc_problem(C.Structure):
         ("f_param", C.c_double * 4), ("src_param", C.c_double * 8), ("ic_param", C.c_double * 4),
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
-        ("precision", C.c_int32), ("reserved", C.c_int32),
+        ("precision", C.c_int32), ("reserved", C.c_int32), ("tol", C.c_double),
     ]
 
 
@@ -58,8 +59,12 @@ class hpsmc_launch(C.Structure):
                 ("blocks_per_cu", C.c_int32), ("round_steps", C.c_int32)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
 # name: (restype, argtypes)
 _SIGS = {
+    "hpsmc_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, C.c_void_p]),
     "hpsmc_create": (C.c_int, [C.POINTER(hpsmc_problem), C.POINTER(C.c_void_p)]),
     "hpsmc_destroy": (None, [C.c_void_p]),
     "hpsmc_grid": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -80,6 +85,8 @@ _SIGS = {
     "hpsmc_reset_stats": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hpsmc_loss_grad_c0": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "hpsmc_set_initial_coeffs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_set_initial_nodes": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "hpsmc_get_coeffs": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
     "hpsmc_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int64]),
     "hpsmc_get_option": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int64)]),
     "hpsmc_last_error": (C.c_char_p, []),
@@ -147,10 +154,40 @@ def make_problem(wl):
     p.ic_data = ic.ctypes.data_as(C.POINTER(C.c_double)) if ic is not None else C.POINTER(C.c_double)()
     p.M, p.iters, p.fresh_per_iter, p.seed = wl.M, wl.iters, int(wl.fresh_per_iter), wl.seed
     p.precision = PRECISIONS[wl.precision]
+    p.tol = float(getattr(wl, "tol", 0.0))
     return p, [tb, deg, ns, ic]
 
 
 # ------------------------------------------------------------ C-ABI mirrors
+_alloc_hooks = None   # the ctypes callbacks must outlive every plan created with them
+
+
+def hpsmc_set_allocator(alloc=None, free=None, ctx=None):
+    """Install Python callables alloc(bytes, stream) -> int pointer and
+    free(pointer, stream) as the device allocator of plans created afterwards;
+    no arguments restores hipMalloc / hipFree."""
+    global _alloc_hooks
+    if alloc is None and free is None:
+        _check(lib().hpsmc_set_allocator(ALLOC_FN(), FREE_FN(), None), "hpsmc_set_allocator")
+        return
+    a = ALLOC_FN(lambda nbytes, stream, c: int(alloc(int(nbytes), stream)) or None)
+    f = FREE_FN(lambda ptr, stream, c: free(int(ptr), stream))
+    _check(lib().hpsmc_set_allocator(a, f, ctx), "hpsmc_set_allocator")
+    _alloc_hooks = (a, f, alloc, free) if _alloc_hooks is None else _alloc_hooks + (a, f, alloc, free)
+
+
+def torch_caching_allocator():
+    """alloc / free callables backed by PyTorch's CUDA caching allocator."""
+    import torch
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes)
+
+    def free(ptr, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+    return alloc, free
+
+
 def hpsmc_create(wl):
     p, keep = make_problem(wl)
     h = C.c_void_p()
@@ -195,7 +232,11 @@ class Plan:
         return x, t
 
     def hpsmc_solve(self, stream=None):
-        _check(lib().hpsmc_solve(self.h, _stream(stream)), "hpsmc_solve")
+        """Returns the status: OK, or ENOTCONVERGED (informational) in tolerance mode."""
+        st = lib().hpsmc_solve(self.h, _stream(stream))
+        if st != ENOTCONVERGED:
+            _check(st, "hpsmc_solve")
+        return st
 
     def hpsmc_start_interval(self, iv, stream=None):
         _check(lib().hpsmc_start_interval(self.h, iv, _stream(stream)), "hpsmc_start_interval")
@@ -222,6 +263,19 @@ class Plan:
         if not on_dev:
             values = np.ascontiguousarray(values, dtype=np.float64).reshape(self._nodes_shape(iv))
         _check(lib().hpsmc_set_nodes(self.h, iv, _ptr(values), int(on_dev), _stream(stream)), "hpsmc_set_nodes")
+
+    def hpsmc_set_initial_nodes(self, u0, stream=None):
+        on_dev = hasattr(u0, "data_ptr")
+        if not on_dev:
+            u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(self.wl.n_instances, self.nsp)
+        _check(lib().hpsmc_set_initial_nodes(self.h, _ptr(u0), int(on_dev), _stream(stream)), "hpsmc_set_initial_nodes")
+
+    def hpsmc_get_coeffs(self, iv, out=None, stream=None):
+        on_dev = out is not None and hasattr(out, "data_ptr")
+        if out is None:
+            out = np.zeros(self._nodes_shape(iv))
+        _check(lib().hpsmc_get_coeffs(self.h, iv, _ptr(out), int(on_dev), _stream(stream)), "hpsmc_get_coeffs")
+        return out
 
     def hpsmc_get_increment(self, iv, stream=None):
         cnt = (self.wl.n_instances, self.nsp * self.wl.degree[iv])
@@ -264,7 +318,8 @@ class Plan:
         s = hpsmc_stats_t()
         _check(lib().hpsmc_stats(self.h, C.byref(s), _stream(stream)), "hpsmc_stats")
         return {"path_steps": s.path_steps, "lane_steps": s.lane_steps, "node_samples": s.node_samples,
-                "max_eps": np.array(s.max_eps[:s.n_records]), "status_flags": s.status_flags,
+                "max_eps": np.array(s.max_eps[:s.n_records]), "n_records": s.n_records,
+                "status_flags": s.status_flags,
                 "sample_launches": s.sample_launches, "recon_launches": s.recon_launches,
                 "sample_ms": s.sample_ms, "sampling_span_ms": s.sampling_span_ms, "recon_ms": s.recon_ms,
                 "slab_ms": s.slab_ms,

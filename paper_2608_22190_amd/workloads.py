@@ -45,6 +45,7 @@ class Workload:
     fresh_per_iter: bool = True
     precision: str = "fp64"     # "fp64" or "fp32" (path sampling precision)
     exact_known: bool = True
+    tol: float = 0.0            # > 0: stop an interval once max|eps| < tol (Algorithm 1's loop condition)
 
     @property
     def n_intervals(self):

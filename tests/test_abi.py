@@ -46,3 +46,40 @@ def test_missing_ic_data_is_rejected():
     with pytest.raises(H.HpsmcError) as ei:
         H.Plan(wl)
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("tol", [-1e-3, float("nan"), float("inf")])
+def test_invalid_tolerance_is_rejected(tol):
+    wl = W.small(dim=1, n=4, M_deg=4).with_(tol=tol)
+    with pytest.raises(H.HpsmcError) as ei:
+        H.Plan(wl)
+    assert ei.value.status == -1
+
+
+def test_allocator_hooks_must_come_in_pairs():
+    lib = H.lib()
+    a = H.ALLOC_FN(lambda n, s, c: None)
+    assert lib.hpsmc_set_allocator(a, H.FREE_FN(), None) == -1
+    assert lib.hpsmc_set_allocator(H.ALLOC_FN(), H.FREE_FN(), None) == 0
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof / offsetof of the ABI structs from a C compiler against the ctypes mirrors."""
+    import ctypes as C
+    import subprocess
+    structs = {"hpsmc_problem": H.hpsmc_problem, "hpsmc_stats_t": H.hpsmc_stats_t, "hpsmc_launch": H.hpsmc_launch}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hpsmc.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.rsplit(" ", 1) for l in subprocess.check_output([str(exe)]).decode().split("\n") if l)
+    for name, cls in structs.items():
+        assert int(got[name]) == C.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, (name, f[0])
