@@ -92,11 +92,32 @@ def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256):
         t1 = time.perf_counter()
         st = plan.hpsmc_stats(stream=stream)
         U = plan.hpsmc_get_nodes(0, stream=stream)
+        grid = plan.hpsmc_grid(0)
         eps, ssq = plan.hpsmc_get_increment(0, stream=stream)
         lau = plan.hpsmc_get_launch()
         mma = plan.hpsmc_get_option("sample_mfma_active")
     sig = float(np.sqrt(np.maximum(ssq / wl.M - eps ** 2, 0.0) / wl.M).max())
-    return {"seconds": t1 - t0, "stats": st, "U": U, "sigma": sig, "launch": lau, "mma": mma}
+    return {"seconds": t1 - t0, "stats": st, "U": U, "sigma": sig, "launch": lau, "mma": mma, "grid": grid}
+
+
+def long_time_exact(wl, grid):
+    """The 2-D long-time workload's manufactured solution at the nodes of
+    interval 1: prod_i (1 - x_i^2) sin(x_0 + x_1) e^{cos t} / (1 + t^2)."""
+    x, t = grid
+    X0, X1 = np.meshgrid(x, x, indexing="ij")
+    sp = ((1 - X0 ** 2) * (1 - X1 ** 2) * np.sin(X0 + X1)).reshape(-1)
+    tf = np.exp(np.cos(t)) / (1 + t ** 2)
+    return sp[:, None] * tf[None, :]
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def run_other(name, args, torch):
@@ -199,6 +220,7 @@ def cpu_baseline(wl, budget_s=20.0):
         if t_used < 1.0:
             m *= 2
     return {"value": done / t_used, "unit": "node-samples/s", "cores": O.num_threads(), "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": f"{nodes_used} random nodes of interval 1 x first samples ({done} node-samples, "
                       f"one residual iteration from the replicated initial data), {t_used:.1f} s"}
 
@@ -286,9 +308,13 @@ def main():
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["seconds"] / args.steps,
                        "roofline_achieved_tflops": a64, "roofline_frac": a64 / FP64_PEAK_TFLOPS}
         out["fp32_over_fp64_speedup"] = value / v64
+        ex = long_time_exact(base, r64["grid"])
         out["accuracy"] = {"max_abs_u32_minus_u64": float(np.max(np.abs(r32["U"] - r64["U"]))),
                            "max_node_std_error_fp64": r64["sigma"],
-                           "note": "same Philox words in both precisions"}
+                           "e32_vs_exact": float(np.max(np.abs(r32["U"][0] - ex))),
+                           "e64_vs_exact": float(np.max(np.abs(r64["U"][0] - ex))),
+                           "note": "same Philox words in both precisions; errors are the max over all nodes "
+                                   "after the timed iterations from the replicated initial data"}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(base.with_(precision="fp64"))
     print(json.dumps(out), flush=True)
