@@ -1697,8 +1697,12 @@ hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t 
 static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hipStream_t s)
 {
     const int G = (int)set.ghost.size();
-    const int nthr = 64;
-    const size_t lds = adjoint_lds_bytes(plan->fp32, plan->d, plan->P, nthr, set.slab.slab_stride);
+    // the matrix-core form sums four waves' outer products in LDS before its
+    // atomics into the slab-adjoint table; the vector form sums one wave's
+    const int mfma = plan->fp32 && plan->adj_use_mfma;
+    const int waves = mfma ? 4 : 1;
+    const int nthr = 64 * waves;
+    const size_t lds = adjoint_lds_bytes(plan->fp32, mfma, plan->d, plan->P, nthr, set.slab.slab_stride);
     const int64_t nvec = set.slab.slab_stride * (plan->fp32 ? 4 : 8) / 16;
     if (nvec > 4LL * nthr || lds > 65536) return fail(HPSMC_ENOTSUP, "slab too large for the adjoint kernel");
     const int C = plan->round_steps;
@@ -1724,8 +1728,8 @@ static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hi
     aa.lambda = plan->lam;
     aa.slab_bar = plan->slab_bar;
     aa.inv_M = 1.0 / (double)plan->pb.M;
-    aa.use_mfma = plan->fp32 && plan->adj_use_mfma;
-    const int blocks = std::max(1, plan->cus * 8);
+    aa.use_mfma = mfma;
+    const int blocks = std::max(1, plan->cus * (8 / waves));
     for (int64_t m0 = 0; m0 < plan->pb.M; m0 += set.ms) {
         const int64_t mc = std::min<int64_t>(set.ms, plan->pb.M - m0);
         a.m0 = m0;
@@ -1737,7 +1741,7 @@ static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hi
             a.live_in = set.live + (r & 1) * G;
             a.live_out = set.live + ((r + 1) & 1) * G;
             HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, a.live_in, a.live_out, set.prefix, plan->counters, s));
-            HIP_TRY(launch_adjoint(aa, plan->fp32, 1, blocks, lds, s));
+            HIP_TRY(launch_adjoint(aa, plan->fp32, waves, blocks, lds, s));
         }
     }
     return HPSMC_OK;

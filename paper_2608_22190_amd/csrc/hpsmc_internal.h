@@ -159,7 +159,7 @@ hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mc
 size_t path_state_bytes(int fp32, int dim);
 hipError_t launch_adjoint(const AdjointArgs &a, int fp32, int waves_per_block, int blocks, size_t lds_bytes,
                           hipStream_t s);
-size_t adjoint_lds_bytes(int fp32, int dim, int P, int nthr, int64_t slab_stride);
+size_t adjoint_lds_bytes(int fp32, int mfma, int dim, int P, int nthr, int64_t slab_stride);
 hipError_t launch_slab_adjoint(const SlabArgs &a, int32_t groups_per_inst, int32_t n_inst, int fp32, double *cbar_u,
                                double *cbar_v, int64_t coef_inst_stride, hipStream_t s);
 hipError_t launch_loss_lambda(const double *U, const double *target, int n_inst, int64_t nsp, int T1, double *lambda,

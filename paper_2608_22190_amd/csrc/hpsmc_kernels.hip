@@ -1595,16 +1595,15 @@ hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mc
 // ===========================================================================
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-size_t adjoint_lds_bytes(int fp32, int dim, int P, int nthr, int64_t slab_stride)
+size_t adjoint_lds_bytes(int fp32, int mfma, int dim, int P, int nthr, int64_t slab_stride)
 {
     const size_t T = fp32 ? 4 : 8;
     const int64_t nvec = slab_stride * (int64_t)T / 16;
     const size_t slab = (size_t)2 * ((nvec + 1) & ~1LL) * 16;
+    if (mfma) return slab + (size_t)nthr * (2 * P + 2) * 4 + 2 * 32 * 32 * 4;
     const int R = dim == 1 ? 1 : P;
-    const int RS = fp32 ? 32 : ((std::max(R, P) + 3) & ~3);
-    const size_t ab = (size_t)nthr * 3 * RS * T;
-    const size_t g = fp32 ? 2 * 32 * 32 * 4 : 0;
-    return slab + ab + g;
+    const int RS = (std::max(R, P) + 3) & ~3;
+    return slab + (size_t)nthr * 3 * RS * T;
 }
 
 template <typename T, int D, int PMAX, bool MFMA>
@@ -1617,11 +1616,17 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
     const int64_t svec = (nvec + 1) & ~(int64_t)1;
     const int P = a.P, PP = a.PP;
     const int R = D == 1 ? 1 : P;
-    const int RS = MFMA ? 32 : (((R > P ? R : P) + 3) & ~3);
+    // vector path: weighted rows Au, Av and columns Bm per sample (stride RS);
+    // matrix-core path: basis rows Am and columns Bm (stride P) and the two
+    // weights Wm per sample, the products' block sum gsum [2][32][32]
+    const int RS = MFMA ? P : (((R > P ? R : P) + 3) & ~3);
     T *Au = (T *)(lds + 2 * svec);
     T *Av = Au + (int64_t)nthr * RS;
     T *Bm = Av + (int64_t)nthr * RS;
-    float *gsum = (float *)(Bm + (int64_t)nthr * RS);   // [2][32][32], matrix-core path
+    float *Am = (float *)(lds + 2 * svec);
+    float *Bmm = Am + (int64_t)nthr * P;
+    float *Wm = Bmm + (int64_t)nthr * P;
+    float *gsum = MFMA ? Wm + 2 * (int64_t)nthr : nullptr;
     __shared__ long long s_item;
     cptr<GroupDesc> groups = as_const(a.groups);
     cptr<NodeDesc> nodes = as_const(a.nodes);
@@ -1751,7 +1756,26 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
                 }
             }
             // ---- outer-product factors of this sample: rows L(X_0) weighted, columns L(X_{d-1})
-            {
+            if constexpr (MFMA) {
+                float *am = Am + (int64_t)tid * P, *bm = Bmm + (int64_t)tid * P;
+                Wm[2 * tid] = wu;
+                Wm[2 * tid + 1] = wv;
+                if constexpr (D == 1) {
+                    for (int i = 0; i < P; ++i) am[i] = i == 0 ? 1.f : 0.f;
+                } else {
+                    float lp = 0.f, lc = 1.f;
+                    const float x0 = X[0][0];
+                    for (int i = 0; i < P; ++i) {
+                        am[i] = lc;
+                        const float nx = rec_a<float>(i) * x0 * lc - rec_b<float>(i) * lp;
+                        lp = lc;
+                        lc = nx;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < PMAX; ++j)
+                    if (j < P) bm[j] = Ll[0][j];
+            } else {
                 T *au = Au + (int64_t)tid * RS, *av = Av + (int64_t)tid * RS, *bm = Bm + (int64_t)tid * RS;
                 if constexpr (D == 1) {
                     for (int i = 0; i < RS; ++i) { au[i] = i == 0 ? wu : (T)0; av[i] = i == 0 ? wv : (T)0; }
@@ -1788,14 +1812,16 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
             // ---- block sum of the outer products into the slab adjoint of step q
             T *dstq = gbar + (int64_t)q * a.slab_stride;
             if constexpr (MFMA) {
+                // K = the wave's 64 samples, two per product; the four waves meet in gsum
                 f32x16 cu = {}, cv = {};
                 const int i = lane & 31;
+                const bool row = i < P;
 #pragma unroll 4
                 for (int kk = 0; kk < 32; ++kk) {
                     const int sidx = wave * 64 + 2 * kk + (lane >> 5);
-                    const float au = Au[sidx * 32 + i], av = Av[sidx * 32 + i], bb = Bm[sidx * 32 + i];
-                    cu = __builtin_amdgcn_mfma_f32_32x32x2f32(au, bb, cu, 0, 0, 0);
-                    cv = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bb, cv, 0, 0, 0);
+                    const float am = row ? Am[sidx * P + i] : 0.f, bb = row ? Bmm[sidx * P + i] : 0.f;
+                    cu = __builtin_amdgcn_mfma_f32_32x32x2f32(Wm[2 * sidx] * am, bb, cu, 0, 0, 0);
+                    cv = __builtin_amdgcn_mfma_f32_32x32x2f32(Wm[2 * sidx + 1] * am, bb, cv, 0, 0, 0);
                 }
                 const int j = lane & 31;
 #pragma unroll
