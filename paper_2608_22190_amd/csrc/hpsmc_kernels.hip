@@ -660,7 +660,7 @@ __global__ void slab_kernel(SlabArgs a)
             double lp = 0.0, lc = 1.0;
             for (int k = 0; k < T1; ++k) {
                 val = fma(c[k], lc, val);
-                const double nx = ((2.0 * k + 1.0) * xi * lc - k * lp) / (k + 1.0);
+                const double nx = c_rec.ad[k] * xi * lc - c_rec.bd[k] * lp;
                 lp = lc;
                 lc = nx;
             }
@@ -843,19 +843,35 @@ __global__ void round_prep_kernel(const GroupDesc *__restrict__ groups, int32_t 
                                   uint32_t *__restrict__ live_out, int64_t *__restrict__ batch_prefix,
                                   unsigned long long *work)
 {
-    // one block: clear the output counters, then a serial prefix over groups
-    for (int g = threadIdx.x; g < n_groups; g += blockDim.x) live_out[g] = 0u;
-    if (threadIdx.x == 0) {
+    // one block of 256 threads: clear the output counters, then an exclusive
+    // prefix over groups of their work items (each thread a contiguous chunk,
+    // a scan of the 256 chunk sums in LDS, then the chunks again)
+    __shared__ int64_t part[256];
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int g = t; g < n_groups; g += nt) live_out[g] = 0u;
+    const int64_t q0 = (int64_t)round * steps;
+    auto items = [&](int g) -> int64_t {
+        int64_t live = round == 0 ? (int64_t)groups[g].node_count * mcount : (int64_t)live_in[g];
+        if (q0 >= groups[g].nstar) live = 0;
+        return (live + batch - 1) / batch;
+    };
+    const int chunk = (n_groups + nt - 1) / nt;
+    const int g0 = min(n_groups, t * chunk), g1 = min(n_groups, g0 + chunk);
+    int64_t sum = 0;
+    for (int g = g0; g < g1; ++g) sum += items(g);
+    part[t] = sum;
+    __syncthreads();
+    if (t == 0) {
         int64_t acc = 0;
-        const int64_t q0 = (int64_t)round * steps;
-        for (int g = 0; g < n_groups; ++g) {
-            batch_prefix[g] = acc;
-            int64_t live = round == 0 ? (int64_t)groups[g].node_count * mcount : (int64_t)live_in[g];
-            if (q0 >= groups[g].nstar) live = 0;
-            acc += (live + batch - 1) / batch;
-        }
+        for (int i = 0; i < nt; ++i) { const int64_t v = part[i]; part[i] = acc; acc += v; }
         batch_prefix[n_groups] = acc;
         *work = 0ull;
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int g = g0; g < g1; ++g) {
+        batch_prefix[g] = acc;
+        acc += items(g);
     }
 }
 
@@ -1935,7 +1951,7 @@ __global__ void slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t
             double lp = 0.0, lc = 1.0;
             for (int m = 0; m < T1; ++m) {
                 accq[m] = fma(val, lc, accq[m]);
-                const double nx = ((2.0 * m + 1.0) * xi * lc - m * lp) / (m + 1.0);
+                const double nx = c_rec.ad[m] * xi * lc - c_rec.bd[m] * lp;
                 lp = lc;
                 lc = nx;
             }
