@@ -539,11 +539,26 @@ static int or_node_info(const or_problem *pb, int interval, int64_t node, const 
     return 0;
 }
 
-/* One path of the residual estimator.  Reading R6: the time of step q runs
+/* eq. uast, the Picard form of the iteration: the integrand is f(u*) plus the
+ * source only (the linear part of the operator is carried by the walk) */
+static double or_picard_integrand(const or_problem *pb, int interval, const double *Ut,
+                                  const double *X, double tau)
+{
+    double t0 = pb->t_breaks[interval], h = pb->t_breaks[interval + 1] - t0;
+    double xi = 2.0 * (tau - t0) / h - 1.0;
+    double v[3];
+    or_eval(pb->dim, pb->n, pb->degree[interval], h, Ut, X, xi, v);
+    return or_f(pb, v[0]) + or_source(pb, X, tau);
+}
+
+/* One path of the estimator.  Reading R6: the time of step q runs
  * backward from the node, tau_q = t_{n,ell} - q*Delta.  eq. indexL / interIQ:
  * the jump X_{q+1} = X_q + J*dir (J = sqrt(2 d Delta), Lemma 2.1) is drawn
  * first; if X_{q+1} has left Omega the path stops (L = q) without adding the
- * last inside point, otherwise Delta*r(X_q, tau_q) is added and the walk moves. */
+ * last inside point, otherwise Delta*r(X_q, tau_q) is added and the walk moves.
+ * Picard form (eq. uast): r = f(u*) + s, and a path still inside after all N*
+ * steps (it reached t_{n-1}) adds the interval's initial data u*(X_{N*}, t_{n-1});
+ * a path that left Omega adds the boundary data g = 0. */
 static double or_path(const or_problem *pb, const double *Ut, int inst, int interval,
                       int iter_tag, int64_t node, const or_node *nd, int64_t sample, int64_t *L_out)
 {
@@ -565,8 +580,16 @@ static double or_path(const or_problem *pb, const double *Ut, int inst, int inte
         }
         if (outside) break;
         double tau = t0 + (nd->span - (double)q * nd->delta);
-        acc += nd->delta * or_residual(pb, interval, Ut, X, tau);
+        if (pb->estimator == OR_EST_PICARD)
+            acc += nd->delta * or_picard_integrand(pb, interval, Ut, X, tau);
+        else
+            acc += nd->delta * or_residual(pb, interval, Ut, X, tau);
         for (int i = 0; i < d; ++i) X[i] = Y[i];
+    }
+    if (pb->estimator == OR_EST_PICARD && q == nd->nstar) {
+        double h = pb->t_breaks[interval + 1] - t0, v[3];
+        or_eval(d, pb->n, pb->degree[interval], h, Ut, X, -1.0, v);   /* t = t_{n-1}: xi = -1 */
+        acc += v[0];
     }
     if (L_out) *L_out = q;
     return acc;
@@ -643,7 +666,8 @@ int or_estimate(const or_problem *pb, int inst, int interval, int iter_tag,
 }
 
 /* Algorithm 1, Steps 1-3 for one interval: reconstruct, estimate the residual
- * at every node (j, ell>=1), add it to the nodal values. */
+ * at every node (j, ell>=1), add it to the nodal values.  Picard form: the
+ * estimate replaces the nodal value and max_eps is the largest change. */
 int or_iterate(const or_problem *pb, int inst, int interval, int iter_tag,
                double *U, double *max_eps, int64_t *steps)
 {
@@ -659,8 +683,15 @@ int or_iterate(const or_problem *pb, int inst, int interval, int iter_tag,
     for (int64_t node = 0; node < nn; ++node) {
         int64_t jf = node % nsp;
         int ell = (int)(node / nsp) + 1;
-        U[jf * (M + 1) + ell] += eps[node];                /* Step 3 */
-        if (!(fabs(eps[node]) <= mx)) mx = fabs(eps[node]); /* NaN propagates */
+        double *u = &U[jf * (M + 1) + ell], change;
+        if (pb->estimator == OR_EST_PICARD) {
+            change = eps[node] - *u;
+            *u = eps[node];
+        } else {
+            change = eps[node];
+            *u += eps[node];                               /* Step 3 */
+        }
+        if (!(fabs(change) <= mx)) mx = fabs(change);     /* NaN propagates */
         tot += st[node];
     }
     if (max_eps) *max_eps = mx;

@@ -69,7 +69,12 @@ typedef struct {
     int32_t iters;            /* iterations per interval (or sweeps)            */
     int32_t fresh_per_iter;   /* 1: iteration tag in the counter, 0: tag = 0    */
     uint64_t seed;
+    int32_t estimator;        /* OR_EST_RESIDUAL or OR_EST_PICARD               */
 } or_problem;
+
+/* estimators: eq. varepsilon_1 (the residual increment, added to the iterate)
+ * or eq. uast (the Picard form: the iterate itself, replacing it) */
+enum { OR_EST_RESIDUAL = 0, OR_EST_PICARD = 1 };
 
 /* Philox4x32-10 block function (Salmon et al., SC'11). */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -38,7 +38,11 @@ class _Problem(C.Structure):
         ("f_param", C.c_double * 4), ("src_param", C.c_double * 8), ("ic_param", C.c_double * 4),
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
+        ("estimator", C.c_int32),
     ]
+
+
+ESTIMATORS = {"residual": 0, "picard": 1}
 
 
 _lib = None
@@ -191,6 +195,7 @@ class Problem:
         s.ic_data = (self.ic_data.ctypes.data_as(C.POINTER(C.c_double)) if self.ic_data is not None
                      else C.POINTER(C.c_double)())
         s.M, s.iters, s.fresh_per_iter, s.seed = wl.M, wl.iters, int(wl.fresh_per_iter), wl.seed
+        s.estimator = ESTIMATORS[getattr(wl, "estimator", "residual")]
         self.s = s
 
     @property

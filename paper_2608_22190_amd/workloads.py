@@ -46,6 +46,7 @@ class Workload:
     precision: str = "fp64"     # "fp64" or "fp32" (path sampling precision)
     exact_known: bool = True
     tol: float = 0.0            # > 0: stop an interval once max|eps| < tol (Algorithm 1's loop condition)
+    estimator: str = "residual" # "residual" (eq. varepsilon_1) or "picard" (eq. uast, classical MC form)
 
     @property
     def n_intervals(self):

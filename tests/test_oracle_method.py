@@ -128,6 +128,96 @@ def test_estimator_matches_bruteforce_expectation():
     assert checked >= 3
 
 
+def _dp_picard(pb, Ut, x0, t_ell, t0, h, nstar, M, terminal=True, integrand="picard"):
+    """exact expectation of the Picard-form path value (eq. uast) for the 1-D
+    sign walk: sum over q < L of Delta (f(u*) + s)(X_q, tau_q), plus u*(X_{N*},
+    t_{n-1}) for walks still inside after N* steps (g = 0 on exit)"""
+    span = t_ell - t0
+    delta = span / nstar
+    J = math.sqrt(2 * delta)
+    p = {0: 1.0}
+    total = 0.0
+    for q in range(nstar):
+        tau = t0 + span - q * delta
+        xi = 2 * (tau - t0) / h - 1
+        nxt = {}
+        for k, pr in p.items():
+            xq = x0 + J * k
+            u, ut, lap = O.evaluate(1, pb.wl.n, M, h, Ut, [xq], xi)
+            r = pb.f(u) + pb.source([xq], tau) + (lap - ut if integrand == "residual" else 0.0)
+            for s in (-1, 1):
+                y = xq + J * s
+                if abs(y) >= 1.0:
+                    continue
+                total += 0.5 * pr * delta * r
+                nxt[k + s] = nxt.get(k + s, 0.0) + 0.5 * pr
+        p = nxt
+    if terminal:
+        for k, pr in p.items():
+            total += pr * O.evaluate(1, pb.wl.n, M, h, Ut, [x0 + J * k], -1.0)[0]
+    return total
+
+
+def test_picard_estimator_matches_bruteforce_expectation():
+    """eq. uast on the 1-D lattice walk: the oracle's Monte Carlo mean agrees with
+    the exact expectation, and the test rejects a dropped terminal term and the
+    residual integrand."""
+    nstar = 12
+    wl = W.small(dim=1, n=6, M_deg=3, M=40000, T=0.6, nstar=nstar, f="u_minus_u3", src="sin_decay",
+                 estimator="picard")
+    pb = O.Problem(wl)
+    x, t = pb.grid(0)
+    rng = np.random.default_rng(3)
+    U = rng.standard_normal((pb.nsp, 4)) * 0.5
+    Ut = O.reconstruct(1, wl.n, 3, U.reshape(-1))
+    rejected = 0
+    for jf, ell in [(0, 3), (2, 2), (3, 1), (5, 3)]:
+        node = jf + pb.nsp * (ell - 1)
+        est, ssq, _ = pb.estimate(U, nodes=[node])
+        se = math.sqrt(max(ssq[0] / wl.M - est[0] ** 2, 0.0) / wl.M)
+        ref = _dp_picard(pb, Ut, x[jf], t[ell], 0.0, 0.6, nstar, 3)
+        assert abs(est[0] - ref) < 4 * se + 1e-14, (jf, ell, est[0], ref, se)
+        for alt in (_dp_picard(pb, Ut, x[jf], t[ell], 0.0, 0.6, nstar, 3, terminal=False),
+                    _dp_picard(pb, Ut, x[jf], t[ell], 0.0, 0.6, nstar, 3, integrand="residual")):
+            if abs(alt - ref) > 12 * se:
+                rejected += 1
+                assert abs(est[0] - alt) > 6 * se
+    assert rejected >= 4
+
+
+def test_picard_iteration_replaces_the_iterate():
+    """One Picard iteration sets every node (l >= 1) to its estimate and keeps the
+    initial column; max|eps| is the largest change."""
+    wl = W.small(dim=1, n=5, M_deg=3, M=64, T=0.5, nstar=20, f="sin", src="sin_decay", estimator="picard")
+    pb = O.Problem(wl)
+    U0 = np.random.default_rng(4).standard_normal((pb.nsp, 4)) * 0.3
+    est, _, _ = pb.estimate(U0.reshape(-1))
+    U1, mx, _ = pb.iterate(U0.reshape(-1))
+    U1 = U1.reshape(pb.nsp, 4)
+    assert np.array_equal(U1[:, 0], U0[:, 0])
+    assert np.array_equal(U1[:, 1:].T.reshape(-1), est)
+    assert mx == np.max(np.abs(U1 - U0))
+
+
+def test_residual_form_removes_the_bias_the_picard_form_keeps():
+    """The classical (Picard) estimator carries the discrete walk's bias (exit
+    monitoring at steps of J = sqrt(2 Delta), left-point quadrature), so its
+    fixed point stays O(J) away from the solution; the residual form's
+    integrand vanishes at its fixed point, which therefore carries no such bias
+    (the paper's contrast between classical MC and the hp method)."""
+    wl = W.small(dim=1, n=8, M_deg=4, M=2000, iters=8, T=0.5, f="u_minus_u3", src="sin_decay")
+    res = {}
+    for est in ("residual", "picard"):
+        pb = O.Problem(wl.with_(estimator=est))
+        U, _ = pb.solve()
+        x, t = pb.grid(0)
+        ex = np.array([[pb.exact([xj], tl) for tl in t] for xj in x])
+        res[est] = np.max(np.abs(U[0].reshape(wl.nsp, -1) - ex))
+    J = math.sqrt(2 * 0.5 / max(wl.nstar))
+    assert res["residual"] < 1e-3, res
+    assert res["picard"] > 20 * res["residual"] and res["picard"] < 5 * J, (res, J)
+
+
 def test_sample_path_matches_estimate_and_is_reproducible():
     wl = W.small(dim=2, n=4, M_deg=3, M=16, T=0.4, src="longtime", f="sin", nstar=50)
     pb = O.Problem(wl)
