@@ -82,6 +82,15 @@ enum { HPSMC_SEQUENTIAL = 0,      /* Algorithm 1: intervals one after another   
                                      takes its initial column from interval n-1's
                                      last column of the previous sweep            */
 
+enum { HPSMC_EST_RESIDUAL = 0,    /* eq. varepsilon_1: the Monte Carlo estimate of the
+                                     residual increment eps, added to the iterate  */
+       HPSMC_EST_PICARD = 1 };    /* eq. uast: the Picard (classical Monte Carlo) form
+                                     -- integrand f(u*) + s, plus the interval's
+                                     initial data at the end point of paths that stay
+                                     inside for all N* steps; the estimate replaces
+                                     the iterate (eps = its change).  Vector-unit
+                                     round kernel only; no gradient               */
+
 enum { HPSMC_FP64 = 0,            /* everything in FP64                            */
        HPSMC_FP32_SAMPLING = 1 }; /* paths and basis evaluation in FP32 with
                                      compensated accumulation; reconstruction,
@@ -104,7 +113,7 @@ typedef struct {
     int32_t fresh_per_iter;    /* 1: new samples each iteration, 0: reuse       */
     uint64_t seed;
     int32_t precision;         /* HPSMC_FP64 or HPSMC_FP32_SAMPLING            */
-    int32_t reserved;
+    int32_t estimator;         /* HPSMC_EST_RESIDUAL (default) or HPSMC_EST_PICARD */
     double tol;                /* 0: exactly `iters` iterations per interval (or
                                   sweeps), asynchronous.  > 0: Algorithm 1's loop
                                   condition -- an interval stops once max|eps| <

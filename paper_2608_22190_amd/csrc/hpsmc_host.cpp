@@ -384,6 +384,7 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     if (pb->schedule < 0 || pb->schedule > 1) return fail(HPSMC_EINVAL, "unknown schedule");
     if (pb->precision < 0 || pb->precision > 1) return fail(HPSMC_EINVAL, "unknown precision");
     if (!std::isfinite(pb->tol) || pb->tol < 0.0) return fail(HPSMC_EINVAL, "tol must be finite and >= 0");
+    if (pb->estimator < 0 || pb->estimator > 1) return fail(HPSMC_EINVAL, "unknown estimator");
     if ((pb->ic_kind == HPSMC_IC_PHI || pb->ic_kind == HPSMC_IC_NODAL) && !pb->ic_data)
         return fail(HPSMC_EINVAL, "ic_data is NULL");
     if (pb->ic_kind == HPSMC_IC_EXACT && pb->src_kind == HPSMC_SRC_NONE)
@@ -441,7 +442,8 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     const int64_t rows = ipow(plan->P, d - 1);
     const int64_t stride = rows * 2 * plan->PP;
     // plans the matrix-core round kernel can serve also get offsets in its slab layout
-    const bool mma_ok = advance_mma_eligible(plan->fp32, d, plan->P, 0, 1, 4);
+    const bool mma_ok = advance_mma_eligible(plan->fp32, d, plan->P, 0, 1, 4) && plan->pb.estimator == HPSMC_EST_RESIDUAL;
+    const int extra = plan->pb.estimator == HPSMC_EST_PICARD ? 1 : 0;   // the slab of q = N* (t = t_{n-1})
     const int64_t mstride = mma_slab_elems(plan->PP);
     int64_t slab_pos = 0, slab_pos_mma = 0, out = 0;
     // canonical output order: [iv][inst][node id]
@@ -481,7 +483,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
                     nd.out = (int32_t)(out + inst * plan->nsp * M + (int64_t)(l - 1) * plan->nsp + j);
                     set.host.push_back(nd);
                 }
-                slab_pos += (int64_t)ns * stride;
+                slab_pos += (int64_t)(ns + extra) * stride;
                 if (mma_ok) slab_pos_mma += (int64_t)ns * mstride;
             }
         }
@@ -550,6 +552,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     sa.slab_off_mma = mma_ok ? (const int64_t *)(gb + G * 48) : nullptr;
     sa.mma_stride = mstride;
     sa.layout = 0;
+    sa.extra = extra;
     sa.n_groups = set.n_groups;
     sa.P = plan->P;
     sa.PP = plan->PP;
@@ -657,6 +660,7 @@ static Physics physics_of(const hpsmc_plan *plan)
     ph.dim = plan->d;
     ph.f_kind = plan->pb.f_kind;
     ph.src_kind = plan->pb.src_kind;
+    ph.picard = plan->pb.estimator == HPSMC_EST_PICARD;
     memcpy(ph.f_param, plan->pb.f_param, sizeof(ph.f_param));
     memcpy(ph.src_param, plan->pb.src_param, sizeof(ph.src_param));
     return ph;
@@ -740,7 +744,8 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     if (ek) HIP_TRY(hipEventRecord(ek->b, s));
     plan->n_advance += (int64_t)R * ((plan->pb.M + set.ms - 1) / set.ms);
     unsigned long long *mb = plan->maxbits + std::min(record, 4095);
-    HIP_TRY(launch_reduce_update(plan->part, 1, set.dev, set.n, plan->pb.M, plan->U, set.eps, set.sumsq, mb, s));
+    HIP_TRY(launch_reduce_update(plan->part, 1, plan->pb.estimator == HPSMC_EST_PICARD, set.dev, set.n, plan->pb.M,
+                                 plan->U, set.eps, set.sumsq, mb, s));
     plan->node_samples += set.n * plan->pb.M;
     plan->n_records = std::max(plan->n_records, std::min(record, 4095) + 1);
     return HPSMC_OK;
@@ -757,6 +762,8 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
     HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
     if (es) HIP_TRY(hipEventRecord(es->b, s));
     if (set.rounds) return sample_rounds(plan, set, tag, record, s);
+    if (plan->pb.estimator != HPSMC_EST_RESIDUAL)
+        return fail(HPSMC_ENOTSUP, "the Picard form needs the round kernel (slab too large for LDS chunks)");
     HIP_TRY(launch_fill_u64(plan->counters, 1, 0ull, s));
     SampleArgs a{};
     a.nodes = set.dev;
@@ -786,7 +793,7 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
     HIP_TRY(launch_sample(a, plan->fp32, ns, plan->launch.waves_per_block, blocks, s));
     if (ek) HIP_TRY(hipEventRecord(ek->b, s));
     unsigned long long *mb = plan->maxbits + std::min(record, 4095);
-    HIP_TRY(launch_reduce_update(plan->part, a.chunks_per_node, set.dev, set.n, plan->pb.M, plan->U, set.eps,
+    HIP_TRY(launch_reduce_update(plan->part, a.chunks_per_node, 0, set.dev, set.n, plan->pb.M, plan->U, set.eps,
                                  set.sumsq, mb, s));
     plan->node_samples += set.n * plan->pb.M;
     plan->n_records = std::max(plan->n_records, std::min(record, 4095) + 1);
@@ -1396,10 +1403,12 @@ static std::string tune_key(const hpsmc_plan *plan, int iv, int64_t M)
         if (c != std::string::npos) arch = arch.substr(0, c);
     }
     // plans that may run the matrix-core round kernel tune separately from those that may not
-    const bool mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
+    const bool picard = plan->pb.estimator == HPSMC_EST_PICARD;
+    const bool mma = plan->sample_mma && !picard && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
     char buf[256];
-    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
-             plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", (long long)M, plan->n_inst, arch.c_str());
+    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
+             plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", picard ? "_picard" : "", (long long)M, plan->n_inst,
+             arch.c_str());
     return buf;
 }
 
@@ -1756,6 +1765,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
         return fail(HPSMC_EINVAL, "the gradient needs one interval, phi-coefficient initial data, sequential schedule");
     if (plan->d > 2 || plan->P > 32 || !plan->sets[0].rounds)
         return fail(HPSMC_ENOTSUP, "the adjoint kernel covers dim <= 2 and n <= 30");
+    if (plan->pb.estimator != HPSMC_EST_RESIDUAL) return fail(HPSMC_ENOTSUP, "the adjoint is that of the residual form");
     hipStream_t s = (hipStream_t)stream;
     const int d = plan->d, n = plan->n, P = plan->P, K = plan->pb.iters, T1 = plan->degree[0] + 1;
     const int64_t I = plan->n_inst, nsp = plan->nsp, psp = plan->psp;

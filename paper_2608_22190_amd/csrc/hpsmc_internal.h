@@ -42,7 +42,8 @@ struct GroupDesc {
 
 // Problem constants every sampling lane needs.
 struct Physics {
-    int32_t dim, f_kind, src_kind, pad;
+    int32_t dim, f_kind, src_kind;
+    int32_t picard;              // 1: Picard-form estimator (eq. uast)
     double f_param[4];
     double src_param[8];
 };
@@ -115,6 +116,7 @@ struct SlabArgs {
     const int64_t *slab_off_mma; // the same in the matrix-core layout (null when not available)
     int64_t mma_stride;          // elements per slab in the matrix-core layout
     int32_t layout;              // 0: rows [k0][u: PP][v: PP]; 1: matrix-core layout
+    int32_t extra;               // slabs past N* per group (1 for the Picard form: q = N*, t_{n-1})
     const double *span;          // per group: t_{n,l} - t_{n-1}
     const double *delta;         // per group: Delta_{n,l}
     const double *h2;            // per group: 2 / h_n
@@ -133,7 +135,7 @@ hipError_t launch_mode_product(const double *in, double *out, int64_t outer, int
 hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t s);
 hipError_t launch_sample(const SampleArgs &a, int fp32, int samples_per_lane, int waves_per_block,
                          int blocks, hipStream_t s);
-hipError_t launch_reduce_update(const double *part, int chunks, const NodeDesc *nodes, int64_t n_nodes,
+hipError_t launch_reduce_update(const double *part, int chunks, int picard, const NodeDesc *nodes, int64_t n_nodes,
                                 int64_t M, double *U, double *eps, double *sumsq,
                                 unsigned long long *maxbits, hipStream_t s);
 hipError_t launch_start_columns(double *U, const double *src, int64_t src_stride, int64_t src_off,

@@ -632,7 +632,7 @@ __global__ void slab_kernel(SlabArgs a)
     const bool mma = a.layout == 1;
     const int64_t stride = mma ? a.mma_stride : a.slab_stride;
     const int64_t base = mma ? a.slab_off_mma[g] : a.slab_off[g];
-    const int64_t total = (int64_t)nstar * stride;
+    const int64_t total = (int64_t)(nstar + a.extra) * stride;
     T *table = (T *)a.slab_table;
     const double *cu = a.cu + a.coef_off[g], *cv = a.cv + a.coef_off[g];
     const double span = a.span[g], delta = a.delta[g], h2 = a.h2[g];
@@ -673,7 +673,7 @@ __global__ void slab_kernel(SlabArgs a)
 hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t s)
 {
     if (a.n_groups <= 0) return hipSuccess;
-    int64_t per = (int64_t)max_nstar * (a.layout == 1 ? a.mma_stride : a.slab_stride);
+    int64_t per = (int64_t)(max_nstar + a.extra) * (a.layout == 1 ? a.mma_stride : a.slab_stride);
     int64_t bx = (per + 255) / 256;
     if (bx > 16384) bx = 16384;
     dim3 grid((unsigned)bx, (unsigned)a.n_groups);
@@ -687,7 +687,8 @@ hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t 
 // ---------------------------------------------------------------------------
 // eps = (1/M) sum of the chunk sums in chunk order; U += eps; max|eps|.
 // ---------------------------------------------------------------------------
-__global__ void reduce_update_kernel(const double *__restrict__ part, int chunks, const NodeDesc *__restrict__ nodes,
+__global__ void reduce_update_kernel(const double *__restrict__ part, int chunks, int picard,
+                                     const NodeDesc *__restrict__ nodes,
                                      int64_t n_nodes, int64_t M, double *__restrict__ U, double *__restrict__ eps,
                                      double *__restrict__ sumsq, unsigned long long *maxbits)
 {
@@ -698,10 +699,16 @@ __global__ void reduce_update_kernel(const double *__restrict__ part, int chunks
         const double *p = part + (int64_t)nd.out * chunks * 2;
         double s1 = 0.0, s2 = 0.0;
         for (int c = 0; c < chunks; ++c) { s1 += p[2 * c]; s2 += p[2 * c + 1]; }
-        const double e = s1 / (double)M;
+        double e = s1 / (double)M;
+        if (picard) {   // eq. uast: the estimate replaces the iterate; eps is the change
+            const double uo = U[nd.u_index];
+            U[nd.u_index] = e;
+            e -= uo;
+        } else {
+            U[nd.u_index] += e;
+        }
         eps[nd.out] = e;
         sumsq[nd.out] = s2;
-        U[nd.u_index] += e;
         mx = fabs(e);
         if (!(mx == mx)) mx = __longlong_as_double(0x7ff8000000000000ll);
     }
@@ -719,12 +726,13 @@ __global__ void reduce_update_kernel(const double *__restrict__ part, int chunks
     if (threadIdx.x == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
-hipError_t launch_reduce_update(const double *part, int chunks, const NodeDesc *nodes, int64_t n_nodes, int64_t M,
+hipError_t launch_reduce_update(const double *part, int chunks, int picard, const NodeDesc *nodes, int64_t n_nodes,
+                                int64_t M,
                                 double *U, double *eps, double *sumsq, unsigned long long *maxbits, hipStream_t s)
 {
     if (n_nodes <= 0) return hipSuccess;
     hipLaunchKernelGGL(reduce_update_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, part, chunks,
-                       nodes, n_nodes, M, U, eps, sumsq, maxbits);
+                       picard, nodes, n_nodes, M, U, eps, sumsq, maxbits);
     return hipGetLastError();
 }
 
@@ -1254,7 +1262,8 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (alive[s]) {
-                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D>(a.phys, X[s], tf) + v[s];
+                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D>(a.phys, X[s], tf) +
+                                    (a.phys.picard ? (T)0 : v[s]);
                         const T y = delta * r;
                         if constexpr (sizeof(T) == 4) {
                             const T yc = y - comp[s];
@@ -1271,6 +1280,75 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                 }
             }
             if (__syncthreads_or(any_live ? 1 : 0) == 0) { ++q; break; }
+        }
+
+        // ---- Picard form (eq. uast): a path still inside after all N* steps has
+        // reached t_{n-1} and adds the interval's initial data u*(X_{N*}, t_{n-1}),
+        // the slab of step N* (xi = -1), streamed through LDS like any step
+        if (a.phys.picard && q1 == nstar && q == q1) {
+            bool any_live = false;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) any_live = any_live || alive[s];
+            const bool wave_live = __ballot(any_live) != 0ull;
+            T Ll[NS][PMAX], u[NS], v[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const T x = X[s][D - 1];
+                Ll[s][0] = (T)1;
+                if (PMAX > 1) Ll[s][1] = x;
+#pragma unroll
+                for (int k = 1; k + 1 < PMAX; ++k)
+                    Ll[s][k + 1] = (T)((2.0 * k + 1.0) / (k + 1.0)) * x * Ll[s][k] - (T)(k / (k + 1.0)) * Ll[s][k - 1];
+                u[s] = (T)0;
+                v[s] = (T)0;
+            }
+            for (int c = 0; c < NC; ++c) {
+                __syncthreads();   // every read of the buffer is over
+                const u32x4 *src = (const u32x4 *)(gtab + (int64_t)nstar * a.slab_stride + (int64_t)c * a.chunk_elems);
+#pragma unroll
+                for (int k = 0; k < NSTG; ++k) {
+                    const int64_t vv = tid + (int64_t)k * nthr;
+                    if (vv < nvec) lds[vv] = src[vv];
+                }
+                __syncthreads();
+                if (wave_live) {
+                    T Wc[NS];
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) Wc[s] = (T)1;
+                    if constexpr (CF > 0) {
+                        int rem = c;
+#pragma unroll
+                        for (int i = CF - 1; i >= 0; --i) {
+                            const int ki = rem % a.P;
+                            rem /= a.P;
+#pragma unroll
+                            for (int s = 0; s < NS; ++s) {
+                                T lp = (T)0, lc = (T)1;
+                                for (int m = 0; m < ki; ++m) {
+                                    const T nx = rec_a<T>(m) * X[s][i] * lc - rec_b<T>(m) * lp;
+                                    lp = lc;
+                                    lc = nx;
+                                }
+                                Wc[s] *= lc;
+                            }
+                        }
+                    }
+                    contract<T, D, PMAX, NS, CF, const T *>((const T *)lds, a.P, a.PP, X, Wc, Ll, u, v, 0);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (alive[s]) {
+                    if constexpr (sizeof(T) == 4) {
+                        const T yc = u[s] - comp[s];
+                        const T tt = acc[s] + yc;
+                        comp[s] = (tt - acc[s]) - yc;
+                        acc[s] = tt;
+                    } else {
+                        acc[s] += u[s];
+                    }
+                }
+            }
         }
 
         // ---- paths alive after the round: finished at N*, or carried to the next round

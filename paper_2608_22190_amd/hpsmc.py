@@ -24,6 +24,7 @@ SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4
 IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
 SCHEDULES = {"sequential": 0, "sweeps": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
+ESTIMATORS = {"residual": 0, "picard": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSUP", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED", -6: "ENOTCONVERGED"}
 ENOTCONVERGED = -6
 
@@ -42,7 +43,7 @@ class hpsmc_problem(C.Structure):
         ("f_param", C.c_double * 4), ("src_param", C.c_double * 8), ("ic_param", C.c_double * 4),
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
-        ("precision", C.c_int32), ("reserved", C.c_int32), ("tol", C.c_double),
+        ("precision", C.c_int32), ("estimator", C.c_int32), ("tol", C.c_double),
     ]
 
 
@@ -155,6 +156,7 @@ def make_problem(wl):
     p.M, p.iters, p.fresh_per_iter, p.seed = wl.M, wl.iters, int(wl.fresh_per_iter), wl.seed
     p.precision = PRECISIONS[wl.precision]
     p.tol = float(getattr(wl, "tol", 0.0))
+    p.estimator = ESTIMATORS[getattr(wl, "estimator", "residual")]
     return p, [tb, deg, ns, ic]
 
 

@@ -1,0 +1,102 @@
+"""The Picard (classical Monte Carlo) form of the estimator, eq. uast, on the GPU
+against the FP64 oracle on identical Philox samples: per-sample path values
+(integrand f(u*) + s, the interval's initial data at the end point of paths
+that stay inside for all N* steps, g = 0 on exit), iterates after the
+replacing update, identical residual-evaluation counts; sequential intervals
+(the terminal data come from the previous interval's last column), sweeps,
+LDS-chunked slabs, and the FP32 form within the Monte Carlo noise."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2608_22190_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _hp():
+    from paper_2608_22190_amd import hpsmc
+    return hpsmc
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("dim,n,deg,M,ns,nstar", [
+    (1, 6, 4, 150, 1, 40), (1, 9, 3, 97, 2, None), (2, 4, 3, 96, 2, 60), (2, 5, 2, 65, 4, None),
+    (3, 3, 2, 70, 1, 30), (4, 2, 2, 40, 2, 20), (5, 2, 2, 33, 1, 12)])
+def test_picard_iteration_matches_oracle_fp64(dim, n, deg, M, ns, nstar):
+    H = _hp()
+    wl = W.small(dim=dim, n=n, M_deg=deg, M=M, T=0.5, f="sin", src="longtime", estimator="picard", nstar=nstar)
+    _say("picard iteration", dim, n, deg, M, ns)
+    U = np.random.default_rng(dim + 10).standard_normal((1, wl.nsp, deg + 1)) * 0.4
+    with H.Plan(wl) as plan:
+        plan.hpsmc_set_launch(ns, 2, 4)
+        assert plan.hpsmc_get_option("sample_mfma_active") == 0
+        plan.hpsmc_set_probe(min(M, 6))
+        plan.hpsmc_set_nodes(0, U)
+        plan.hpsmc_iterate(0, 1)
+        Ug = plan.hpsmc_get_nodes(0)[0]
+        eps_g, _ = plan.hpsmc_get_increment(0)
+        pr = plan.hpsmc_get_probe(0)[0]
+        st = plan.hpsmc_stats()
+    pb = O.Problem(wl)
+    Uo, mx, steps = pb.iterate(U[0].reshape(-1), iter_tag=1)
+    Uo = Uo.reshape(wl.nsp, deg + 1)
+    scale = max(1.0, np.max(np.abs(Uo)))
+    assert np.max(np.abs(Ug - Uo)) <= TOL * scale
+    assert np.array_equal(Ug[:, 0], U[0][:, 0])
+    assert np.max(np.abs(eps_g[0] - (Uo - U[0])[:, 1:].T.reshape(-1))) <= TOL * scale
+    assert st["path_steps"] == steps
+    Ut = O.reconstruct(dim, n, deg, U[0].reshape(-1))
+    for node in np.random.default_rng(3).choice(pr.shape[0], size=min(5, pr.shape[0]), replace=False):
+        for smp in range(pr.shape[1]):
+            S, _ = pb.sample_path(Ut, 0, 0, 1, int(node), smp)
+            assert abs(pr[node, smp] - S) <= TOL * (1 + abs(S))
+
+
+def test_picard_solve_intervals_and_sweeps_match_oracle_fp64():
+    H = _hp()
+    _say("picard solves")
+    for wl in [W.small(dim=1, n=6, M_deg=[3, 4], M=120, iters=3, T=0.8, n_intervals=2, estimator="picard",
+                       f="u_minus_u3", src="sin_decay"),
+               W.small(dim=2, n=4, M_deg=[2, 3, 2], M=64, iters=4, T=0.6, n_intervals=3, estimator="picard",
+                       schedule="sweeps", f="sin", src="longtime")]:
+        with H.Plan(wl) as plan:
+            plan.hpsmc_solve()
+            got = [plan.hpsmc_get_nodes(iv)[0] for iv in range(wl.n_intervals)]
+        Uo, _ = O.Problem(wl).solve()
+        for iv in range(wl.n_intervals):
+            assert np.max(np.abs(got[iv] - Uo[iv])) <= TOL * max(1.0, np.max(np.abs(Uo[iv]))), (wl.schedule, iv)
+
+
+def test_picard_fp32_within_monte_carlo_noise():
+    H = _hp()
+    wl = W.small(dim=2, n=5, M_deg=3, M=512, iters=3, T=0.5, f="sin", src="longtime", estimator="picard")
+    _say("picard fp32")
+    res = {}
+    for prec in ("fp64", "fp32"):
+        with H.Plan(wl.with_(precision=prec)) as plan:
+            plan.hpsmc_set_launch(1, 4, 4)
+            assert plan.hpsmc_get_option("sample_mfma_active") == 0
+            plan.hpsmc_solve()
+            res[prec] = plan.hpsmc_get_nodes(0)[0]
+            _, ssq = plan.hpsmc_get_increment(0)
+            if prec == "fp64":
+                U = res[prec]
+                sig = np.sqrt(np.maximum(ssq[0] / wl.M - (U[:, 1:].T.reshape(-1)) ** 2, 0) / wl.M).max()
+    d = np.max(np.abs(res["fp32"] - res["fp64"]))
+    print(f"|u32-u64|={d:.3e} sigma={sig:.3e}")
+    assert d <= 3 * sig + 1e-5
+
+
+def test_picard_has_no_gradient():
+    H = _hp()
+    wl = W.small(dim=2, n=3, M_deg=2, M=16, ic="phi", ic_data=np.zeros((1, 9)), src="longtime", f="sin",
+                 estimator="picard")
+    with H.Plan(wl) as plan:
+        with pytest.raises(H.HpsmcError) as ei:
+            plan.hpsmc_loss_grad_c0(np.zeros((1, 9)))
+        assert ei.value.status == -2
