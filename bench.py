@@ -52,13 +52,14 @@ def measured_traffic(launch):
     return 1024.0 * (rec["fetch_kib_per_launch"] * rec["fetch_factor"] + rec["write_kib_per_launch"] * rec["write_factor"])
 
 
-def flops_per_eval(dim, P):
+def flops_per_eval(dim, P, picard=False):
     """Algorithmic FP operations of one residual evaluation: the nested
     tensor-product contraction of the u and v slabs (2 polynomials x 2 flops x
     (P^d + P^{d-1} + ... + P) multiply-adds) plus the three-term recurrences of
-    the d coordinates (3 flops per new Legendre value)."""
+    the d coordinates (3 flops per new Legendre value).  The Picard-form
+    integrand f(u*) + s needs the u slab only (one polynomial)."""
     cont = sum(P ** k for k in range(1, dim + 1))
-    return 4 * cont + 3 * dim * (P - 2)
+    return (2 if picard else 4) * cont + 3 * dim * (P - 2)
 
 
 def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256):
@@ -127,8 +128,12 @@ def run_other(name, args, torch):
     from paper_2608_22190_amd import hpsmc, workloads as W
     stream = torch.cuda.Stream()
     m = args.m_slice
+    if name == "compare":
+        return run_compare(args, torch)
     if name == "c1":
         wl = W.c1_single_step()
+    elif name == "c2p":
+        wl = W.c2_long_time(M=m, iters=args.steps + args.warmup, n_intervals=1, estimator="picard")
     elif name == "c3":
         wl = W.c3_initial_singularity(M=m, sweeps=args.steps + args.warmup)
     elif name == "c4":
@@ -139,14 +144,16 @@ def run_other(name, args, torch):
     with hpsmc.Plan(wl) as plan:
         if args.launch:
             plan.hpsmc_set_launch(*(int(v) for v in args.launch.split(",")))
-        elif args.tune_cache and name in ("c3", "c4", "c5"):
+        elif args.tune_cache and name in ("c2p", "c3", "c4", "c5"):
             t0 = time.perf_counter()
-            plan.hpsmc_tune(0, min(wl.M, 4), args.tune_cache, stream=stream)
+            plan.hpsmc_tune(0, 256 if name == "c2p" else min(wl.M, 4), args.tune_cache, stream=stream)
             print(f"[bench] {name} launch {plan.hpsmc_get_launch()} ({time.perf_counter() - t0:.1f}s)",
                   file=sys.stderr, flush=True)
         def step(k):
             if name == "c1":
                 plan.hpsmc_solve(stream=stream)
+            elif name == "c2p":
+                plan.hpsmc_iterate(0, k, stream=stream)
             elif name == "c3":
                 plan.hpsmc_sweep(k, stream=stream)
             elif name == "c4":
@@ -172,10 +179,12 @@ def run_other(name, args, torch):
         mma = plan.hpsmc_get_option("sample_mfma_active")
     per_step = nodes * wl.M * (wl.iters if name in ("c1", "c5") else 1)
     P = wl.n + 2
-    fpe = flops_per_eval(wl.dim, P)
+    fpe = flops_per_eval(wl.dim, P, picard=wl.estimator == "picard")
     k_ms = st["sample_ms"] / max(1, st["sample_launches"])
     launches = max(1, st["advance_launches"] or st["sample_launches"])
     desc = {"c1": "c1_1d_single_step: whole solve (5 iterations, 256 nodes x M=4096), FP64, hipGraph replay",
+            "c2p": f"c2_2d_long_time interval 1, one Picard-form (classical Monte Carlo, eq. uast) iteration, "
+                   f"{nodes} nodes x samples 0..{m - 1} of M=65536, FP32 sampling",
             "c3": f"c3_2d_initial_singularity: one sweep over all 12 geometric intervals ({nodes} nodes, "
                   f"degrees 4..26) x samples 0..{m - 1} of M=32768, FP32",
             "c4": f"c4_5d: one residual iteration, {nodes} nodes (8^5 x 8) x samples 0..{m - 1} of M=16384, FP32",
@@ -197,6 +206,43 @@ def run_other(name, args, torch):
     out["path_steps_per_s"] = st["path_steps"] / sec
     out["mean_path_length"] = st["path_steps"] / max(1, st["node_samples"])
     print(json.dumps(out), flush=True)
+
+
+def run_compare(args, torch):
+    """The paper's contrast between the classical (Picard-form) Monte Carlo
+    estimator and the residual form, on one partition: the 1-D long-time
+    problem u_t = u_xx + sin u + s to T = 10 in unit intervals (u_ex =
+    (1-x^2) sin x e^{cos t}/(1+t^2)), 16 nodes, degree 16 in time, M = 4096,
+    6 iterations per interval, FP64; error against u_ex at every node."""
+    from paper_2608_22190_amd import hpsmc, workloads as W
+    tb = [float(k) for k in range(11)]
+    base = W._mk("long_time_1d", 1, 16, tb, [16] * 10, f="sin", src="longtime", ic="exact", M=4096, iters=6,
+                 seed=0, precision="fp64")
+    out = {}
+    for est in ("residual", "picard"):
+        wl = base.with_(estimator=est)
+        with hpsmc.Plan(wl) as plan:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.hpsmc_solve()
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            errs = []
+            for iv in range(10):
+                x, t = plan.hpsmc_grid(iv)
+                ex = ((1 - x ** 2) * np.sin(x))[:, None] * (np.exp(np.cos(t)) / (1 + t ** 2))[None, :]
+                errs.append(float(np.max(np.abs(plan.hpsmc_get_nodes(iv)[0] - ex))))
+        out[est] = {"seconds": sec, "max_error_per_interval": errs, "max_error": max(errs)}
+        print(f"[bench] compare {est}: {sec:.2f}s, max error {max(errs):.3e}", file=sys.stderr, flush=True)
+    ns = base.nodes_per_sweep * base.M * base.iters
+    line = {"metric": METRIC, "value": ns / out["residual"]["seconds"], "unit": "node-samples/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": 1e3 * out["residual"]["seconds"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "1-D long-time problem to T=10 in unit intervals, residual form against the "
+                                   "Picard (classical Monte Carlo) form, 16 x 16 nodes per interval, M=4096, "
+                                   "6 iterations per interval, FP64"},
+            "comparison": out}
+    print(json.dumps(line), flush=True)
 
 
 def cpu_baseline(wl, budget_s=20.0):
@@ -233,7 +279,7 @@ def main():
     ap.add_argument("--m-slice", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "compare"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--launch", type=str, default="",

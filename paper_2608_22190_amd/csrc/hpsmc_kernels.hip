@@ -273,10 +273,12 @@ __device__ __forceinline__ T source_of(const Physics &ph, const T (&X)[D], T t)
 // The last dimension's L values sit in registers (Ll); the outer dimensions
 // run as loops whose L values advance by the recurrence on the fly.  Slab rows
 // are wave-uniform: [u: PP][v: PP] per multi-index of the first d-1 dims.
+// uo (wave-uniform) skips the v half: the Picard-form integrand needs u only.
 // ---------------------------------------------------------------------------
 template <typename T, int D, int PMAX, int NS, int LV, typename SP>
 __device__ __forceinline__ void contract(SP S, int P, int PP, const T (&X)[NS][D], const T (&W)[NS],
-                                         const T (&Ll)[NS][PMAX], T (&u)[NS], T (&v)[NS], int row)
+                                         const T (&Ll)[NS][PMAX], T (&u)[NS], T (&v)[NS], int row,
+                                         bool uo = false)
 {
     if constexpr (LV == D - 1) {
         // rows are padded with zeros to a multiple of 4 modes and read 4 at a time
@@ -284,6 +286,30 @@ __device__ __forceinline__ void contract(SP S, int P, int PP, const T (&X)[NS][D
         T tu[NS], tv[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) { tu[s] = (T)0; tv[s] = (T)0; }
+        if (uo) {
+#pragma unroll
+            for (int kb = 0; kb < PMAX / 4; ++kb) {
+                if (kb * 4 < P) {
+                    T cu[4];
+                    if constexpr (std::is_same<SP, const T *>::value) {
+                        typedef T v4 __attribute__((ext_vector_type(4)));
+                        const v4 qu = *(const v4 *)(srow + 4 * kb);
+                        cu[0] = qu.x; cu[1] = qu.y; cu[2] = qu.z; cu[3] = qu.w;
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) cu[c] = srow[4 * kb + c];
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                        for (int s = 0; s < NS; ++s) tu[s] = m_fma(cu[c], Ll[s][4 * kb + c], tu[s]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) u[s] = m_fma(W[s], tu[s], u[s]);
+            return;
+        }
 #pragma unroll
         for (int kb = 0; kb < PMAX / 4; ++kb) {
             if (kb * 4 < P) {
@@ -321,7 +347,7 @@ __device__ __forceinline__ void contract(SP S, int P, int PP, const T (&X)[NS][D
             T W2[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) W2[s] = W[s] * Lc[s];
-            contract<T, D, PMAX, NS, LV + 1, SP>(S, P, PP, X, W2, Ll, u, v, row * P + k);
+            contract<T, D, PMAX, NS, LV + 1, SP>(S, P, PP, X, W2, Ll, u, v, row * P + k, uo);
             const T ak = rec_a<T>(k), bk = rec_b<T>(k);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -1245,7 +1271,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                             }
                         }
                     }
-                    contract<T, D, PMAX, NS, CF, const T *>(S, a.P, a.PP, X, Wc, Ll, u, v, 0);
+                    contract<T, D, PMAX, NS, CF, const T *>(S, a.P, a.PP, X, Wc, Ll, u, v, 0, a.phys.picard != 0);
                 }
                 if (has_next) {
                     u32x4 *dst = lds + (int64_t)(buf ^ 1) * cvec;
@@ -1333,7 +1359,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                             }
                         }
                     }
-                    contract<T, D, PMAX, NS, CF, const T *>((const T *)lds, a.P, a.PP, X, Wc, Ll, u, v, 0);
+                    contract<T, D, PMAX, NS, CF, const T *>((const T *)lds, a.P, a.PP, X, Wc, Ll, u, v, 0, true);
                 }
             }
 #pragma unroll
