@@ -700,6 +700,62 @@ int or_iterate(const or_problem *pb, int inst, int interval, int iter_tag,
     return 0;
 }
 
+/* The remark after Algorithm 1: Aitken extrapolation of the iteration as a
+ * weighted average of the iterate and its update.  Read as Aitken's
+ * delta-squared process for vector sequences in relaxation form (Irons and
+ * Tuck, 1969): u <- u + w r, with w the secant estimate of 1/(1 - G') along
+ * the last two residuals r of the fixed-point map G. */
+static void or_aitken_bounds(const or_problem *pb, double w[3])
+{
+    w[0] = pb->omega[0] != 0.0 ? pb->omega[0] : 1.0;
+    w[1] = pb->omega[1] != 0.0 ? pb->omega[1] : 0.5;
+    w[2] = pb->omega[2] != 0.0 ? pb->omega[2] : 2.0;
+}
+
+int or_iterate_aitken(const or_problem *pb, int inst, int interval, int iter_tag, double *U,
+                      double *r_prev, double state[2], double *max_eps, int64_t *steps)
+{
+    int d = pb->dim, n = pb->n, M = pb->degree[interval];
+    int64_t nsp = or_ipow(n, d), nn = nsp * M;
+    double *r = malloc(sizeof(double) * nn);
+    int64_t *st = malloc(sizeof(int64_t) * nn);
+    if (!r || !st) { free(r); free(st); return -3; }
+    int rc = or_estimate(pb, inst, interval, iter_tag, U, NULL, nn, 0, pb->M, r, NULL, st);
+    if (rc) { free(r); free(st); return rc; }
+    double mx = 0.0, num = 0.0, den = 0.0;
+    int64_t tot = 0;
+    for (int64_t node = 0; node < nn; ++node) {
+        int64_t jf = node % nsp;
+        int ell = (int)(node / nsp) + 1;
+        if (pb->estimator == OR_EST_PICARD) r[node] -= U[jf * (M + 1) + ell];
+        double dr = r[node] - r_prev[node];
+        num += r_prev[node] * dr;
+        den += dr * dr;
+        if (!(fabs(r[node]) <= mx)) mx = fabs(r[node]);
+        tot += st[node];
+    }
+    double wb[3], w;
+    or_aitken_bounds(pb, wb);
+    if (state[1] == 0.0) w = wb[0];
+    else if (den > 0.0) w = -state[0] * num / den;
+    else w = state[0];
+    if (w < wb[1]) w = wb[1];
+    if (w > wb[2]) w = wb[2];
+    if (!(w == w)) w = wb[0];
+    for (int64_t node = 0; node < nn; ++node) {
+        int64_t jf = node % nsp;
+        int ell = (int)(node / nsp) + 1;
+        U[jf * (M + 1) + ell] += w * r[node];
+        r_prev[node] = r[node];
+    }
+    state[0] = w;
+    state[1] = 1.0;
+    if (max_eps) *max_eps = mx;
+    if (steps) *steps = tot;
+    free(r); free(st);
+    return 0;
+}
+
 static int64_t or_interval_offset(const or_problem *pb, int interval)
 {
     int64_t nsp = or_ipow(pb->n, pb->dim), off = 0;
@@ -731,12 +787,19 @@ int or_solve(const or_problem *pb, int inst, double *U_all, double *max_eps)
                 }
                 for (int l = 0; l <= M; ++l) U[j * (M + 1) + l] = c0;
             }
+            double *rp = NULL, ast[2] = {0.0, 0.0};
+            if (pb->accel == OR_ACCEL_AITKEN) {
+                rp = calloc((size_t)(nsp * M), sizeof(double));
+                if (!rp) { free(u0); return -3; }
+            }
             for (int k = 0; k < pb->iters; ++k) {
                 double mx;
-                rc = or_iterate(pb, inst, iv, or_iter_tag(pb, k), U, &mx, NULL);
-                if (rc) { free(u0); return rc; }
+                if (rp) rc = or_iterate_aitken(pb, inst, iv, or_iter_tag(pb, k), U, rp, ast, &mx, NULL);
+                else rc = or_iterate(pb, inst, iv, or_iter_tag(pb, k), U, &mx, NULL);
+                if (rc) { free(u0); free(rp); return rc; }
                 if (max_eps) max_eps[iv * pb->iters + k] = mx;
             }
+            free(rp);
         }
     } else {
         for (int iv = 0; iv < pb->n_intervals; ++iv) {
@@ -747,7 +810,15 @@ int or_solve(const or_problem *pb, int inst, double *U_all, double *max_eps)
         }
         double *last = malloc(sizeof(double) * nsp * (pb->n_intervals > 0 ? pb->n_intervals : 1));
         if (!last) { free(u0); return -3; }
-        for (int s = 0; s < pb->iters; ++s) {
+        /* Aitken under sweeps: one weight and residual history per interval */
+        double **rp = calloc((size_t)pb->n_intervals, sizeof(double *));
+        double *ast = calloc((size_t)pb->n_intervals * 2, sizeof(double));
+        if (!rp || !ast) { free(u0); free(last); free(rp); free(ast); return -3; }
+        for (int iv = 0; iv < pb->n_intervals && pb->accel == OR_ACCEL_AITKEN; ++iv) {
+            rp[iv] = calloc((size_t)(nsp * pb->degree[iv]), sizeof(double));
+            if (!rp[iv]) rc = -3;
+        }
+        for (int s = 0; s < pb->iters && !rc; ++s) {
             /* every interval takes column 0 from the previous sweep's last column
              * of the interval before it */
             for (int iv = 0; iv < pb->n_intervals; ++iv) {
@@ -761,15 +832,22 @@ int or_solve(const or_problem *pb, int inst, double *U_all, double *max_eps)
                 for (int64_t j = 0; j < nsp; ++j) U[j * (M + 1)] = last[(iv - 1) * nsp + j];
             }
             double mxs = 0.0;
-            for (int iv = 0; iv < pb->n_intervals; ++iv) {
-                double mx;
-                rc = or_iterate(pb, inst, iv, or_iter_tag(pb, s), U_all + or_interval_offset(pb, iv), &mx, NULL);
-                if (rc) { free(u0); free(last); return rc; }
+            for (int iv = 0; iv < pb->n_intervals && !rc; ++iv) {
+                double mx = 0.0;
+                double *Ui = U_all + or_interval_offset(pb, iv);
+                if (pb->accel == OR_ACCEL_AITKEN)
+                    rc = or_iterate_aitken(pb, inst, iv, or_iter_tag(pb, s), Ui, rp[iv], ast + 2 * iv, &mx, NULL);
+                else
+                    rc = or_iterate(pb, inst, iv, or_iter_tag(pb, s), Ui, &mx, NULL);
                 if (!(mx <= mxs)) mxs = mx;
             }
+            if (rc) break;
             if (max_eps) max_eps[s] = mxs;
         }
+        for (int iv = 0; iv < pb->n_intervals; ++iv) free(rp[iv]);
+        free(rp); free(ast);
         free(last);
+        if (rc) { free(u0); return rc; }
     }
     free(u0);
     return 0;

@@ -70,7 +70,14 @@ typedef struct {
     int32_t fresh_per_iter;   /* 1: iteration tag in the counter, 0: tag = 0    */
     uint64_t seed;
     int32_t estimator;        /* OR_EST_RESIDUAL or OR_EST_PICARD               */
+    int32_t accel;            /* OR_ACCEL_NONE or OR_ACCEL_AITKEN               */
+    double omega[3];          /* Aitken: first weight, lower and upper bound of
+                                 the weight; a zero entry selects 1, 0.5, 2     */
 } or_problem;
+
+/* acceleration of the fixed-point iteration (the remark after Algorithm 1):
+ * none, or Aitken's delta-squared extrapolation in relaxation form */
+enum { OR_ACCEL_NONE = 0, OR_ACCEL_AITKEN = 1 };
 
 /* estimators: eq. varepsilon_1 (the residual increment, added to the iterate)
  * or eq. uast (the Picard form: the iterate itself, replacing it) */
@@ -137,6 +144,16 @@ int or_iterate(const or_problem *pb, int inst, int interval, int iter_tag,
  * U_all: the nodal arrays of all intervals concatenated (sum n^d (M_n+1)).
  * max_eps: n_intervals*iters entries (sequential) or iters entries (sweeps). */
 int or_solve(const or_problem *pb, int inst, double *U_all, double *max_eps);
+
+/* One Aitken-relaxed iteration of one interval: r = the estimator's change
+ * (eq. varepsilon_1's increment, or eq. uast's estimate minus the iterate),
+ * weight w = w0 on the first iteration, else
+ *   w = -w_prev <r_prev, r - r_prev> / |r - r_prev|^2   (w_prev if the
+ * denominator is 0), clipped to [w_min, w_max]; U += w r at every node l >= 1.
+ * r_prev [n^d M] and state {w_prev, have_prev} carry over between calls
+ * (zero state: first iteration).  max_eps = max |r|. */
+int or_iterate_aitken(const or_problem *pb, int inst, int interval, int iter_tag, double *U,
+                      double *r_prev, double state[2], double *max_eps, int64_t *steps);
 
 /* terminal misfit L = 1/2 sum_j (u(x_j,T) - target_j)^2 of a single-interval
  * solve from phi-coefficients c0, and its gradient dL/dc0 by reverse mode with

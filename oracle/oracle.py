@@ -38,11 +38,12 @@ class _Problem(C.Structure):
         ("f_param", C.c_double * 4), ("src_param", C.c_double * 8), ("ic_param", C.c_double * 4),
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
-        ("estimator", C.c_int32),
+        ("estimator", C.c_int32), ("accel", C.c_int32), ("omega", C.c_double * 3),
     ]
 
 
 ESTIMATORS = {"residual": 0, "picard": 1}
+ACCELS = {"none": 0, "aitken": 1}
 
 
 _lib = None
@@ -70,6 +71,7 @@ def lib():
             "or_sample_path": (d, [pp, p, C.c_int, C.c_int, C.c_int, i64, i64, p]),
             "or_estimate": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, p, p, i64, i64, i64, p, p, p]),
             "or_iterate": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, p, p, p]),
+            "or_iterate_aitken": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, p, p, p, p, p]),
             "or_solve": (C.c_int, [pp, C.c_int, p, p]),
             "or_loss_grad": (C.c_int, [pp, C.c_int, p, p, p, p]),
             "or_exit_fraction": (d, [C.c_int, d, C.c_int, p, i64, C.c_uint64]),
@@ -196,6 +198,9 @@ class Problem:
                      else C.POINTER(C.c_double)())
         s.M, s.iters, s.fresh_per_iter, s.seed = wl.M, wl.iters, int(wl.fresh_per_iter), wl.seed
         s.estimator = ESTIMATORS[getattr(wl, "estimator", "residual")]
+        s.accel = ACCELS[getattr(wl, "accel", "none")]
+        for i, v in enumerate(getattr(wl, "omega", [0.0, 0.0, 0.0])):
+            s.omega[i] = v
         self.s = s
 
     @property
@@ -266,6 +271,17 @@ class Problem:
         mx = np.zeros(1)
         st = np.zeros(1, dtype=np.int64)
         _check(lib().or_iterate(self.ref, inst, iv, iter_tag, _ptr(U), _ptr(mx), _ptr(st)), "iterate")
+        return U, float(mx[0]), int(st[0])
+
+    def iterate_aitken(self, U, r_prev, state, inst=0, iv=0, iter_tag=0):
+        """one Aitken-relaxed iteration; r_prev (n^d M) and state [w, have_prev]
+        are updated in place"""
+        U = np.array(U, dtype=np.float64, copy=True)
+        assert r_prev.dtype == np.float64 and r_prev.flags.c_contiguous and state.dtype == np.float64
+        mx = np.zeros(1)
+        st = np.zeros(1, dtype=np.int64)
+        _check(lib().or_iterate_aitken(self.ref, inst, iv, iter_tag, _ptr(U), _ptr(r_prev), _ptr(state),
+                                       _ptr(mx), _ptr(st)), "iterate_aitken")
         return U, float(mx[0]), int(st[0])
 
     def solve(self, inst=0):
