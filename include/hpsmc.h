@@ -91,6 +91,20 @@ enum { HPSMC_EST_RESIDUAL = 0,    /* eq. varepsilon_1: the Monte Carlo estimate 
                                      the iterate (eps = its change).  Vector-unit
                                      round kernel only; no gradient               */
 
+enum { HPSMC_ACCEL_NONE = 0,      /* Algorithm 1's update: U += eps               */
+       HPSMC_ACCEL_AITKEN = 1 };  /* the acceleration remark after Algorithm 1:
+                                     Aitken's delta-squared extrapolation as a
+                                     weighted average, U += w eps, per (instance,
+                                     interval) vector of node values, with
+                                     w = omega[0] on its first iteration, then
+                                     w = -w_prev <e_prev, e - e_prev> / |e - e_prev|^2
+                                     (w_prev when the denominator is 0), clipped to
+                                     [omega[1], omega[2]]; e is the estimator's
+                                     change (eps).  The history restarts at
+                                     hpsmc_start_interval, at the start of every
+                                     solve, and after hpsmc_set_nodes of the
+                                     interval.  No gradient                       */
+
 enum { HPSMC_FP64 = 0,            /* everything in FP64                            */
        HPSMC_FP32_SAMPLING = 1 }; /* paths and basis evaluation in FP32 with
                                      compensated accumulation; reconstruction,
@@ -120,6 +134,10 @@ typedef struct {
                                   tol (at most `iters`); the host reads max|eps|
                                   after every iteration, so hpsmc_solve runs
                                   eagerly even with the "graph" option          */
+    int32_t accel;             /* HPSMC_ACCEL_NONE (default) or HPSMC_ACCEL_AITKEN */
+    double omega[3];           /* Aitken: first weight, lower and upper bound;
+                                  0 selects 1, 0.5, 2; need 0 < omega[1] <=
+                                  omega[0] <= omega[2] after the defaults       */
 } hpsmc_problem;
 
 typedef struct hpsmc_plan hpsmc_plan;

@@ -236,6 +236,10 @@ struct NodeSet {               // the nodes one sampling launch covers
     uint32_t *live = nullptr;  // [2][n_groups]
     int64_t *prefix = nullptr; // [n_groups + 1]
     double *result = nullptr;  // [n][ms]
+    // Aitken-relaxed update: one vector per (interval of the set, instance)
+    int32_t n_vec = 0;
+    int64_t *vbeg = nullptr;   // [n_vec + 1] node ranges
+    double *ait = nullptr;     // [2 n_vec] {w_prev, have_prev}, then e_prev [n]
 };
 
 }  // namespace hpsmc
@@ -358,6 +362,14 @@ static bool pick_chunking(const hpsmc_plan *plan, int nthr, int *cf, int64_t *ch
     return false;
 }
 
+// first weight and bounds of the Aitken relaxation; zeros select 1, 0.5, 2
+static void aitken_weights(const hpsmc_problem *pb, double w[3])
+{
+    w[0] = pb->omega[0] != 0.0 ? pb->omega[0] : 1.0;
+    w[1] = pb->omega[1] != 0.0 ? pb->omega[1] : 0.5;
+    w[2] = pb->omega[2] != 0.0 ? pb->omega[2] : 2.0;
+}
+
 static hpsmc_status validate(const hpsmc_problem *pb)
 {
     if (!pb) return fail(HPSMC_EINVAL, "problem is NULL");
@@ -385,6 +397,14 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     if (pb->precision < 0 || pb->precision > 1) return fail(HPSMC_EINVAL, "unknown precision");
     if (!std::isfinite(pb->tol) || pb->tol < 0.0) return fail(HPSMC_EINVAL, "tol must be finite and >= 0");
     if (pb->estimator < 0 || pb->estimator > 1) return fail(HPSMC_EINVAL, "unknown estimator");
+    if (pb->accel < 0 || pb->accel > 1) return fail(HPSMC_EINVAL, "unknown accel");
+    if (pb->accel == HPSMC_ACCEL_AITKEN) {
+        double w[3];
+        aitken_weights(pb, w);
+        if (!(std::isfinite(w[0]) && std::isfinite(w[1]) && std::isfinite(w[2]) && w[1] > 0.0 && w[1] <= w[0] &&
+              w[0] <= w[2]))
+            return fail(HPSMC_EINVAL, "Aitken weights need 0 < omega[1] <= omega[0] <= omega[2]");
+    }
     if ((pb->ic_kind == HPSMC_IC_PHI || pb->ic_kind == HPSMC_IC_NODAL) && !pb->ic_data)
         return fail(HPSMC_EINVAL, "ic_data is NULL");
     if (pb->ic_kind == HPSMC_IC_EXACT && pb->src_kind == HPSMC_SRC_NONE)
@@ -433,7 +453,7 @@ static double expected_cost(const NodeDesc &nd, int d)
 
 static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<int32_t> &ivs)
 {
-    const int d = plan->d, T = (int)(plan->fp32 ? sizeof(float) : sizeof(double));
+    const int d = plan->d;
     set.ivs = ivs;
     set.host.clear();
     std::vector<int64_t> coef_off, slab_off, slab_off_mma;
@@ -560,6 +580,18 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     sa.slab_stride = stride;
     if ((st = dalloc(plan, (void **)&set.eps, sizeof(double) * set.n))) return st;
     if ((st = dalloc(plan, (void **)&set.sumsq, sizeof(double) * set.n))) return st;
+    if (plan->pb.accel == HPSMC_ACCEL_AITKEN) {
+        // nodes were generated interval by interval, instance by instance
+        std::vector<int64_t> vb(1, 0);
+        for (int32_t iv : ivs)
+            for (int inst = 0; inst < plan->n_inst; ++inst) vb.push_back(vb.back() + plan->nsp * plan->degree[iv]);
+        set.n_vec = (int32_t)(vb.size() - 1);
+        if ((st = dalloc(plan, (void **)&set.vbeg, sizeof(int64_t) * vb.size()))) return st;
+        if ((st = dalloc(plan, (void **)&set.ait, sizeof(double) * (2 * set.n_vec + set.n)))) return st;
+        if (hipMemcpy(set.vbeg, vb.data(), sizeof(int64_t) * vb.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemset(set.ait, 0, sizeof(double) * (2 * set.n_vec + set.n)) != hipSuccess)
+            return fail(HPSMC_EDEVICE, "Aitken state upload failed");
+    }
     if (set.rounds) {
         const size_t sb = path_state_bytes(plan->fp32, d);
         const int64_t per_sample = (int64_t)(2 * sb + sizeof(double));
@@ -583,7 +615,8 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
 static void free_set(const hpsmc_plan *plan, NodeSet &s)
 {
     for (void *p : {(void *)s.dev, s.group_mem, (void *)s.eps, (void *)s.sumsq, (void *)s.probe, (void *)s.gdev,
-                    s.state[0], s.state[1], (void *)s.live, (void *)s.prefix, (void *)s.result})
+                    s.state[0], s.state[1], (void *)s.live, (void *)s.prefix, (void *)s.result, (void *)s.vbeg,
+                    (void *)s.ait})
         dfree(plan, p);
     s = NodeSet{};
 }
@@ -680,6 +713,33 @@ static int set_uses_mma(const hpsmc_plan *plan, const NodeSet &set)
 
 // Round-based sampling of one node set: slices of samples, each advanced in
 // rounds of round_steps walk steps with compaction between rounds.
+// reduce-kernel mode: bit 0 Picard form, bit 1 the Aitken kernel applies the update
+static int update_mode(const hpsmc_plan *plan)
+{
+    return (plan->pb.estimator == HPSMC_EST_PICARD ? 1 : 0) | (plan->pb.accel == HPSMC_ACCEL_AITKEN ? 2 : 0);
+}
+
+static hpsmc_status aitken_update(hpsmc_plan *plan, NodeSet &set, hipStream_t s)
+{
+    if (plan->pb.accel != HPSMC_ACCEL_AITKEN) return HPSMC_OK;
+    double w[3];
+    aitken_weights(&plan->pb, w);
+    HIP_TRY(launch_aitken(set.dev, set.vbeg, set.n_vec, set.eps, set.ait + 2 * set.n_vec, set.ait, w[0], w[1], w[2],
+                          plan->U, s));
+    return HPSMC_OK;
+}
+
+// restart the Aitken history of interval iv (every instance)
+static hpsmc_status aitken_reset(hpsmc_plan *plan, int iv, hipStream_t s)
+{
+    if (plan->pb.accel != HPSMC_ACCEL_AITKEN) return HPSMC_OK;
+    const bool seq = plan->pb.schedule == HPSMC_SEQUENTIAL;
+    NodeSet &set = seq ? plan->sets[iv] : plan->sets[0];
+    const int64_t v0 = (int64_t)(seq ? 0 : iv) * plan->n_inst;
+    HIP_TRY(launch_fill_u64((unsigned long long *)(set.ait + 2 * v0), 2 * (int64_t)plan->n_inst, 0ull, s));
+    return HPSMC_OK;
+}
+
 static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
 {
     const int ns = plan->launch.samples_per_lane, waves = plan->launch.waves_per_block;
@@ -744,8 +804,9 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     if (ek) HIP_TRY(hipEventRecord(ek->b, s));
     plan->n_advance += (int64_t)R * ((plan->pb.M + set.ms - 1) / set.ms);
     unsigned long long *mb = plan->maxbits + std::min(record, 4095);
-    HIP_TRY(launch_reduce_update(plan->part, 1, plan->pb.estimator == HPSMC_EST_PICARD, set.dev, set.n, plan->pb.M,
-                                 plan->U, set.eps, set.sumsq, mb, s));
+    HIP_TRY(launch_reduce_update(plan->part, 1, update_mode(plan), set.dev, set.n, plan->pb.M, plan->U, set.eps,
+                                 set.sumsq, mb, s));
+    if (hpsmc_status st = aitken_update(plan, set, s)) return st;
     plan->node_samples += set.n * plan->pb.M;
     plan->n_records = std::max(plan->n_records, std::min(record, 4095) + 1);
     return HPSMC_OK;
@@ -793,8 +854,9 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
     HIP_TRY(launch_sample(a, plan->fp32, ns, plan->launch.waves_per_block, blocks, s));
     if (ek) HIP_TRY(hipEventRecord(ek->b, s));
     unsigned long long *mb = plan->maxbits + std::min(record, 4095);
-    HIP_TRY(launch_reduce_update(plan->part, a.chunks_per_node, 0, set.dev, set.n, plan->pb.M, plan->U, set.eps,
-                                 set.sumsq, mb, s));
+    HIP_TRY(launch_reduce_update(plan->part, a.chunks_per_node, update_mode(plan), set.dev, set.n, plan->pb.M,
+                                 plan->U, set.eps, set.sumsq, mb, s));
+    if (hpsmc_status st = aitken_update(plan, set, s)) return st;
     plan->node_samples += set.n * plan->pb.M;
     plan->n_records = std::max(plan->n_records, std::min(record, 4095) + 1);
     return HPSMC_OK;
@@ -802,6 +864,7 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
 
 static hpsmc_status start_interval(hpsmc_plan *plan, int iv, int replicate, hipStream_t s)
 {
+    if (hpsmc_status st = aitken_reset(plan, iv, s)) return st;
     const int T1 = plan->degree[iv] + 1;
     const int64_t rows = (int64_t)plan->n_inst * plan->nsp;
     double *dst = plan->U + plan->u_off[iv];
@@ -1143,9 +1206,11 @@ static hpsmc_status solve_body(hpsmc_plan *plan, hipStream_t s)
             if (tol > 0.0 && k == K) unconverged = true;
         }
     } else {
-        for (int iv = 0; iv < plan->n_iv; ++iv)
+        for (int iv = 0; iv < plan->n_iv; ++iv) {
             HIP_TRY(launch_start_columns(plan->U + plan->u_off[iv], plan->ic, 1, 0, plan->degree[iv] + 1,
                                          plan->degree[iv] + 1, (int64_t)plan->n_inst * plan->nsp, 1, s));
+            if ((st = aitken_reset(plan, iv, s))) return st;
+        }
         std::vector<double> hist;
         int k = 0;
         for (; k < K; ++k) {
@@ -1220,6 +1285,7 @@ hpsmc_status hpsmc_set_nodes(hpsmc_plan *plan, int32_t iv, const double *in, int
 {
     CHECK_PLAN(plan);
     if (iv < 0 || iv >= plan->n_iv || !in) return fail(HPSMC_EINVAL, "bad interval or input");
+    if (hpsmc_status st = aitken_reset(plan, iv, (hipStream_t)stream)) return st;
     return copy_nodes(plan, iv, plan->U + plan->u_off[iv], in, on_device, (hipStream_t)stream, true);
 }
 
@@ -1505,6 +1571,8 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
         return fail(HPSMC_EDEVICE, "tune events");
     }
     plan->pb.M = mt;
+    const int32_t accel_save = plan->pb.accel;
+    plan->pb.accel = HPSMC_ACCEL_NONE;   // trials leave the Aitken history alone
     auto trial = [&](const hpsmc_launch &l, float &ms) -> hpsmc_status {
         hpsmc_launch keep = plan->launch;
         plan->launch = l;
@@ -1552,6 +1620,7 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
         }
     }
     plan->pb.M = M_full;
+    plan->pb.accel = accel_save;
     (void)launch_fill_u64(plan->maxbits + 4095, 1, 0ull, s);
     plan->node_samples = ns_save;
     plan->n_records = rec_save;
@@ -1766,6 +1835,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
     if (plan->d > 2 || plan->P > 32 || !plan->sets[0].rounds)
         return fail(HPSMC_ENOTSUP, "the adjoint kernel covers dim <= 2 and n <= 30");
     if (plan->pb.estimator != HPSMC_EST_RESIDUAL) return fail(HPSMC_ENOTSUP, "the adjoint is that of the residual form");
+    if (plan->pb.accel != HPSMC_ACCEL_NONE) return fail(HPSMC_ENOTSUP, "the adjoint is that of the unrelaxed iteration");
     hipStream_t s = (hipStream_t)stream;
     const int d = plan->d, n = plan->n, P = plan->P, K = plan->pb.iters, T1 = plan->degree[0] + 1;
     const int64_t I = plan->n_inst, nsp = plan->nsp, psp = plan->psp;

@@ -135,9 +135,12 @@ hipError_t launch_mode_product(const double *in, double *out, int64_t outer, int
 hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t s);
 hipError_t launch_sample(const SampleArgs &a, int fp32, int samples_per_lane, int waves_per_block,
                          int blocks, hipStream_t s);
-hipError_t launch_reduce_update(const double *part, int chunks, int picard, const NodeDesc *nodes, int64_t n_nodes,
+hipError_t launch_reduce_update(const double *part, int chunks, int mode, const NodeDesc *nodes, int64_t n_nodes,
                                 int64_t M, double *U, double *eps, double *sumsq,
                                 unsigned long long *maxbits, hipStream_t s);
+// Aitken-relaxed update of the vectors [vbeg[v], vbeg[v+1]) of a node set
+hipError_t launch_aitken(const NodeDesc *nodes, const int64_t *vbeg, int n_vec, const double *eps, double *eprev,
+                         double *state, double w0, double wmin, double wmax, double *U, hipStream_t s);
 hipError_t launch_start_columns(double *U, const double *src, int64_t src_stride, int64_t src_off,
                                 int64_t dst_stride, int T1, int64_t count, int replicate, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);

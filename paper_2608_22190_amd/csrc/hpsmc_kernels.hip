@@ -712,8 +712,10 @@ hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t 
 
 // ---------------------------------------------------------------------------
 // eps = (1/M) sum of the chunk sums in chunk order; U += eps; max|eps|.
+// mode bit 0: Picard form (the estimate replaces U, eps = the change);
+// bit 1: leave U alone (the Aitken kernel applies the weighted update).
 // ---------------------------------------------------------------------------
-__global__ void reduce_update_kernel(const double *__restrict__ part, int chunks, int picard,
+__global__ void reduce_update_kernel(const double *__restrict__ part, int chunks, int mode,
                                      const NodeDesc *__restrict__ nodes,
                                      int64_t n_nodes, int64_t M, double *__restrict__ U, double *__restrict__ eps,
                                      double *__restrict__ sumsq, unsigned long long *maxbits)
@@ -726,7 +728,9 @@ __global__ void reduce_update_kernel(const double *__restrict__ part, int chunks
         double s1 = 0.0, s2 = 0.0;
         for (int c = 0; c < chunks; ++c) { s1 += p[2 * c]; s2 += p[2 * c + 1]; }
         double e = s1 / (double)M;
-        if (picard) {   // eq. uast: the estimate replaces the iterate; eps is the change
+        if (mode & 2) {
+            if (mode & 1) e -= U[nd.u_index];
+        } else if (mode & 1) {   // eq. uast: the estimate replaces the iterate; eps is the change
             const double uo = U[nd.u_index];
             U[nd.u_index] = e;
             e -= uo;
@@ -752,13 +756,85 @@ __global__ void reduce_update_kernel(const double *__restrict__ part, int chunks
     if (threadIdx.x == 0) atomicMax(maxbits, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
-hipError_t launch_reduce_update(const double *part, int chunks, int picard, const NodeDesc *nodes, int64_t n_nodes,
+hipError_t launch_reduce_update(const double *part, int chunks, int mode, const NodeDesc *nodes, int64_t n_nodes,
                                 int64_t M,
                                 double *U, double *eps, double *sumsq, unsigned long long *maxbits, hipStream_t s)
 {
     if (n_nodes <= 0) return hipSuccess;
     hipLaunchKernelGGL(reduce_update_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, part, chunks,
-                       picard, nodes, n_nodes, M, U, eps, sumsq, maxbits);
+                       mode, nodes, n_nodes, M, U, eps, sumsq, maxbits);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Aitken-relaxed update (the acceleration remark after Algorithm 1), one block
+// per (instance, interval) vector of nodes [vbeg[v], vbeg[v+1]):
+//   w = w0 on the vector's first iteration, else
+//   w = -w_prev <e_prev, e - e_prev> / |e - e_prev|^2 (w_prev if that is 0/0),
+// clipped to [wmin, wmax]; U += w e; e_prev = e.  state[2v] = w_prev,
+// state[2v+1] = 1 once the vector has a history.  The two inner products are
+// summed per thread in node order, then by a fixed tree: deterministic.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) aitken_update_kernel(const NodeDesc *__restrict__ nodes,
+                                                            const int64_t *__restrict__ vbeg,
+                                                            const double *__restrict__ eps,
+                                                            double *__restrict__ eprev, double *__restrict__ state,
+                                                            double w0, double wmin, double wmax,
+                                                            double *__restrict__ U)
+{
+    const int v = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t b = vbeg[v], e = vbeg[v + 1];
+    const bool have = state[2 * v + 1] != 0.0;
+    double num = 0.0, den = 0.0;
+    if (have) {
+        for (int64_t i = b + tid; i < e; i += blockDim.x) {
+            const int32_t o = nodes[i].out;
+            const double rp = eprev[o], dr = eps[o] - rp;
+            num = fma(rp, dr, num);
+            den = fma(dr, dr, den);
+        }
+    }
+    __shared__ double sn[256], sd[256];
+    __shared__ double w_sh;
+    sn[tid] = num;
+    sd[tid] = den;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+            sn[tid] += sn[tid + o];
+            sd[tid] += sd[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double wp = state[2 * v];
+        double w = !have ? w0 : (sd[0] > 0.0 ? -wp * sn[0] / sd[0] : wp);
+        if (w < wmin) w = wmin;
+        if (w > wmax) w = wmax;
+        if (!(w == w)) w = w0;
+        w_sh = w;
+    }
+    __syncthreads();
+    const double w = w_sh;
+    for (int64_t i = b + tid; i < e; i += blockDim.x) {
+        const NodeDesc &nd = nodes[i];
+        const double r = eps[nd.out];
+        U[nd.u_index] += w * r;
+        eprev[nd.out] = r;
+    }
+    if (tid == 0) {
+        state[2 * v] = w;
+        state[2 * v + 1] = 1.0;
+    }
+}
+
+hipError_t launch_aitken(const NodeDesc *nodes, const int64_t *vbeg, int n_vec, const double *eps, double *eprev,
+                         double *state, double w0, double wmin, double wmax, double *U, hipStream_t s)
+{
+    if (n_vec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(aitken_update_kernel, dim3((unsigned)n_vec), dim3(256), 0, s, nodes, vbeg, eps, eprev, state,
+                       w0, wmin, wmax, U);
     return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
 SCHEDULES = {"sequential": 0, "sweeps": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 ESTIMATORS = {"residual": 0, "picard": 1}
+ACCELS = {"none": 0, "aitken": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSUP", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED", -6: "ENOTCONVERGED"}
 ENOTCONVERGED = -6
 
@@ -44,6 +45,7 @@ class hpsmc_problem(C.Structure):
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
         ("precision", C.c_int32), ("estimator", C.c_int32), ("tol", C.c_double),
+        ("accel", C.c_int32), ("omega", C.c_double * 3),
     ]
 
 
@@ -157,6 +159,9 @@ def make_problem(wl):
     p.precision = PRECISIONS[wl.precision]
     p.tol = float(getattr(wl, "tol", 0.0))
     p.estimator = ESTIMATORS[getattr(wl, "estimator", "residual")]
+    p.accel = ACCELS[getattr(wl, "accel", "none")]
+    for i, v in enumerate(getattr(wl, "omega", [0.0, 0.0, 0.0])):
+        p.omega[i] = v
     return p, [tb, deg, ns, ic]
 
 

@@ -56,6 +56,15 @@ def test_invalid_tolerance_is_rejected(tol):
     assert ei.value.status == -1
 
 
+@pytest.mark.parametrize("omega", [[3.0, 0, 0], [0.3, 0, 0], [1.0, -1.0, 2.0], [float("nan"), 0, 0],
+                                   [1.0, 1.5, 1.2], [1.0, 0.5, float("inf")]])
+def test_invalid_aitken_weights_are_rejected(omega):
+    wl = W.small(dim=1, n=4, M_deg=4).with_(accel="aitken", omega=omega)
+    with pytest.raises(H.HpsmcError) as ei:
+        H.Plan(wl)
+    assert ei.value.status == -1
+
+
 def test_allocator_hooks_must_come_in_pairs():
     lib = H.lib()
     a = H.ALLOC_FN(lambda n, s, c: None)
