@@ -130,6 +130,8 @@ def run_other(name, args, torch):
     m = args.m_slice
     if name == "compare":
         return run_compare(args, torch)
+    if name == "aitken":
+        return run_aitken(args, torch)
     if name == "c1":
         wl = W.c1_single_step()
     elif name == "c2p":
@@ -245,6 +247,49 @@ def run_compare(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def run_aitken(args, torch):
+    """What the Aitken relaxation (the remark after Algorithm 1) buys on the
+    single-step problem (1-D, u = e^{-t} sin(pi x), 16 x 16 nodes, M = 4096,
+    FP64): (a) common random numbers, so the iteration map is deterministic:
+    iterations until max|eps| < 1e-10; (b) fresh samples each iteration (the
+    paper's setting): error against the exact solution after each iteration
+    count 1..8."""
+    from paper_2608_22190_amd import hpsmc, workloads as W
+    out = {}
+    for accel in ("none", "aitken"):
+        wl = W.c1_single_step(iters=60).with_(fresh_per_iter=False, tol=1e-10, accel=accel)
+        with hpsmc.Plan(wl) as plan:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status = plan.hpsmc_solve()
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            st = plan.hpsmc_stats()
+        hist = list(st["max_eps"][:st["n_records"]])
+        errs = []
+        for k in range(1, 9):
+            wlf = W.c1_single_step(iters=k).with_(accel=accel)
+            with hpsmc.Plan(wlf) as plan:
+                plan.hpsmc_solve()
+                x, t = plan.hpsmc_grid(0)
+                ex = np.sin(np.pi * x)[:, None] * np.exp(-t)[None, :]
+                errs.append(float(np.max(np.abs(plan.hpsmc_get_nodes(0)[0] - ex))))
+        out[accel] = {"crn_iterations_to_1e-10": len(hist), "crn_status": int(status), "crn_seconds": sec,
+                      "crn_max_eps": hist, "fresh_error_after_k": errs}
+        print(f"[bench] aitken {accel}: {len(hist)} iterations to 1e-10 ({sec:.2f}s), fresh errors "
+              f"{', '.join(f'{e:.2e}' for e in errs)}", file=sys.stderr, flush=True)
+    wl = W.c1_single_step()
+    ns = wl.nodes_per_sweep * wl.M * out["aitken"]["crn_iterations_to_1e-10"]
+    line = {"metric": METRIC, "value": ns / out["aitken"]["crn_seconds"], "unit": "node-samples/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": 1e3 * out["aitken"]["crn_seconds"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "c1_1d_single_step with common random numbers, solved to max|eps| < 1e-10, "
+                                   "Aitken-relaxed against plain iteration; then fresh samples, K = 1..8"},
+            "iterations_saved": 1 - out["aitken"]["crn_iterations_to_1e-10"] / out["none"]["crn_iterations_to_1e-10"],
+            "comparison": out}
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(wl, budget_s=20.0):
     """The FP64 oracle on a bounded sample: random nodes of the same interval,
     the first samples of each, one residual iteration from the same iterate."""
@@ -279,7 +324,7 @@ def main():
     ap.add_argument("--m-slice", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "compare"])
+    ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "compare", "aitken"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--launch", type=str, default="",
