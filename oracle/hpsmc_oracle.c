@@ -499,6 +499,56 @@ static void or_direction(or_stream *st, int dim, int64_t q, double *dir)
     for (int i = 0; i < dim; ++i) dir[i] = g[i] / nrm;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Ball point of a walk step (OR_QUAD_BALL).  The expected path integral over */
+/* the sojourn in the ball B_r(x), r = J, equals W(x) E_{Q_r}[g(Y)] with       */
+/* Q_r = G_r(x, .)/W(x) and G_r the Green's function of -Laplace on the ball  */
+/* with pole at its centre (Sec. 3, the representation used for the B_1       */
+/* bound).  W(x) = r^2/(2d) = Delta.  Q_r is radial: the radius rho = r s has  */
+/* density proportional to s^{d-1} G(s), i.e. 2d/(d-2) (s - s^{d-1}) for      */
+/* d >= 3, 4 s log(1/s) for d = 2 and 2 (1 - s) for d = 1 -- in every case    */
+/* the law of the product sqrt(U_a) * U_b^{1/d} of independent uniform powers */
+/* (a product of variables with densities 2a and d b^{d-1}).  The direction   */
+/* is uniform.  Philox words: counter word 2 with bit 31 set, 2q (radius      */
+/* from words 0 and 1, direction from words 2 and 3) and, for d >= 3, 2q+1   */
+/* (more Box-Muller pairs); the walk's own counters never set bit 31.        */
+/* ------------------------------------------------------------------------ */
+static void or_ball_point(or_stream *st, int dim, int64_t q, double *off)
+{
+    uint32_t w[8];
+    or_stream_block(st, (int64_t)(0x80000000u | (uint32_t)(2 * q)), w);
+    double ua = or_u01(w[0]), ub = or_u01(w[1]), root;
+    switch (dim) {
+    case 1: root = ub; break;
+    case 2: root = sqrt(ub); break;
+    case 3: root = cbrt(ub); break;
+    case 4: root = sqrt(sqrt(ub)); break;
+    default: root = pow(ub, 0.2); break;
+    }
+    double s = sqrt(ua) * root;
+    if (dim == 1) {
+        off[0] = (w[2] & 1u) ? s : -s;
+        return;
+    }
+    if (dim == 2) {
+        double th = 2.0 * OR_PI * or_u01(w[2]);
+        off[0] = s * cos(th); off[1] = s * sin(th);
+        return;
+    }
+    or_stream_block(st, (int64_t)(0x80000000u | (uint32_t)(2 * q + 1)), w + 4);
+    double g[6];
+    for (int k = 0; k < 3; ++k) {
+        double rr = sqrt(-2.0 * log(or_u01(w[2 + 2 * k])));
+        double th = 2.0 * OR_PI * or_u01(w[3 + 2 * k]);
+        g[2 * k] = rr * cos(th);
+        g[2 * k + 1] = rr * sin(th);
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < dim; ++i) nrm += g[i] * g[i];
+    nrm = sqrt(nrm);
+    for (int i = 0; i < dim; ++i) off[i] = s * g[i] / nrm;
+}
+
 static void or_stream_init(or_stream *st, uint64_t seed, int64_t node, int64_t sample,
                            int inst, int interval, int iter_tag)
 {
@@ -580,10 +630,18 @@ static double or_path(const or_problem *pb, const double *Ut, int inst, int inte
         }
         if (outside) break;
         double tau = t0 + (nd->span - (double)q * nd->delta);
+        const double *E = X;            /* where the step's integrand is evaluated */
+        double Z[OR_MAXD];
+        if (pb->quad == OR_QUAD_BALL) {
+            double off[OR_MAXD];
+            or_ball_point(&st, d, q, off);
+            for (int i = 0; i < d; ++i) Z[i] = fma(J, off[i], X[i]);
+            E = Z;
+        }
         if (pb->estimator == OR_EST_PICARD)
-            acc += nd->delta * or_picard_integrand(pb, interval, Ut, X, tau);
+            acc += nd->delta * or_picard_integrand(pb, interval, Ut, E, tau);
         else
-            acc += nd->delta * or_residual(pb, interval, Ut, X, tau);
+            acc += nd->delta * or_residual(pb, interval, Ut, E, tau);
         for (int i = 0; i < d; ++i) X[i] = Y[i];
     }
     if (pb->estimator == OR_EST_PICARD && q == nd->nstar) {
@@ -596,6 +654,16 @@ static double or_path(const or_problem *pb, const double *Ut, int inst, int inte
 }
 
 static int or_iter_tag(const or_problem *pb, int k) { return pb->fresh_per_iter ? k : 0; }
+
+int or_ball_offset(const or_problem *pb, int inst, int interval, int iter_tag, int64_t node,
+                   int64_t sample, int64_t q, double *offset)
+{
+    if (pb->dim < 1 || pb->dim > OR_MAXD || q < 0 || q >= (1 << 24)) return -1;
+    or_stream st;
+    or_stream_init(&st, pb->seed, node, sample, inst, interval, iter_tag);
+    or_ball_point(&st, pb->dim, q, offset);
+    return 0;
+}
 
 double or_sample_path(const or_problem *pb, const double *Ut, int inst, int interval,
                       int iter_tag, int64_t node, int64_t sample, int64_t *L_out)
@@ -905,6 +973,8 @@ int or_loss_grad(const or_problem *pb, int inst, const double *c0,
     int d = pb->dim, n = pb->n, M = pb->degree[0], T1 = M + 1, K = pb->iters;
     int64_t nsp = or_ipow(n, d), size = nsp * T1, nn = nsp * M;
     if (pb->n_intervals != 1 || K < 1) return -1;
+    /* the reverse mode below is that of the plain residual iteration */
+    if (pb->estimator != OR_EST_RESIDUAL || pb->accel != OR_ACCEL_NONE || pb->quad != OR_QUAD_CENTRE) return -2;
     double x[OR_MAXN], w[OR_MAXN];
     or_jg11(n, x, w);
     /* Phi[j][p] = prod_i phi_{p_i}(x_{j_i}) */

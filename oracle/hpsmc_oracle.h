@@ -71,6 +71,7 @@ typedef struct {
     uint64_t seed;
     int32_t estimator;        /* OR_EST_RESIDUAL or OR_EST_PICARD               */
     int32_t accel;            /* OR_ACCEL_NONE or OR_ACCEL_AITKEN               */
+    int32_t quad;             /* OR_QUAD_CENTRE or OR_QUAD_BALL                 */
     double omega[3];          /* Aitken: first weight, lower and upper bound of
                                  the weight; a zero entry selects 1, 0.5, 2     */
 } or_problem;
@@ -78,6 +79,12 @@ typedef struct {
 /* acceleration of the fixed-point iteration (the remark after Algorithm 1):
  * none, or Aitken's delta-squared extrapolation in relaxation form */
 enum { OR_ACCEL_NONE = 0, OR_ACCEL_AITKEN = 1 };
+
+/* path quadrature of one walk step: the integrand at the ball centre X_q
+ * (eq. interIQ), or at a point Y_q drawn in the ball B_r(X_q) from the
+ * normalized Green's function density Q_r (the path-integral representation
+ * of the error analysis, Sec. 3), with the same weight Delta = W(X_q) */
+enum { OR_QUAD_CENTRE = 0, OR_QUAD_BALL = 1 };
 
 /* estimators: eq. varepsilon_1 (the residual increment, added to the iterate)
  * or eq. uast (the Picard form: the iterate itself, replacing it) */
@@ -123,6 +130,11 @@ int or_grid(const or_problem *pb, int interval, double *x_nodes, double *t_nodes
 
 /* initial nodal values of one instance, n^d entries */
 int or_ic_nodes(const or_problem *pb, int inst, double *u0);
+
+/* the ball point of walk step q of a path as an offset in the unit ball
+ * (Y_q = X_q + J * offset), OR_QUAD_BALL's law */
+int or_ball_offset(const or_problem *pb, int inst, int interval, int iter_tag, int64_t node,
+                   int64_t sample, int64_t q, double *offset);
 
 /* one sample path of the residual estimator (eq. interIQ, eq. varepsilon_1):
  * returns S = Delta * sum_{q<L} r(X_q, tau_q); *L_out = L. */

@@ -38,12 +38,13 @@ class _Problem(C.Structure):
         ("f_param", C.c_double * 4), ("src_param", C.c_double * 8), ("ic_param", C.c_double * 4),
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
-        ("estimator", C.c_int32), ("accel", C.c_int32), ("omega", C.c_double * 3),
+        ("estimator", C.c_int32), ("accel", C.c_int32), ("quad", C.c_int32), ("omega", C.c_double * 3),
     ]
 
 
 ESTIMATORS = {"residual": 0, "picard": 1}
 ACCELS = {"none": 0, "aitken": 1}
+QUADS = {"centre": 0, "ball": 1}
 
 
 _lib = None
@@ -72,6 +73,7 @@ def lib():
             "or_estimate": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, p, p, i64, i64, i64, p, p, p]),
             "or_iterate": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, p, p, p]),
             "or_iterate_aitken": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, p, p, p, p, p]),
+            "or_ball_offset": (C.c_int, [pp, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int64, C.c_int64, p]),
             "or_solve": (C.c_int, [pp, C.c_int, p, p]),
             "or_loss_grad": (C.c_int, [pp, C.c_int, p, p, p, p]),
             "or_exit_fraction": (d, [C.c_int, d, C.c_int, p, i64, C.c_uint64]),
@@ -199,6 +201,7 @@ class Problem:
         s.M, s.iters, s.fresh_per_iter, s.seed = wl.M, wl.iters, int(wl.fresh_per_iter), wl.seed
         s.estimator = ESTIMATORS[getattr(wl, "estimator", "residual")]
         s.accel = ACCELS[getattr(wl, "accel", "none")]
+        s.quad = QUADS[getattr(wl, "quad", "centre")]
         for i, v in enumerate(getattr(wl, "omega", [0.0, 0.0, 0.0])):
             s.omega[i] = v
         self.s = s
@@ -272,6 +275,13 @@ class Problem:
         st = np.zeros(1, dtype=np.int64)
         _check(lib().or_iterate(self.ref, inst, iv, iter_tag, _ptr(U), _ptr(mx), _ptr(st)), "iterate")
         return U, float(mx[0]), int(st[0])
+
+    def ball_offset(self, node, sample, q, inst=0, iv=0, iter_tag=0):
+        """the ball point of walk step q as an offset in the unit ball"""
+        out = np.zeros(self.wl.dim)
+        _check(lib().or_ball_offset(self.ref, inst, iv, iter_tag, int(node), int(sample), int(q), _ptr(out)),
+               "ball_offset")
+        return out
 
     def iterate_aitken(self, U, r_prev, state, inst=0, iv=0, iter_tag=0):
         """one Aitken-relaxed iteration; r_prev (n^d M) and state [w, have_prev]

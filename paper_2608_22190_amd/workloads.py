@@ -48,6 +48,7 @@ class Workload:
     tol: float = 0.0            # > 0: stop an interval once max|eps| < tol (Algorithm 1's loop condition)
     estimator: str = "residual" # "residual" (eq. varepsilon_1) or "picard" (eq. uast, classical MC form)
     accel: str = "none"         # "none" or "aitken" (relaxed iteration, remark after Algorithm 1)
+    quad: str = "centre"        # path quadrature: "centre" (eq. interIQ) or "ball" (Green's-function ball point)
     omega: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])  # Aitken w0, w_min, w_max (0: default)
 
     @property
