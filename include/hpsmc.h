@@ -105,6 +105,18 @@ enum { HPSMC_ACCEL_NONE = 0,      /* Algorithm 1's update: U += eps             
                                      solve, and after hpsmc_set_nodes of the
                                      interval.  No gradient                       */
 
+enum { HPSMC_QUAD_CENTRE = 0,     /* eq. interIQ: a walk step adds Delta * r at its
+                                     ball centre X_q                               */
+       HPSMC_QUAD_BALL = 1 };     /* the path-integral representation of a step in
+                                     the error analysis (Sec. 3): Delta * r(Y_q) with
+                                     Y_q drawn in the ball B_J(X_q) from the
+                                     normalized Green's function of -Laplace with
+                                     pole at X_q (Y_q = X_q + J sqrt(U_a) U_b^{1/d}
+                                     theta, theta uniform; Philox counter word 2
+                                     with bit 31 set, 2q and, for d >= 3, 2q+1).
+                                     Y_q may lie outside Omega.  Vector-unit round
+                                     kernel only; no gradient                     */
+
 enum { HPSMC_FP64 = 0,            /* everything in FP64                            */
        HPSMC_FP32_SAMPLING = 1 }; /* paths and basis evaluation in FP32 with
                                      compensated accumulation; reconstruction,
@@ -135,6 +147,7 @@ typedef struct {
                                   after every iteration, so hpsmc_solve runs
                                   eagerly even with the "graph" option          */
     int32_t accel;             /* HPSMC_ACCEL_NONE (default) or HPSMC_ACCEL_AITKEN */
+    int32_t quad;              /* HPSMC_QUAD_CENTRE (default) or HPSMC_QUAD_BALL  */
     double omega[3];           /* Aitken: first weight, lower and upper bound;
                                   0 selects 1, 0.5, 2; need 0 < omega[1] <=
                                   omega[0] <= omega[2] after the defaults       */

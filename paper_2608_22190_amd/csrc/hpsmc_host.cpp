@@ -398,6 +398,7 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     if (!std::isfinite(pb->tol) || pb->tol < 0.0) return fail(HPSMC_EINVAL, "tol must be finite and >= 0");
     if (pb->estimator < 0 || pb->estimator > 1) return fail(HPSMC_EINVAL, "unknown estimator");
     if (pb->accel < 0 || pb->accel > 1) return fail(HPSMC_EINVAL, "unknown accel");
+    if (pb->quad < 0 || pb->quad > 1) return fail(HPSMC_EINVAL, "unknown quad");
     if (pb->accel == HPSMC_ACCEL_AITKEN) {
         double w[3];
         aitken_weights(pb, w);
@@ -462,7 +463,8 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     const int64_t rows = ipow(plan->P, d - 1);
     const int64_t stride = rows * 2 * plan->PP;
     // plans the matrix-core round kernel can serve also get offsets in its slab layout
-    const bool mma_ok = advance_mma_eligible(plan->fp32, d, plan->P, 0, 1, 4) && plan->pb.estimator == HPSMC_EST_RESIDUAL;
+    const bool mma_ok = advance_mma_eligible(plan->fp32, d, plan->P, 0, 1, 4) &&
+                        plan->pb.estimator == HPSMC_EST_RESIDUAL && plan->pb.quad == HPSMC_QUAD_CENTRE;
     const int extra = plan->pb.estimator == HPSMC_EST_PICARD ? 1 : 0;   // the slab of q = N* (t = t_{n-1})
     const int64_t mstride = mma_slab_elems(plan->PP);
     int64_t slab_pos = 0, slab_pos_mma = 0, out = 0;
@@ -694,6 +696,7 @@ static Physics physics_of(const hpsmc_plan *plan)
     ph.f_kind = plan->pb.f_kind;
     ph.src_kind = plan->pb.src_kind;
     ph.picard = plan->pb.estimator == HPSMC_EST_PICARD;
+    ph.ball = plan->pb.quad == HPSMC_QUAD_BALL;
     memcpy(ph.f_param, plan->pb.f_param, sizeof(ph.f_param));
     memcpy(ph.src_param, plan->pb.src_param, sizeof(ph.src_param));
     return ph;
@@ -823,8 +826,9 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
     HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
     if (es) HIP_TRY(hipEventRecord(es->b, s));
     if (set.rounds) return sample_rounds(plan, set, tag, record, s);
-    if (plan->pb.estimator != HPSMC_EST_RESIDUAL)
-        return fail(HPSMC_ENOTSUP, "the Picard form needs the round kernel (slab too large for LDS chunks)");
+    if (plan->pb.estimator != HPSMC_EST_RESIDUAL || plan->pb.quad != HPSMC_QUAD_CENTRE)
+        return fail(HPSMC_ENOTSUP, "the Picard form and the ball quadrature need the round kernel (slab too large "
+                                   "for LDS chunks)");
     HIP_TRY(launch_fill_u64(plan->counters, 1, 0ull, s));
     SampleArgs a{};
     a.nodes = set.dev;
@@ -1470,11 +1474,12 @@ static std::string tune_key(const hpsmc_plan *plan, int iv, int64_t M)
     }
     // plans that may run the matrix-core round kernel tune separately from those that may not
     const bool picard = plan->pb.estimator == HPSMC_EST_PICARD;
-    const bool mma = plan->sample_mma && !picard && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
+    const bool ball = plan->pb.quad == HPSMC_QUAD_BALL;
+    const bool mma = plan->sample_mma && !picard && !ball && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
     char buf[256];
-    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
-             plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", picard ? "_picard" : "", (long long)M, plan->n_inst,
-             arch.c_str());
+    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
+             plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", picard ? "_picard" : "", ball ? "_ball" : "",
+             (long long)M, plan->n_inst, arch.c_str());
     return buf;
 }
 
@@ -1836,6 +1841,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
         return fail(HPSMC_ENOTSUP, "the adjoint kernel covers dim <= 2 and n <= 30");
     if (plan->pb.estimator != HPSMC_EST_RESIDUAL) return fail(HPSMC_ENOTSUP, "the adjoint is that of the residual form");
     if (plan->pb.accel != HPSMC_ACCEL_NONE) return fail(HPSMC_ENOTSUP, "the adjoint is that of the unrelaxed iteration");
+    if (plan->pb.quad != HPSMC_QUAD_CENTRE) return fail(HPSMC_ENOTSUP, "the adjoint is that of the centre-point rule");
     hipStream_t s = (hipStream_t)stream;
     const int d = plan->d, n = plan->n, P = plan->P, K = plan->pb.iters, T1 = plan->degree[0] + 1;
     const int64_t I = plan->n_inst, nsp = plan->nsp, psp = plan->psp;

@@ -44,6 +44,8 @@ struct GroupDesc {
 struct Physics {
     int32_t dim, f_kind, src_kind;
     int32_t picard;              // 1: Picard-form estimator (eq. uast)
+    int32_t ball;                // 1: integrand at the step's Green's-function ball point
+    int32_t reserved;
     double f_param[4];
     double src_param[8];
 };

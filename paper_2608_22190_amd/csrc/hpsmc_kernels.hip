@@ -108,6 +108,57 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
 }
 
 // ---------------------------------------------------------------------------
+// Ball point of walk step q (the Green's-function representation of a step's
+// path integral, Sec. 3): an offset in the unit ball whose radius s has the
+// density of s^{d-1} G(s), G the Green's function of -Laplace on the ball with
+// pole at its centre -- the law of sqrt(U_a) * U_b^{1/d} -- in a uniform
+// direction.  Counter word 2 = bit 31 | 2q (radius words 0, 1; direction
+// words 2, 3) and, for d >= 3, bit 31 | (2q + 1) for two more normal pairs.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ void ball_offset(uint32_t c0, uint32_t c1, int q, uint32_t c3, uint32_t k0, uint32_t k1,
+                                            T (&off)[D])
+{
+    uint32_t o[4];
+    philox(c0, c1, 0x80000000u | (uint32_t)(2 * q), c3, k0, k1, o);
+    const T ua = u01(o[0], (T)0), ub = u01(o[1], (T)0);
+    T root;
+    if constexpr (D == 1) root = ub;
+    else if constexpr (D == 2) root = m_sqrt(ub);
+    else if constexpr (D == 3) root = sizeof(T) == 4 ? (T)cbrtf((float)ub) : (T)cbrt((double)ub);
+    else if constexpr (D == 4) root = m_sqrt(m_sqrt(ub));
+    else root = sizeof(T) == 4 ? (T)powf((float)ub, 0.2f) : (T)pow((double)ub, 0.2);
+    const T sr = m_sqrt(ua) * root;
+    if constexpr (D == 1) {
+        off[0] = (o[2] & 1u) ? sr : -sr;
+    } else if constexpr (D == 2) {
+        T c, sn;
+        angle_dir(u01(o[2], (T)0), c, sn);
+        off[0] = sr * c;
+        off[1] = sr * sn;
+    } else {
+        uint32_t o2[4];
+        philox(c0, c1, 0x80000000u | (uint32_t)(2 * q + 1), c3, k0, k1, o2);
+        const uint32_t ww[6] = {o[2], o[3], o2[0], o2[1], o2[2], o2[3]};
+        T g[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T r = m_sqrt((T)-2 * m_log(u01(ww[2 * k], (T)0)));
+            T c, sn;
+            angle_dir(u01(ww[2 * k + 1], (T)0), c, sn);
+            g[2 * k] = r * c;
+            g[2 * k + 1] = r * sn;
+        }
+        T nrm = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) nrm += g[i] * g[i];
+        nrm = m_sqrt(nrm);
+#pragma unroll
+        for (int i = 0; i < D; ++i) off[i] = sr * g[i] / nrm;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Problem terms.
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1293,7 +1344,21 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                 any_live = any_live || alive[s];
             }
             slots += NS;
-            // ---- residual at X_q, time tau_q = t_{n,l} - q Delta: the slab of step q
+            // ---- the point where step q's integrand is evaluated: the ball centre
+            // X_q (eq. interIQ) or the step's Green's-function ball point
+            T E[NS][D];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) E[s][i] = X[s][i];
+                if (a.phys.ball && alive[s]) {
+                    T off[D];
+                    ball_offset<T, D>(c0[s], sample[s], q, c3, a.key0, a.key1, off);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) E[s][i] = m_fma(J, off[i], X[s][i]);
+                }
+            }
+            // ---- residual at E_q, time tau_q = t_{n,l} - q Delta: the slab of step q
             // streams through LDS in NC chunks (double buffered along the chunk sequence)
             const bool wave_live = __ballot(any_live) != 0ull;
             T u[NS], v[NS];
@@ -1302,7 +1367,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
             T Ll[NS][PMAX];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const T x = X[s][D - 1];
+                const T x = E[s][D - 1];
                 Ll[s][0] = (T)1;
                 if (PMAX > 1) Ll[s][1] = x;
 #pragma unroll
@@ -1339,7 +1404,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                             for (int s = 0; s < NS; ++s) {
                                 T lp = (T)0, lc = (T)1;
                                 for (int m = 0; m < ki; ++m) {
-                                    const T nx = rec_a<T>(m) * X[s][i] * lc - rec_b<T>(m) * lp;
+                                    const T nx = rec_a<T>(m) * E[s][i] * lc - rec_b<T>(m) * lp;
                                     lp = lc;
                                     lc = nx;
                                 }
@@ -1347,7 +1412,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                             }
                         }
                     }
-                    contract<T, D, PMAX, NS, CF, const T *>(S, a.P, a.PP, X, Wc, Ll, u, v, 0, a.phys.picard != 0);
+                    contract<T, D, PMAX, NS, CF, const T *>(S, a.P, a.PP, E, Wc, Ll, u, v, 0, a.phys.picard != 0);
                 }
                 if (has_next) {
                     u32x4 *dst = lds + (int64_t)(buf ^ 1) * cvec;
@@ -1364,7 +1429,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (alive[s]) {
-                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D>(a.phys, X[s], tf) +
+                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D>(a.phys, E[s], tf) +
                                     (a.phys.picard ? (T)0 : v[s]);
                         const T y = delta * r;
                         if constexpr (sizeof(T) == 4) {
@@ -1853,8 +1918,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
         const int nstar = G->nstar;
         const int q0 = a.round * a.steps;
         const int q1 = min(q0 + a.steps, nstar);
-        const T delta = (T)G->delta, J = (T)G->jump;
-        const double span = G->span, t_prev = G->t_prev, ddelta = G->delta;
+        const T J = (T)G->jump;
+        const double ddelta = G->delta;
         const uint32_t c3 = G->c3 | (uint32_t)a.tag;
         const int64_t live = a.round == 0 ? (int64_t)G->node_count * a.mcount : (int64_t)a.live_in[g];
         const T *gtab = (const T *)a.slab_table + G->slab;

@@ -26,6 +26,7 @@ SCHEDULES = {"sequential": 0, "sweeps": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 ESTIMATORS = {"residual": 0, "picard": 1}
 ACCELS = {"none": 0, "aitken": 1}
+QUADS = {"centre": 0, "ball": 1}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSUP", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED", -6: "ENOTCONVERGED"}
 ENOTCONVERGED = -6
 
@@ -45,7 +46,7 @@ class hpsmc_problem(C.Structure):
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
         ("precision", C.c_int32), ("estimator", C.c_int32), ("tol", C.c_double),
-        ("accel", C.c_int32), ("omega", C.c_double * 3),
+        ("accel", C.c_int32), ("quad", C.c_int32), ("omega", C.c_double * 3),
     ]
 
 
@@ -160,6 +161,7 @@ def make_problem(wl):
     p.tol = float(getattr(wl, "tol", 0.0))
     p.estimator = ESTIMATORS[getattr(wl, "estimator", "residual")]
     p.accel = ACCELS[getattr(wl, "accel", "none")]
+    p.quad = QUADS[getattr(wl, "quad", "centre")]
     for i, v in enumerate(getattr(wl, "omega", [0.0, 0.0, 0.0])):
         p.omega[i] = v
     return p, [tb, deg, ns, ic]
