@@ -132,10 +132,14 @@ def run_other(name, args, torch):
         return run_compare(args, torch)
     if name == "aitken":
         return run_aitken(args, torch)
+    if name == "ballcmp":
+        return run_ballcmp(args, torch)
     if name == "c1":
         wl = W.c1_single_step()
     elif name == "c2p":
         wl = W.c2_long_time(M=m, iters=args.steps + args.warmup, n_intervals=1, estimator="picard")
+    elif name == "c2b":
+        wl = W.c2_long_time(M=m, iters=args.steps + args.warmup, n_intervals=1, quad="ball")
     elif name == "c3":
         wl = W.c3_initial_singularity(M=m, sweeps=args.steps + args.warmup)
     elif name == "c4":
@@ -146,15 +150,15 @@ def run_other(name, args, torch):
     with hpsmc.Plan(wl) as plan:
         if args.launch:
             plan.hpsmc_set_launch(*(int(v) for v in args.launch.split(",")))
-        elif args.tune_cache and name in ("c2p", "c3", "c4", "c5"):
+        elif args.tune_cache and name in ("c2p", "c2b", "c3", "c4", "c5"):
             t0 = time.perf_counter()
-            plan.hpsmc_tune(0, 256 if name == "c2p" else min(wl.M, 4), args.tune_cache, stream=stream)
+            plan.hpsmc_tune(0, 256 if name in ("c2p", "c2b") else min(wl.M, 4), args.tune_cache, stream=stream)
             print(f"[bench] {name} launch {plan.hpsmc_get_launch()} ({time.perf_counter() - t0:.1f}s)",
                   file=sys.stderr, flush=True)
         def step(k):
             if name == "c1":
                 plan.hpsmc_solve(stream=stream)
-            elif name == "c2p":
+            elif name in ("c2p", "c2b"):
                 plan.hpsmc_iterate(0, k, stream=stream)
             elif name == "c3":
                 plan.hpsmc_sweep(k, stream=stream)
@@ -186,6 +190,8 @@ def run_other(name, args, torch):
     launches = max(1, st["advance_launches"] or st["sample_launches"])
     desc = {"c1": "c1_1d_single_step: whole solve (5 iterations, 256 nodes x M=4096), FP64, hipGraph replay",
             "c2p": f"c2_2d_long_time interval 1, one Picard-form (classical Monte Carlo, eq. uast) iteration, "
+                   f"{nodes} nodes x samples 0..{m - 1} of M=65536, FP32 sampling",
+            "c2b": f"c2_2d_long_time interval 1, one residual iteration with the ball-point path quadrature, "
                    f"{nodes} nodes x samples 0..{m - 1} of M=65536, FP32 sampling",
             "c3": f"c3_2d_initial_singularity: one sweep over all 12 geometric intervals ({nodes} nodes, "
                   f"degrees 4..26) x samples 0..{m - 1} of M=32768, FP32",
@@ -243,6 +249,40 @@ def run_compare(args, torch):
             "config": {"workload": "1-D long-time problem to T=10 in unit intervals, residual form against the "
                                    "Picard (classical Monte Carlo) form, 16 x 16 nodes per interval, M=4096, "
                                    "6 iterations per interval, FP64"},
+            "comparison": out}
+    print(json.dumps(line), flush=True)
+
+
+def run_ballcmp(args, torch):
+    """Centre-point (eq. interIQ) against ball-point path quadrature on the
+    single-step problem (1-D, u = e^{-t} sin(pi x), 16 x 16 nodes, M = 4096,
+    FP64, fresh samples): error against the exact solution after K = 1..8
+    iterations, time of the whole 8-iteration solve."""
+    from paper_2608_22190_amd import hpsmc, workloads as W
+    out = {}
+    for quad in ("centre", "ball"):
+        errs, secs = [], 0.0
+        for k in range(1, 9):
+            wl = W.c1_single_step(iters=k).with_(quad=quad)
+            with hpsmc.Plan(wl) as plan:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan.hpsmc_solve()
+                torch.cuda.synchronize()
+                secs = time.perf_counter() - t0
+                x, t = plan.hpsmc_grid(0)
+                ex = np.sin(np.pi * x)[:, None] * np.exp(-t)[None, :]
+                errs.append(float(np.max(np.abs(plan.hpsmc_get_nodes(0)[0] - ex))))
+        out[quad] = {"error_after_k": errs, "seconds_8_iterations": secs}
+        print(f"[bench] ballcmp {quad}: {secs:.2f}s for 8 iterations, errors "
+              f"{', '.join(f'{e:.2e}' for e in errs)}", file=sys.stderr, flush=True)
+    wl = W.c1_single_step(iters=8)
+    line = {"metric": METRIC, "value": wl.nodes_per_sweep * wl.M * 8 / out["ball"]["seconds_8_iterations"],
+            "unit": "node-samples/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": 1e3 * out["ball"]["seconds_8_iterations"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "c1_1d_single_step, 8 iterations, ball-point against centre-point path "
+                                   "quadrature, fresh samples"},
             "comparison": out}
     print(json.dumps(line), flush=True)
 
@@ -324,7 +364,8 @@ def main():
     ap.add_argument("--m-slice", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c3", "c4", "c5", "compare", "aitken"])
+    ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c2b", "c3", "c4", "c5", "compare", "aitken",
+                                                              "ballcmp"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--launch", type=str, default="",
