@@ -286,6 +286,252 @@ int or_eval(int dim, int n, int M, double h, const double *Ut,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Fractional operator (Ex. 2-3; the remark that the method carries over with */
+/* an alpha-stable walk and generalized Jacobi functions of parameter         */
+/* (alpha/2, alpha/2)).  d = 1.                                                */
+/* ------------------------------------------------------------------------ */
+static int or_is_frac(const or_problem *pb) { return pb->alpha > 0.0 && pb->alpha < 2.0; }
+
+/* Jacobi P_p^{(al,be)} by the standard three-term recurrence */
+static double or_jacobi_ab(int p, double al, double be, double x)
+{
+    if (p == 0) return 1.0;
+    double pm = 1.0, pc = 0.5 * (al - be) + 0.5 * (al + be + 2.0) * x;
+    for (int k = 1; k < p; ++k) {
+        double s2 = 2.0 * k + al + be;
+        double c1 = 2.0 * (k + 1.0) * (k + al + be + 1.0) * s2;
+        double c2 = (s2 + 1.0) * (al * al - be * be);
+        double c3 = s2 * (s2 + 1.0) * (s2 + 2.0);
+        double c4 = 2.0 * (k + al) * (k + be) * (s2 + 2.0);
+        double pn = ((c2 + c3 * x) * pc - c4 * pm) / c1;
+        pm = pc; pc = pn;
+    }
+    return pc;
+}
+
+double or_jacobi_aa(int p, double a, double x) { return or_jacobi_ab(p, a, a, x); }
+
+/* Gauss-Jacobi rule for the weight (1-x^2)^a: zeros of P_n^{(a,a)} by Newton's
+ * method with deflation (P_n' = (n+2a+1)/2 P_{n-1}^{(a+1,a+1)}), weights
+ *   w_j = 2^{2a+1} Gamma(n+a+1)^2 / (n! Gamma(n+2a+1) (1-x_j^2) P_n'(x_j)^2). */
+int or_gauss_jacobi(int n, double a, double *x, double *w)
+{
+    if (n < 1 || !(a > -1.0)) return -1;
+    for (int j = 0; j < n; ++j) {
+        double z = -cos(OR_PI * (j + 0.75) / (n + 0.5));
+        for (int it = 0; it < 200; ++it) {
+            double p = or_jacobi_ab(n, a, a, z);
+            double dp = 0.5 * (n + 2.0 * a + 1.0) * or_jacobi_ab(n - 1, a + 1.0, a + 1.0, z);
+            double sdef = 0.0;
+            for (int i = 0; i < j; ++i) sdef += 1.0 / (z - x[i]);
+            double dz = p / (dp - sdef * p);
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        x[j] = z;
+    }
+    for (int i = 1; i < n; ++i)
+        for (int k = i; k > 0 && x[k - 1] > x[k]; --k) { double t = x[k]; x[k] = x[k - 1]; x[k - 1] = t; }
+    double lc = (2.0 * a + 1.0) * log(2.0) + 2.0 * lgamma(n + a + 1.0) - lgamma(n + 1.0) - lgamma(n + 2.0 * a + 1.0);
+    for (int j = 0; j < n; ++j) {
+        double dp = 0.5 * (n + 2.0 * a + 1.0) * or_jacobi_ab(n - 1, a + 1.0, a + 1.0, x[j]);
+        w[j] = exp(lc) / ((1.0 - x[j] * x[j]) * dp * dp);
+    }
+    return 0;
+}
+
+/* (-Delta)^{alpha/2} [(1-x^2)_+^{alpha/2} P_p^{(alpha/2,alpha/2)}] = lambda_p P_p^{(alpha/2,alpha/2)}
+ * on (-1,1), lambda_p = Gamma(p+alpha+1)/p! (the operator with Fourier symbol |xi|^alpha) */
+double or_frac_lambda(int p, double alpha) { return exp(lgamma(p + alpha + 1.0) - lgamma(p + 1.0)); }
+
+/* regularized incomplete beta I_x(a,b) by the continued fraction of DLMF 8.17.22
+ * (modified Lentz), with I_x(a,b) = 1 - I_{1-x}(b,a) beyond (a+1)/(a+b+2) */
+double or_ibeta(double x, double a, double b)
+{
+    if (x <= 0.0) return 0.0;
+    if (x >= 1.0) return 1.0;
+    if (x > (a + 1.0) / (a + b + 2.0)) return 1.0 - or_ibeta(1.0 - x, b, a);
+    double lpre = a * log(x) + b * log1p(-x) - log(a) - (lgamma(a) + lgamma(b) - lgamma(a + b));
+    const double tiny = 1e-300;
+    double f = 1.0, C = 1.0, D = 0.0;
+    for (int j = 1; j < 2000; ++j) {
+        int m = j / 2;
+        double dj = (j & 1) ? -(a + m) * (a + b + m) * x / ((a + 2.0 * m) * (a + 2.0 * m + 1.0))
+                            : m * (b - m) * x / ((a + 2.0 * m - 1.0) * (a + 2.0 * m));
+        D = 1.0 + dj * D;
+        if (fabs(D) < tiny) D = tiny;
+        C = 1.0 + dj / C;
+        if (fabs(C) < tiny) C = tiny;
+        D = 1.0 / D;
+        double del = C * D;
+        f *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return exp(lpre) / f;
+}
+
+/* inverse in x of I_x(a,b) = y by bisection on log x over [-745, 0] */
+double or_ibeta_inv(double y, double a, double b)
+{
+    double lo = -745.0, hi = 0.0;
+    for (int it = 0; it < 90; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (or_ibeta(exp(mid), a, b) < y) lo = mid; else hi = mid;
+    }
+    return exp(0.5 * (lo + hi));
+}
+
+/* Jump length of the alpha-stable walk from the centre of its ball.  The
+ * ball radius r = (Delta / C_1^alpha)^{1/alpha} with C_1^alpha = 1/Gamma(1+alpha)
+ * (the mean exit time of the ball is Delta).  The exit point Y of the process
+ * started at the centre has P(|Y| > rho) = I_{r^2/rho^2}(alpha/2, 1 - alpha/2)
+ * (the exit law of a ball for a symmetric stable process), so a uniform omega
+ * gives rho = r / sqrt(I^{-1}(omega; alpha/2, 1 - alpha/2)). */
+double or_frac_jump(double alpha, double delta, double omega)
+{
+    double r = pow(delta * exp(lgamma(1.0 + alpha)), 1.0 / alpha);
+    return r / sqrt(or_ibeta_inv(omega, 0.5 * alpha, 1.0 - 0.5 * alpha));
+}
+
+/* nodal -> modal: collocation solve sum_p c_p w(x_j) P_p(x_j) = U_j (Gaussian
+ * elimination with partial pivoting) for every time column, then B in time */
+int or_frac_reconstruct(double alpha, int n, int M, const double *U, double *Ut)
+{
+    int T1 = M + 1;
+    double a = 0.5 * alpha, x[OR_MAXN], w[OR_MAXN];
+    if (n < 1 || n > OR_MAXN || M < 1 || or_gauss_jacobi(n, a, x, w)) return -1;
+    double *Phi = malloc(sizeof(double) * n * n), *rhs = malloc(sizeof(double) * n * T1);
+    double *B = malloc(sizeof(double) * T1 * T1), *C = malloc(sizeof(double) * n * T1);
+    if (!Phi || !rhs || !B || !C) { free(Phi); free(rhs); free(B); free(C); return -3; }
+    for (int j = 0; j < n; ++j)
+        for (int p = 0; p < n; ++p) Phi[j * n + p] = pow(1.0 - x[j] * x[j], a) * or_jacobi_aa(p, a, x[j]);
+    memcpy(rhs, U, sizeof(double) * n * T1);
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r) if (fabs(Phi[r * n + c]) > fabs(Phi[piv * n + c])) piv = r;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) { double t = Phi[c * n + k]; Phi[c * n + k] = Phi[piv * n + k]; Phi[piv * n + k] = t; }
+            for (int k = 0; k < T1; ++k) { double t = rhs[c * T1 + k]; rhs[c * T1 + k] = rhs[piv * T1 + k]; rhs[piv * T1 + k] = t; }
+        }
+        for (int r = c + 1; r < n; ++r) {
+            double m = Phi[r * n + c] / Phi[c * n + c];
+            for (int k = c; k < n; ++k) Phi[r * n + k] -= m * Phi[c * n + k];
+            for (int k = 0; k < T1; ++k) rhs[r * T1 + k] -= m * rhs[c * T1 + k];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c)
+        for (int k = 0; k < T1; ++k) {
+            double s = rhs[c * T1 + k];
+            for (int q = c + 1; q < n; ++q) s -= Phi[c * n + q] * C[q * T1 + k];
+            C[c * T1 + k] = s / Phi[c * n + c];
+        }
+    or_matrix_B(M, B);
+    or_mode_product(C, Ut, n, T1, 1, B);
+    free(Phi); free(rhs); free(B); free(C);
+    return 0;
+}
+
+int or_frac_eval(double alpha, int n, int M, double h, const double *Ut, double x, double xi, double out[3])
+{
+    int T1 = M + 1;
+    double a = 0.5 * alpha, Lt[OR_MAXN], dLt[OR_MAXN];
+    if (n > OR_MAXN || T1 > OR_MAXN) return -1;
+    or_legendre_all(M, xi, Lt, dLt, NULL);
+    double w = pow(1.0 - x * x, a), u = 0.0, ut = 0.0, F = 0.0;
+    for (int p = 0; p < n; ++p) {
+        double J = or_jacobi_aa(p, a, x), lam = or_frac_lambda(p, alpha);
+        double su = 0.0, st = 0.0;
+        for (int q = 0; q < T1; ++q) { su += Ut[p * T1 + q] * Lt[q]; st += Ut[p * T1 + q] * dLt[q]; }
+        u += J * su;
+        ut += J * st;
+        F += lam * J * su;
+    }
+    out[0] = w * u;
+    out[1] = (2.0 / h) * w * ut;
+    out[2] = -F;
+    return 0;
+}
+
+/* Manufactured fractional solutions u = w g T: (-Delta)^{alpha/2}(w g) =
+ * sum_k a_k lambda_k P_k^{(a,a)} with a_k the Jacobi coefficients of g
+ * (Gauss-Jacobi quadrature with 160 nodes).  Cached per (alpha, kind, params);
+ * or_frac_prepare runs outside parallel regions. */
+#define OR_FRAC_NQ 160
+#define OR_FRAC_K 150
+static struct { int valid, kind; double alpha, par[4]; int K; double c[OR_FRAC_K]; } or_fsrc;
+
+static double or_frac_g(int kind, const double *par, double x)
+{
+    switch (kind) {
+    case OR_SRC_FRAC_LONGTIME: return sin(x);
+    case OR_SRC_FRAC_SINGULAR: return cos(x * x * x + 1.0) / (10.0 * x * x + 1.0);
+    case OR_SRC_FRAC_POLY: return par[0] + par[1] * x + par[2] * x * x;
+    }
+    return 0.0;
+}
+
+static int or_frac_prepare(const or_problem *pb)
+{
+    int kind = pb->src_kind;
+    if (kind < OR_SRC_FRAC_LONGTIME || kind > OR_SRC_FRAC_POLY) return 0;
+    if (or_fsrc.valid && or_fsrc.kind == kind && or_fsrc.alpha == pb->alpha &&
+        memcmp(or_fsrc.par, pb->src_param, sizeof(or_fsrc.par)) == 0) return 0;
+    double a = 0.5 * pb->alpha;
+    double *x = malloc(sizeof(double) * OR_FRAC_NQ), *w = malloc(sizeof(double) * OR_FRAC_NQ);
+    if (!x || !w) { free(x); free(w); return -3; }
+    or_gauss_jacobi(OR_FRAC_NQ, a, x, w);
+    int K = kind == OR_SRC_FRAC_POLY ? 3 : kind == OR_SRC_FRAC_LONGTIME ? 40 : OR_FRAC_K;
+    for (int k = 0; k < K; ++k) {
+        /* ||P_k||^2 = 2^{2a+1} Gamma(k+a+1)^2 / ((2k+2a+1) k! Gamma(k+2a+1)) */
+        double nrm = exp((2.0 * a + 1.0) * log(2.0) + 2.0 * lgamma(k + a + 1.0) - lgamma(k + 1.0) -
+                         lgamma(k + 2.0 * a + 1.0)) / (2.0 * k + 2.0 * a + 1.0);
+        double s = 0.0;
+        for (int j = 0; j < OR_FRAC_NQ; ++j) s += w[j] * or_frac_g(kind, pb->src_param, x[j]) * or_jacobi_aa(k, a, x[j]);
+        or_fsrc.c[k] = s / nrm * or_frac_lambda(k, pb->alpha);
+    }
+    free(x); free(w);
+    or_fsrc.K = K;
+    or_fsrc.kind = kind;
+    or_fsrc.alpha = pb->alpha;
+    memcpy(or_fsrc.par, pb->src_param, sizeof(or_fsrc.par));
+    or_fsrc.valid = 1;
+    return 0;
+}
+
+static void or_frac_exact_parts(const or_problem *pb, double x, double t, double *u, double *ut, double *lap)
+{
+    or_frac_prepare(pb);
+    double a = 0.5 * pb->alpha, w = pow(1.0 - x * x, a), g = or_frac_g(pb->src_kind, pb->src_param, x);
+    double T, Tp;
+    switch (pb->src_kind) {
+    case OR_SRC_FRAC_LONGTIME:
+        T = exp(cos(t)) / (1.0 + t * t);
+        Tp = T * (-sin(t) - 2.0 * t / (1.0 + t * t));
+        break;
+    case OR_SRC_FRAC_SINGULAR:
+        T = pow(t, pb->src_param[0]);
+        Tp = t > 0.0 ? pb->src_param[0] * pow(t, pb->src_param[0] - 1.0) : 0.0;
+        break;
+    default:
+        T = 1.0 + pb->src_param[3] * t;
+        Tp = pb->src_param[3];
+        break;
+    }
+    double F = 0.0;
+    for (int k = 0; k < or_fsrc.K; ++k) F += or_fsrc.c[k] * or_jacobi_aa(k, a, x);
+    *u = w * g * T;
+    *ut = w * g * Tp;
+    *lap = -F * T;            /* -(-Delta)^{alpha/2} u */
+}
+
+/* spatial nodes of the problem: JG(1,1), or Gauss-Jacobi (alpha/2, alpha/2) */
+static int or_space_nodes(const or_problem *pb, double *x, double *w)
+{
+    if (or_is_frac(pb)) return or_gauss_jacobi(pb->n, 0.5 * pb->alpha, x, w);
+    return or_jg11(pb->n, x, w);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Problem data: f, f', manufactured sources and exact solutions.             */
 /* ------------------------------------------------------------------------ */
 double or_f(const or_problem *pb, double u)
@@ -319,6 +565,10 @@ static void or_exact_parts(const or_problem *pb, const double *X, double t,
                            double *u, double *ut, double *lap)
 {
     int d = pb->dim;
+    if (pb->src_kind >= OR_SRC_FRAC_LONGTIME && pb->src_kind <= OR_SRC_FRAC_POLY) {
+        or_frac_exact_parts(pb, X[0], t, u, ut, lap);
+        return;
+    }
     switch (pb->src_kind) {
     case OR_SRC_SIN_DECAY: {
         double p = exp(-t);
@@ -377,7 +627,8 @@ double or_exact(const or_problem *pb, const double *X, double t)
 }
 
 /* s = u_t - Lap u - f(u) at the exact solution, so that the exact solution
- * satisfies u_t = Lap u + f(u) + s */
+ * satisfies u_t = Lap u + f(u) + s (fractional kinds: -(-Delta)^{alpha/2} in
+ * place of Lap) */
 double or_source(const or_problem *pb, const double *X, double t)
 {
     if (pb->src_kind == OR_SRC_NONE) return 0.0;
@@ -394,14 +645,15 @@ double or_residual(const or_problem *pb, int interval, const double *Ut,
     double t0 = pb->t_breaks[interval], h = pb->t_breaks[interval + 1] - t0;
     double xi = 2.0 * (tau - t0) / h - 1.0;
     double v[3];
-    or_eval(pb->dim, pb->n, pb->degree[interval], h, Ut, X, xi, v);
+    if (or_is_frac(pb)) or_frac_eval(pb->alpha, pb->n, pb->degree[interval], h, Ut, X[0], xi, v);
+    else or_eval(pb->dim, pb->n, pb->degree[interval], h, Ut, X, xi, v);
     return or_f(pb, v[0]) + or_source(pb, X, tau) - v[1] + v[2];
 }
 
 int or_grid(const or_problem *pb, int interval, double *x_nodes, double *t_nodes)
 {
     double w[OR_MAXN], xi[OR_MAXN];
-    if (x_nodes && or_jg11(pb->n, x_nodes, w)) return -1;
+    if (x_nodes && or_space_nodes(pb, x_nodes, w)) return -1;
     if (t_nodes) {
         int M = pb->degree[interval];
         if (or_lgl(M, xi, w)) return -1;
@@ -415,7 +667,7 @@ int or_ic_nodes(const or_problem *pb, int inst, double *u0)
 {
     double x[OR_MAXN], w[OR_MAXN];
     int d = pb->dim, n = pb->n;
-    if (or_jg11(n, x, w)) return -1;
+    if (or_space_nodes(pb, x, w)) return -1;
     int64_t nsp = or_ipow(n, d);
     for (int64_t jf = 0; jf < nsp; ++jf) {
         int ji[OR_MAXD];
@@ -567,7 +819,7 @@ typedef struct { double x[OR_MAXN]; double xi[OR_MAXN]; } or_ref;
 static void or_ref_nodes(const or_problem *pb, int interval, or_ref *rf)
 {
     double w[OR_MAXN];
-    or_jg11(pb->n, rf->x, w);
+    or_space_nodes(pb, rf->x, w);
     or_lgl(pb->degree[interval], rf->xi, w);
 }
 
@@ -622,7 +874,17 @@ static double or_path(const or_problem *pb, const double *Ut, int inst, int inte
     double acc = 0.0;
     int64_t q;
     for (q = 0; q < nd->nstar; ++q) {
-        or_direction(&st, d, q, dir);
+        if (or_is_frac(pb)) {
+            /* alpha-stable walk (d = 1): a uniform omega and a fair sign from the
+             * Philox block q/2, words 2(q mod 2) and 2(q mod 2) + 1 */
+            int64_t blk = q >> 1;
+            if (blk != st.blk) { or_stream_block(&st, blk, st.w); st.blk = blk; }
+            double om = or_u01(st.w[2 * (q & 1)]);
+            dir[0] = (st.w[2 * (q & 1) + 1] & 1u) ? 1.0 : -1.0;
+            J = or_frac_jump(pb->alpha, nd->delta, om);
+        } else {
+            or_direction(&st, d, q, dir);
+        }
         int outside = 0;
         for (int i = 0; i < d; ++i) {
             Y[i] = fma(J, dir[i], X[i]);
@@ -691,9 +953,18 @@ int or_estimate(const or_problem *pb, int inst, int interval, int iter_tag,
     int64_t nsp = or_ipow(n, d), size = nsp * (M + 1);
     int64_t cnt = m_hi - m_lo;
     if (cnt <= 0 || m_lo < 0) return -1;
+    if (or_is_frac(pb)) {
+        /* the fractional form: d = 1, residual estimator, centre-point rule */
+        if (d != 1 || pb->estimator != OR_EST_RESIDUAL || pb->quad != OR_QUAD_CENTRE) return -2;
+        int rc = or_frac_prepare(pb);
+        if (rc) return rc;
+    }
     double *Ut = malloc(sizeof(double) * size);
     if (!Ut) return -3;
-    if (or_reconstruct(d, n, M, U, Ut)) { free(Ut); return -1; }
+    if (or_is_frac(pb) ? or_frac_reconstruct(pb->alpha, n, M, U, Ut) : or_reconstruct(d, n, M, U, Ut)) {
+        free(Ut);
+        return -1;
+    }
     int64_t total = nodes ? n_nodes : nsp * M;
     int err = 0;
     or_ref rf;

@@ -47,7 +47,11 @@ enum { OR_SRC_NONE = 0,        /* s = 0                                         
        OR_SRC_SIN_DECAY = 1,   /* u_ex = exp(-t) prod sin(pi x_i)                    */
        OR_SRC_COS_DECAY = 2,   /* u_ex = exp(-t) prod cos(pi x_i / 2)                */
        OR_SRC_LONGTIME = 3,    /* u_ex = prod(1-x_i^2) sin(sum x_i) e^{cos t}/(1+t^2) */
-       OR_SRC_QUAD = 4 };      /* u_ex = prod(1-x_i^2) (c0 + c1 t + c2 t^2), src_param = {c0,c1,c2} */
+       OR_SRC_QUAD = 4,        /* u_ex = prod(1-x_i^2) (c0 + c1 t + c2 t^2), src_param = {c0,c1,c2} */
+       /* fractional operator (alpha in (0,2), d = 1), u_ex = (1-x^2)_+^{alpha/2} g(x) T(t): */
+       OR_SRC_FRAC_LONGTIME = 5, /* g = sin x, T = e^{cos t}/(1+t^2) (Ex. 2)             */
+       OR_SRC_FRAC_SINGULAR = 6, /* g = cos(x^3+1)/(10x^2+1), T = t^rho, rho = src_param[0] (Ex. 3) */
+       OR_SRC_FRAC_POLY = 7 };   /* g = p0 + p1 x + p2 x^2, T = 1 + c t, src_param = {p0,p1,p2,c} */
 
 /* initial data u0 */
 enum { OR_IC_EXACT = 0,        /* u0 = u_ex(x, 0) of the source's exact solution     */
@@ -74,6 +78,9 @@ typedef struct {
     int32_t quad;             /* OR_QUAD_CENTRE or OR_QUAD_BALL                 */
     double omega[3];          /* Aitken: first weight, lower and upper bound of
                                  the weight; a zero entry selects 1, 0.5, 2     */
+    double alpha;             /* order of the operator: 2 (or 0) the Laplacian;
+                                 (0,2) the fractional Laplacian (-Delta)^{alpha/2}
+                                 with the alpha-stable walk, d = 1 only         */
 } or_problem;
 
 /* acceleration of the fixed-point iteration (the remark after Algorithm 1):
@@ -130,6 +137,23 @@ int or_grid(const or_problem *pb, int interval, double *x_nodes, double *t_nodes
 
 /* initial nodal values of one instance, n^d entries */
 int or_ic_nodes(const or_problem *pb, int inst, double *u0);
+
+/* fractional operator (Ex. 2-3): Gauss-Jacobi (a,a) nodes and weights
+ * (weight (1-x^2)^a), the symmetric Jacobi polynomial P_p^{(a,a)}, the
+ * eigenvalue of (-Delta)^{alpha/2} on the generalized Jacobi function
+ * (1-x^2)_+^{alpha/2} P_p^{(alpha/2,alpha/2)}, the regularized incomplete beta
+ * function and its inverse, the jump of the alpha-stable walk */
+int or_gauss_jacobi(int n, double a, double *x, double *w);
+double or_jacobi_aa(int p, double a, double x);
+double or_frac_lambda(int p, double alpha);
+double or_ibeta(double x, double a, double b);
+double or_ibeta_inv(double y, double a, double b);
+double or_frac_jump(double alpha, double delta, double omega);
+/* nodal -> modal for the fractional basis (d = 1): Ut[p][q] with
+ * u = (1-x^2)^{alpha/2} sum Ut[p][q] P_p^{(a,a)}(x) L_q(xi) */
+int or_frac_reconstruct(double alpha, int n, int M, const double *U, double *Ut);
+/* u*, d_t u*, -(-Delta)^{alpha/2} u* at (x, xi) */
+int or_frac_eval(double alpha, int n, int M, double h, const double *Ut, double x, double xi, double out[3]);
 
 /* the ball point of walk step q of a path as an offset in the unit ball
  * (Y_q = X_q + J * offset), OR_QUAD_BALL's law */

@@ -17,7 +17,8 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "hpsmc_oracle.c")
 
 F_KINDS = {"affine": 0, "u_minus_u3": 1, "sin": 2, "u2_over_1pu2": 3, "neg_u3": 4, "u_sin_u": 5}
-SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4}
+SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4, "frac_longtime": 5,
+             "frac_singular": 6, "frac_poly": 7}
 IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
 SCHEDULES = {"sequential": 0, "sweeps": 1}
 
@@ -39,6 +40,7 @@ class _Problem(C.Structure):
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
         ("estimator", C.c_int32), ("accel", C.c_int32), ("quad", C.c_int32), ("omega", C.c_double * 3),
+        ("alpha", C.c_double),
     ]
 
 
@@ -78,6 +80,11 @@ def lib():
             "or_loss_grad": (C.c_int, [pp, C.c_int, p, p, p, p]),
             "or_exit_fraction": (d, [C.c_int, d, C.c_int, p, i64, C.c_uint64]),
             "or_num_threads": (C.c_int, []),
+            "or_gauss_jacobi": (C.c_int, [C.c_int, d, p, p]), "or_jacobi_aa": (d, [C.c_int, d, d]),
+            "or_frac_lambda": (d, [C.c_int, d]), "or_ibeta": (d, [d, d, d]), "or_ibeta_inv": (d, [d, d, d]),
+            "or_frac_jump": (d, [d, d, d]),
+            "or_frac_reconstruct": (C.c_int, [d, C.c_int, C.c_int, p, p]),
+            "or_frac_eval": (C.c_int, [d, C.c_int, C.c_int, d, p, d, d, p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -159,6 +166,27 @@ def evaluate(dim, n, M, h, Ut, X, xi):
     return out
 
 
+def gauss_jacobi(n, a):
+    x, w = np.zeros(n), np.zeros(n)
+    _check(lib().or_gauss_jacobi(n, float(a), _ptr(x), _ptr(w)), "gauss_jacobi")
+    return x, w
+
+
+def frac_reconstruct(alpha, n, M, U):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    Ut = np.zeros_like(U)
+    _check(lib().or_frac_reconstruct(float(alpha), n, M, _ptr(U), _ptr(Ut)), "frac_reconstruct")
+    return Ut
+
+
+def frac_evaluate(alpha, n, M, h, Ut, x, xi):
+    """u*, d_t u*, -(-Delta)^{alpha/2} u* at (x, xi)"""
+    Ut = np.ascontiguousarray(Ut, dtype=np.float64)
+    out = np.zeros(3)
+    _check(lib().or_frac_eval(float(alpha), n, M, float(h), _ptr(Ut), float(x), float(xi), _ptr(out)), "frac_eval")
+    return out
+
+
 def exit_fraction(dim, T, nstar, starts, seed=0):
     starts = np.ascontiguousarray(starts, dtype=np.float64)
     return lib().or_exit_fraction(dim, float(T), int(nstar), _ptr(starts), starts.shape[0], seed)
@@ -202,6 +230,7 @@ class Problem:
         s.estimator = ESTIMATORS[getattr(wl, "estimator", "residual")]
         s.accel = ACCELS[getattr(wl, "accel", "none")]
         s.quad = QUADS[getattr(wl, "quad", "centre")]
+        s.alpha = float(getattr(wl, "alpha", 2.0))
         for i, v in enumerate(getattr(wl, "omega", [0.0, 0.0, 0.0])):
             s.omega[i] = v
         self.s = s

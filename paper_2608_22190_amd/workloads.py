@@ -49,6 +49,7 @@ class Workload:
     estimator: str = "residual" # "residual" (eq. varepsilon_1) or "picard" (eq. uast, classical MC form)
     accel: str = "none"         # "none" or "aitken" (relaxed iteration, remark after Algorithm 1)
     quad: str = "centre"        # path quadrature: "centre" (eq. interIQ) or "ball" (Green's-function ball point)
+    alpha: float = 2.0          # order of the operator: 2 the Laplacian, (0, 2) the fractional Laplacian (d = 1)
     omega: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])  # Aitken w0, w_min, w_max (0: default)
 
     @property
@@ -79,15 +80,19 @@ class Workload:
 # Lobatto point; only the integer N* matters and both implementations receive
 # the same integers.
 # --------------------------------------------------------------------------
-def rho_estimate(dim: int, n: int, M: int, h: float) -> float:
-    return dim * 0.025 * (n + 2) ** 4 + (2.0 / h) * 0.1 * (M + 1) ** 2
+# With the fractional operator of order alpha < 2 (d = 1) the spatial part of
+# rho is 0.03 * 2^{2.7 (2 - alpha)} (n+2)^{2 alpha}, which bounds the measured
+# radii of the collocation operator for alpha in [0.4, 1.9], n <= 24.
+def rho_estimate(dim: int, n: int, M: int, h: float, alpha: float = 2.0) -> float:
+    space = dim * 0.025 * (n + 2) ** 4 if alpha >= 2.0 else 0.03 * 2 ** (2.7 * (2 - alpha)) * (n + 2) ** (2 * alpha)
+    return space + (2.0 / h) * 0.1 * (M + 1) ** 2
 
 
-def nstar_rule(dim, n, t_breaks, degree, c=0.25, nmin=4, nmax=(1 << 24) - 1):
+def nstar_rule(dim, n, t_breaks, degree, c=0.25, nmin=4, nmax=(1 << 24) - 1, alpha=2.0):
     out = []
     for iv, M in enumerate(degree):
         h = t_breaks[iv + 1] - t_breaks[iv]
-        dt_max = c / rho_estimate(dim, n, M, h)
+        dt_max = c / rho_estimate(dim, n, M, h, alpha)
         for ell in range(1, M + 1):
             frac = 0.5 * (1.0 - math.cos(math.pi * ell / M))
             out.append(int(min(nmax, max(nmin, math.ceil(frac * h / dt_max)))))
@@ -100,7 +105,7 @@ def fixed_nstar(degree, value):
 
 def _mk(name, dim, n, t_breaks, degree, c=0.25, nmin=4, **kw):
     return Workload(name=name, dim=dim, n=n, t_breaks=list(t_breaks), degree=list(degree),
-                    nstar=nstar_rule(dim, n, t_breaks, degree, c=c, nmin=nmin), **kw)
+                    nstar=nstar_rule(dim, n, t_breaks, degree, c=c, nmin=nmin, alpha=kw.get("alpha", 2.0)), **kw)
 
 
 # --------------------------------------------------------------------------
@@ -163,6 +168,27 @@ def c5_target(n_instances, nsp, seed=1, scale=0.1):
     """misfit target at the final time, one nodal vector per instance"""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((n_instances, nsp)) * scale
+
+
+def frac_long_time(M=8192, iters=6, n_intervals=20, h=0.5, n=11, deg=6, alpha=0.4, precision="fp64", **kw):
+    """1-D fractional Allen-Cahn u_t = -(-Delta)^{alpha/2} u + u - u^3 + s on
+    (-1,1), u = 0 outside, exact solution (1-x^2)_+^{alpha/2} sin x
+    e^{cos t}/(1+t^2) (Ex. 2: alpha = 0.4, M_n = 6, N_x = 10), unit-free
+    intervals of length h to T = n_intervals h."""
+    tb = [h * k for k in range(n_intervals + 1)]
+    return _mk("frac_long_time", 1, n, tb, [deg] * n_intervals, f="u_minus_u3", src="frac_longtime",
+               ic="exact", M=M, iters=iters, seed=0, precision=precision, alpha=alpha, **kw)
+
+
+def frac_singular(M=8192, iters=6, N=8, T=0.5, n=11, alpha=0.4, rho=0.51, precision="fp64", **kw):
+    """Ex. 3: exact solution (1-x^2)_+^{alpha/2} cos(x^3+1)/(10x^2+1) t^rho with a
+    weak singularity at t = 0, geometric mesh t_n = T 0.2^{N-n}, degrees
+    M_1 = 1, M_n = max(1, floor(1.5 n))."""
+    tb = [0.0] + [T * 0.2 ** (N - k) for k in range(1, N + 1)]
+    deg = [1] + [max(1, int(math.floor(1.5 * k))) for k in range(2, N + 1)]
+    return _mk("frac_singular", 1, n, tb, deg, f="u_minus_u3", src="frac_singular",
+               src_param=[rho, 0, 0, 0, 0, 0, 0, 0], ic="exact", M=M, iters=iters, seed=0, precision=precision,
+               alpha=alpha, **kw)
 
 
 CONFIGS = {
