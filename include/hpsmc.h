@@ -69,7 +69,13 @@ enum { HPSMC_SRC_NONE = 0,        /* s = 0 */
        HPSMC_SRC_SIN_DECAY = 1,   /* u_ex = e^{-t} prod sin(pi x_i)   */
        HPSMC_SRC_COS_DECAY = 2,   /* u_ex = e^{-t} prod cos(pi x_i/2) */
        HPSMC_SRC_LONGTIME = 3,    /* u_ex = prod(1-x_i^2) sin(sum x_i) e^{cos t}/(1+t^2) */
-       HPSMC_SRC_QUAD = 4 };      /* u_ex = prod(1-x_i^2)(c0 + c1 t + c2 t^2), src_param = {c0,c1,c2} */
+       HPSMC_SRC_QUAD = 4,        /* u_ex = prod(1-x_i^2)(c0 + c1 t + c2 t^2), src_param = {c0,c1,c2} */
+       /* fractional operator only (0 < alpha < 2, d = 1), u_ex = (1-x^2)_+^{alpha/2} g(x) T(t),
+          source s = u_t + (-Delta)^{alpha/2} u - f(u) (Ex. 2-3): */
+       HPSMC_SRC_FRAC_LONGTIME = 5, /* g = sin x, T = e^{cos t}/(1+t^2)                   */
+       HPSMC_SRC_FRAC_SINGULAR = 6, /* g = cos(x^3+1)/(10x^2+1), T = t^rho, rho = src_param[0] */
+       HPSMC_SRC_FRAC_POLY = 7 };   /* g = p0 + p1 x + p2 x^2, T = 1 + c t,
+                                       src_param = {p0, p1, p2, c}                         */
 
 /* initial data */
 enum { HPSMC_IC_EXACT = 0,        /* u_ex(x, t_0) of the source's exact solution */
@@ -151,6 +157,17 @@ typedef struct {
     double omega[3];           /* Aitken: first weight, lower and upper bound;
                                   0 selects 1, 0.5, 2; need 0 < omega[1] <=
                                   omega[0] <= omega[2] after the defaults       */
+    double alpha;              /* order of the operator: 0 or 2 the Laplacian;
+                                  0 < alpha < 2 the fractional Laplacian
+                                  (-Delta)^{alpha/2} with u = 0 outside Omega
+                                  (Ex. 2-3): d = 1, spatial nodes Gauss-Jacobi
+                                  (alpha/2, alpha/2), basis (1-x^2)^{alpha/2}
+                                  P_p^{(alpha/2,alpha/2)}, p < n, the alpha-stable
+                                  walk (jumps from the exit law of a ball whose
+                                  mean exit time is Delta).  Residual estimator,
+                                  centre-point rule, initial data IC_EXACT or
+                                  IC_NODAL; no gradient, no hpsmc_eval or
+                                  hpsmc_get_coeffs                              */
 } hpsmc_problem;
 
 typedef struct hpsmc_plan hpsmc_plan;

@@ -62,10 +62,20 @@ static int sturm_count(const std::vector<double> &e2, int n, double x)
     return cnt;
 }
 
+static void gauss_rule_e2(int n, double mu0, const std::vector<double> &e2, std::vector<double> &x,
+                          std::vector<double> &w);
+
 static void gauss_rule(int n, double mu0, double (*beta)(int), std::vector<double> &x, std::vector<double> &w)
 {
     std::vector<double> e2(n + 1, 0.0);
     for (int k = 1; k < n; ++k) e2[k] = beta(k);
+    gauss_rule_e2(n, mu0, e2, x, w);
+}
+
+// e2[k] = beta_k (k = 1..n-1) of the monic recurrence, mu0 = integral of the weight
+static void gauss_rule_e2(int n, double mu0, const std::vector<double> &e2, std::vector<double> &x,
+                          std::vector<double> &w)
+{
     x.assign(n, 0.0);
     w.assign(n, 0.0);
     for (int i = 0; i < n; ++i) {
@@ -91,6 +101,74 @@ static void gauss_rule(int n, double mu0, double (*beta)(int), std::vector<doubl
 }
 
 static double beta_legendre(int k) { return double(k) * k / (4.0 * k * k - 1.0); }
+
+// ---------------------------------------------------------------------------
+// Fractional operator (Ex. 2-3), d = 1: symmetric Jacobi polynomials of
+// parameter a = alpha/2 in the standard normalization,
+//   P_{k+1} = A_k x P_k - C_k P_{k-1},  A_k = (2k+2a+1)(2k+2a+2) / (2(k+1)(k+2a+1)),
+//   C_k = (k+a)^2 (2k+2a+2) / ((k+1)(k+2a+1)(2k+2a)),
+// their Gauss rule for the weight (1-x^2)^a (monic beta_k = k(k+2a) /
+// ((2k+2a+1)(2k+2a-1)), mu0 = 2^{2a+1} Gamma(a+1)^2 / Gamma(2a+2)) and norms
+//   gamma_k = 2^{2a+1} Gamma(k+a+1)^2 / ((2k+2a+1) k! Gamma(k+2a+1)).
+// ---------------------------------------------------------------------------
+static void jacobi_rec(int kmax, double a, std::vector<double> &A, std::vector<double> &C)
+{
+    A.assign(kmax, 0.0);
+    C.assign(kmax, 0.0);
+    const double s2 = 2.0 * a;
+    for (int k = 0; k < kmax; ++k) {
+        A[k] = (2.0 * k + s2 + 1.0) * (2.0 * k + s2 + 2.0) / (2.0 * (k + 1.0) * (k + s2 + 1.0));
+        C[k] = (k + a) * (k + a) * (2.0 * k + s2 + 2.0) / ((k + 1.0) * (k + s2 + 1.0) * (2.0 * k + s2));
+    }
+}
+
+static void jacobi_values(int kmax, const std::vector<double> &A, const std::vector<double> &C, double x, double *P)
+{
+    double pm = 0.0, pc = 1.0;
+    for (int k = 0; k < kmax; ++k) {
+        P[k] = pc;
+        const double pn = A[k] * x * pc - C[k] * pm;
+        pm = pc;
+        pc = pn;
+    }
+}
+
+static void gauss_jacobi_aa(int n, double a, std::vector<double> &x, std::vector<double> &w)
+{
+    std::vector<double> e2(n + 1, 0.0);
+    for (int k = 1; k < n; ++k) e2[k] = k * (k + 2.0 * a) / ((2.0 * k + 2.0 * a + 1.0) * (2.0 * k + 2.0 * a - 1.0));
+    const double mu0 = std::exp((2.0 * a + 1.0) * std::log(2.0) + 2.0 * std::lgamma(a + 1.0) - std::lgamma(2.0 * a + 2.0));
+    gauss_rule_e2(n, mu0, e2, x, w);
+}
+
+static double jacobi_norm2(int k, double a)
+{
+    return std::exp((2.0 * a + 1.0) * std::log(2.0) + 2.0 * std::lgamma(k + a + 1.0) - std::lgamma(k + 1.0) -
+                    std::lgamma(k + 2.0 * a + 1.0)) / (2.0 * k + 2.0 * a + 1.0);
+}
+
+static bool is_frac(const hpsmc_problem &pb) { return pb.alpha > 0.0 && pb.alpha < 2.0; }
+
+// the spatial factor g of the fractional manufactured solutions
+static double frac_g(const hpsmc_problem &pb, double x)
+{
+    switch (pb.src_kind) {
+    case HPSMC_SRC_FRAC_LONGTIME: return std::sin(x);
+    case HPSMC_SRC_FRAC_SINGULAR: return std::cos(x * x * x + 1.0) / (10.0 * x * x + 1.0);
+    case HPSMC_SRC_FRAC_POLY: return pb.src_param[0] + x * (pb.src_param[1] + x * pb.src_param[2]);
+    }
+    return 0.0;
+}
+
+static double frac_T(const hpsmc_problem &pb, double t)
+{
+    switch (pb.src_kind) {
+    case HPSMC_SRC_FRAC_LONGTIME: return std::exp(std::cos(t)) / (1.0 + t * t);
+    case HPSMC_SRC_FRAC_SINGULAR: return std::pow(t, pb.src_param[0]);
+    case HPSMC_SRC_FRAC_POLY: return 1.0 + pb.src_param[3] * t;
+    }
+    return 0.0;
+}
 static double beta_jacobi11(int k) { return double(k) * (k + 2) / ((2.0 * k + 1.0) * (2.0 * k + 3.0)); }
 
 static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) { gauss_rule(n, 2.0, beta_legendre, x, w); }
@@ -186,6 +264,8 @@ static double exact_solution(const hpsmc_problem &pb, const double *X, double t)
 {
     const int d = pb.dim;
     const double pi = 3.14159265358979323846;
+    if (pb.src_kind >= HPSMC_SRC_FRAC_LONGTIME)
+        return std::pow(1.0 - X[0] * X[0], 0.5 * pb.alpha) * frac_g(pb, X[0]) * frac_T(pb, t);
     switch (pb.src_kind) {
     case HPSMC_SRC_SIN_DECAY: { double p = std::exp(-t); for (int i = 0; i < d; ++i) p *= std::sin(pi * X[i]); return p; }
     case HPSMC_SRC_COS_DECAY: { double p = std::exp(-t); for (int i = 0; i < d; ++i) p *= std::cos(0.5 * pi * X[i]); return p; }
@@ -282,6 +362,11 @@ struct hpsmc_plan {
     // hipGraph of a whole solve (captured on the first graph solve, replayed after)
     int32_t use_graph = 0;
     int32_t sample_mma = 1;     // 2-D FP32 round kernel on the matrix cores where eligible
+    // fractional operator (d = 1): tables of the round kernel (see Physics)
+    bool frac = false;
+    double *frac_tab = nullptr;
+    int32_t frac_kmax = 0, frac_K = 0, frac_nt = 0;
+    double frac_half = 0.0, frac_lpb1 = 0.0, frac_lpb2 = 0.0;
     bool capturing = false;
     hipStream_t own_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -391,7 +476,20 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     if (pb->M < 1 || pb->M > (int64_t)0xFFFFFFFFll) return fail(HPSMC_EINVAL, "M must be 1..2^32-1");
     if (pb->iters < 1 || pb->iters > 255) return fail(HPSMC_EINVAL, "iters must be 1..255");
     if (pb->f_kind < 0 || pb->f_kind > 5) return fail(HPSMC_EINVAL, "unknown f_kind");
-    if (pb->src_kind < 0 || pb->src_kind > 4) return fail(HPSMC_EINVAL, "unknown src_kind");
+    if (pb->src_kind < 0 || pb->src_kind > 7) return fail(HPSMC_EINVAL, "unknown src_kind");
+    if (!std::isfinite(pb->alpha) || pb->alpha < 0.0 || pb->alpha > 2.0)
+        return fail(HPSMC_EINVAL, "alpha must be 0 (the Laplacian) or in (0, 2]");
+    if (is_frac(*pb)) {
+        if (pb->dim != 1) return fail(HPSMC_ENOTSUP, "the fractional operator is built for d = 1");
+        if (pb->src_kind != HPSMC_SRC_NONE && pb->src_kind < HPSMC_SRC_FRAC_LONGTIME)
+            return fail(HPSMC_EINVAL, "the Laplacian's manufactured sources do not solve the fractional problem");
+        if (pb->estimator != HPSMC_EST_RESIDUAL || pb->quad != HPSMC_QUAD_CENTRE)
+            return fail(HPSMC_ENOTSUP, "the fractional form takes the residual estimator and the centre-point rule");
+        if (pb->ic_kind != HPSMC_IC_EXACT && pb->ic_kind != HPSMC_IC_NODAL)
+            return fail(HPSMC_ENOTSUP, "the fractional form takes IC_EXACT or IC_NODAL");
+    } else if (pb->src_kind >= HPSMC_SRC_FRAC_LONGTIME) {
+        return fail(HPSMC_EINVAL, "fractional sources need 0 < alpha < 2");
+    }
     if (pb->ic_kind < 0 || pb->ic_kind > 3) return fail(HPSMC_EINVAL, "unknown ic_kind");
     if (pb->schedule < 0 || pb->schedule > 1) return fail(HPSMC_EINVAL, "unknown schedule");
     if (pb->precision < 0 || pb->precision > 1) return fail(HPSMC_EINVAL, "unknown precision");
@@ -452,6 +550,15 @@ static double expected_cost(const NodeDesc &nd, int d)
     return steps;
 }
 
+// sphere radius of a walk step: sqrt(2 d Delta) (Lemma 2.1), or for the
+// alpha-stable walk the ball radius whose mean exit time from the centre is
+// Delta, (Delta Gamma(1+alpha))^{1/alpha} in 1-D
+static double walk_radius(const hpsmc_plan *plan, double delta)
+{
+    if (plan->frac) return std::pow(delta * std::exp(std::lgamma(1.0 + plan->pb.alpha)), 1.0 / plan->pb.alpha);
+    return std::sqrt(2.0 * plan->d * delta);
+}
+
 static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<int32_t> &ivs)
 {
     const int d = plan->d;
@@ -494,7 +601,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
                     int64_t r = j;
                     for (int i = d - 1; i >= 0; --i) { nd.x0[i] = plan->x[r % plan->n]; r /= plan->n; }
                     nd.delta = dl;
-                    nd.jump = std::sqrt(2.0 * d * dl);
+                    nd.jump = walk_radius(plan, dl);
                     nd.span = sp;
                     nd.t_prev = plan->t_breaks[iv];
                     nd.u_index = plan->u_off[iv] + ((int64_t)inst * plan->nsp + j) * (M + 1) + l;
@@ -525,7 +632,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
         for (size_t g = 0; g < coef_off.size(); ++g) {
             GroupDesc gd{};
             gd.delta = delta[g];
-            gd.jump = std::sqrt(2.0 * d * delta[g]);
+            gd.jump = walk_radius(plan, delta[g]);
             gd.span = span[g];
             gd.node_begin = (int32_t)(g * per);
             gd.node_count = (int32_t)per;
@@ -624,6 +731,71 @@ static void free_set(const hpsmc_plan *plan, NodeSet &s)
 }
 
 // initial nodal values [inst][nsp], computed on the host in FP64
+// nodal -> Jacobi coefficients of u/w (fractional basis): c_p = sum_j A[p][j] U_j,
+// A[p][j] = P_p(x_j) w_j / ((1 - x_j^2)^a gamma_p), exact by the Gauss rule
+static std::vector<double> frac_nodal_to_modal(const std::vector<double> &x, const std::vector<double> &w, double a)
+{
+    const int n = (int)x.size();
+    std::vector<double> A, C, Pv(n), M((size_t)n * n);
+    jacobi_rec(n, a, A, C);
+    for (int j = 0; j < n; ++j) {
+        jacobi_values(n, A, C, x[j], Pv.data());
+        const double wt = std::pow(1.0 - x[j] * x[j], a);
+        for (int p = 0; p < n; ++p) M[(size_t)p * n + j] = Pv[p] * w[j] / (wt * jacobi_norm2(p, a));
+    }
+    return M;
+}
+
+// tables of the fractional round kernel: recurrence, eigenvalues, the source
+// series sum_k a_k lambda_k P_k = (-Delta)^{alpha/2}(w g) (a_k the Jacobi
+// coefficients of g by a 160-point Gauss rule), the series ratios of the
+// inverse incomplete beta; and its branch point and constants
+static hpsmc_status frac_tables(hpsmc_plan *plan)
+{
+    const double alpha = plan->pb.alpha, a = 0.5 * alpha, b = 1.0 - a;
+    const int P = plan->P;
+    int K = 0;
+    switch (plan->pb.src_kind) {
+    case HPSMC_SRC_FRAC_LONGTIME: K = 40; break;
+    case HPSMC_SRC_FRAC_SINGULAR: K = 150; break;
+    case HPSMC_SRC_FRAC_POLY: K = 3; break;
+    }
+    const int kmax = std::max(P, K), nt = plan->fp32 ? 26 : 60;
+    std::vector<double> A, C;
+    jacobi_rec(kmax, a, A, C);
+    std::vector<double> tab(A);
+    tab.insert(tab.end(), C.begin(), C.end());
+    for (int k = 0; k < P; ++k) tab.push_back(std::exp(std::lgamma(k + alpha + 1.0) - std::lgamma(k + 1.0)));
+    if (K > 0) {
+        std::vector<double> xq, wq, Pv(K);
+        gauss_jacobi_aa(160, a, xq, wq);
+        std::vector<double> ck(K, 0.0);
+        for (size_t j = 0; j < xq.size(); ++j) {
+            jacobi_values(K, A, C, xq[j], Pv.data());
+            const double g = frac_g(plan->pb, xq[j]);
+            for (int k = 0; k < K; ++k) ck[k] += wq[j] * g * Pv[k];
+        }
+        for (int k = 0; k < K; ++k)
+            tab.push_back(ck[k] / jacobi_norm2(k, a) * std::exp(std::lgamma(k + alpha + 1.0) - std::lgamma(k + 1.0)));
+    }
+    for (int k = 0; k < nt; ++k) tab.push_back((k + 1.0) / (a + 1.0 + k));
+    for (int k = 0; k < nt; ++k) tab.push_back((k + 1.0) / (b + 1.0 + k));
+    plan->frac_kmax = kmax;
+    plan->frac_K = K;
+    plan->frac_nt = nt;
+    plan->frac_lpb1 = std::log(a) + std::lgamma(a) + std::lgamma(b);
+    plan->frac_lpb2 = std::log(b) + std::lgamma(a) + std::lgamma(b);
+    // I_{1/2}(a, b) by its series (x = 1/2): x^a (1-x)^b / (a B) sum_k t_k
+    double S = 1.0, t = 1.0;
+    for (int k = 0; k < 200; ++k) { t *= 0.5 * (k + 1.0) / (a + 1.0 + k); S += t; }
+    plan->frac_half = std::exp(-std::log(2.0) - plan->frac_lpb1) * S;
+    hpsmc_status st;
+    if ((st = dalloc(plan, (void **)&plan->frac_tab, tab.size() * 8))) return st;
+    if (hipMemcpy(plan->frac_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(HPSMC_EDEVICE, "fractional table upload failed");
+    return HPSMC_OK;
+}
+
 static void initial_nodes(const hpsmc_plan *plan, std::vector<double> &u0)
 {
     const int d = plan->d, n = plan->n;
@@ -697,6 +869,16 @@ static Physics physics_of(const hpsmc_plan *plan)
     ph.src_kind = plan->pb.src_kind;
     ph.picard = plan->pb.estimator == HPSMC_EST_PICARD;
     ph.ball = plan->pb.quad == HPSMC_QUAD_BALL;
+    ph.frac = plan->frac ? 1 : 0;
+    ph.frac_kmax = plan->frac_kmax;
+    ph.frac_K = plan->frac_K;
+    ph.frac_nt = plan->frac_nt;
+    ph.frac_P = plan->P;
+    ph.frac_a = 0.5 * plan->pb.alpha;
+    ph.frac_half = plan->frac_half;
+    ph.frac_lpb1 = plan->frac_lpb1;
+    ph.frac_lpb2 = plan->frac_lpb2;
+    ph.frac_tab = plan->frac_tab;
     memcpy(ph.f_param, plan->pb.f_param, sizeof(ph.f_param));
     memcpy(ph.src_param, plan->pb.src_param, sizeof(ph.src_param));
     return ph;
@@ -745,7 +927,7 @@ static hpsmc_status aitken_reset(hpsmc_plan *plan, int iv, hipStream_t s)
 
 static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
 {
-    const int ns = plan->launch.samples_per_lane, waves = plan->launch.waves_per_block;
+    const int ns = plan->frac ? 1 : plan->launch.samples_per_lane, waves = plan->launch.waves_per_block;
     const int nthr = 64 * waves;
     int cf, n_chunks;
     int64_t chunk_elems;
@@ -903,7 +1085,8 @@ void hpsmc_destroy(hpsmc_plan *plan)
         for (auto &e : *pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     void *ptrs[] = {plan->U, plan->cu, plan->cv, plan->tmp0, plan->tmp1, plan->ic, plan->mats,
                     plan->slab_table, plan->part, plan->counters, plan->maxbits, plan->hist_u, plan->hist_v,
-                    plan->lam, plan->cbar_u, plan->cbar_v, plan->dtarget, plan->dloss, plan->dgrad, plan->slab_bar};
+                    plan->lam, plan->cbar_u, plan->cbar_v, plan->dtarget, plan->dloss, plan->dgrad, plan->slab_bar,
+                    plan->frac_tab};
     for (void *p : ptrs) dfree(plan, p);
     delete plan;
 }
@@ -924,7 +1107,8 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
     plan->pb = *pb;
     plan->d = pb->dim;
     plan->n = pb->n;
-    plan->P = pb->n + 2;
+    plan->frac = is_frac(*pb);
+    plan->P = plan->frac ? pb->n : pb->n + 2;   // Jacobi modes p < n, or Legendre modes of phi_p, p < n
     plan->PP = (plan->P + 3) / 4 * 4;
     plan->n_iv = pb->n_intervals;
     plan->n_inst = pb->n_instances;
@@ -945,7 +1129,8 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
 
     // grid
     std::vector<double> wx;
-    jacobi_gauss11(plan->n, plan->x, wx);
+    if (plan->frac) gauss_jacobi_aa(plan->n, 0.5 * pb->alpha, plan->x, wx);
+    else jacobi_gauss11(plan->n, plan->x, wx);
     plan->xi.resize(plan->n_iv);
     plan->tnodes.resize(plan->n_iv);
     for (int iv = 0; iv < plan->n_iv; ++iv) {
@@ -984,11 +1169,12 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
     if ((st = dalloc(pl, (void **)&pl->ic, I * plan->nsp * 8))) return st;
     if ((st = dalloc(pl, (void **)&pl->counters, 4 * 8))) return st;
     if ((st = dalloc(pl, (void **)&pl->maxbits, 4096 * 8))) return st;
+    if (pl->frac && (st = frac_tables(pl))) return st;
 
     // transform matrices
     std::vector<double> mats;
-    auto G0 = spatial_to_legendre(plan->x, plan->P);
-    auto D2 = legendre_d2(plan->P);
+    auto G0 = plan->frac ? frac_nodal_to_modal(plan->x, wx, 0.5 * pb->alpha) : spatial_to_legendre(plan->x, plan->P);
+    auto D2 = plan->frac ? std::vector<double>((size_t)plan->P * plan->P, 0.0) : legendre_d2(plan->P);
     mats.insert(mats.end(), G0.begin(), G0.end());
     mats.insert(mats.end(), D2.begin(), D2.end());
     auto transpose = [](const std::vector<double> &A, int rows, int cols) {
@@ -1321,6 +1507,7 @@ hpsmc_status hpsmc_eval(hpsmc_plan *plan, int32_t iv, int32_t inst, const double
                         void *stream)
 {
     CHECK_PLAN(plan);
+    if (plan->frac) return fail(HPSMC_ENOTSUP, "hpsmc_eval covers the Laplacian's basis");
     if (iv < 0 || iv >= plan->n_iv || inst < 0 || inst >= plan->n_inst || npts < 0 || (npts && (!pts || !out)))
         return fail(HPSMC_EINVAL, "bad eval arguments");
     if (npts == 0) return HPSMC_OK;
@@ -1557,6 +1744,7 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     const int nsv[3] = {1, 2, 4};
     for (int a = 0; a < 3; ++a) {
         if (nsv[a] == 4 && plan->d > 2) continue;
+        if (nsv[a] != 1 && plan->frac) continue;   // the fractional kernel runs one path per lane
         for (int w : {2, 4}) {
             // two-wave blocks of the matrix-core kernel: 1, 1.5, 2, 3, 4 waves per SIMD
             if (w == 2 && nsv[a] == 1 && plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 2)) {
@@ -1695,6 +1883,7 @@ hpsmc_status hpsmc_set_initial_nodes(hpsmc_plan *plan, const double *u0, int32_t
 hpsmc_status hpsmc_get_coeffs(hpsmc_plan *plan, int32_t iv, double *out, int32_t on_device, void *stream)
 {
     CHECK_PLAN(plan);
+    if (plan->frac) return fail(HPSMC_ENOTSUP, "hpsmc_get_coeffs covers the Laplacian's basis");
     if (iv < 0 || iv >= plan->n_iv || !out) return fail(HPSMC_EINVAL, "bad interval or output");
     hipStream_t s = (hipStream_t)stream;
     const int d = plan->d, n = plan->n, T1 = plan->degree[iv] + 1;
@@ -1842,6 +2031,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
     if (plan->pb.estimator != HPSMC_EST_RESIDUAL) return fail(HPSMC_ENOTSUP, "the adjoint is that of the residual form");
     if (plan->pb.accel != HPSMC_ACCEL_NONE) return fail(HPSMC_ENOTSUP, "the adjoint is that of the unrelaxed iteration");
     if (plan->pb.quad != HPSMC_QUAD_CENTRE) return fail(HPSMC_ENOTSUP, "the adjoint is that of the centre-point rule");
+    if (plan->frac) return fail(HPSMC_ENOTSUP, "no adjoint for the fractional operator");
     hipStream_t s = (hipStream_t)stream;
     const int d = plan->d, n = plan->n, P = plan->P, K = plan->pb.iters, T1 = plan->degree[0] + 1;
     const int64_t I = plan->n_inst, nsp = plan->nsp, psp = plan->psp;

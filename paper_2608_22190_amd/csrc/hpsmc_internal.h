@@ -45,7 +45,13 @@ struct Physics {
     int32_t dim, f_kind, src_kind;
     int32_t picard;              // 1: Picard-form estimator (eq. uast)
     int32_t ball;                // 1: integrand at the step's Green's-function ball point
-    int32_t reserved;
+    int32_t frac;                // 1: fractional operator (d = 1, alpha-stable walk)
+    int32_t frac_kmax, frac_K, frac_nt;  // recurrence length, source series terms, series terms of the inverse
+    int32_t frac_P;              // Jacobi modes of the slab
+    double frac_a;               // alpha / 2
+    double frac_half;            // I_{1/2}(a, 1 - a): the branch of the inverse
+    double frac_lpb1, frac_lpb2; // log(a B(a, 1-a)), log((1-a) B(1-a, a))
+    const double *frac_tab;      // A[kmax], C[kmax], lambda[P], src[K], ra[nt], rb[nt]
     double f_param[4];
     double src_param[8];
 };

@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhpsmc.so")
 
 F_KINDS = {"affine": 0, "u_minus_u3": 1, "sin": 2, "u2_over_1pu2": 3, "neg_u3": 4, "u_sin_u": 5}
-SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4}
+SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4, "frac_longtime": 5,
+             "frac_singular": 6, "frac_poly": 7}
 IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
 SCHEDULES = {"sequential": 0, "sweeps": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
@@ -46,7 +47,7 @@ class hpsmc_problem(C.Structure):
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
         ("precision", C.c_int32), ("estimator", C.c_int32), ("tol", C.c_double),
-        ("accel", C.c_int32), ("quad", C.c_int32), ("omega", C.c_double * 3),
+        ("accel", C.c_int32), ("quad", C.c_int32), ("omega", C.c_double * 3), ("alpha", C.c_double),
     ]
 
 
@@ -162,6 +163,7 @@ def make_problem(wl):
     p.estimator = ESTIMATORS[getattr(wl, "estimator", "residual")]
     p.accel = ACCELS[getattr(wl, "accel", "none")]
     p.quad = QUADS[getattr(wl, "quad", "centre")]
+    p.alpha = float(getattr(wl, "alpha", 2.0))
     for i, v in enumerate(getattr(wl, "omega", [0.0, 0.0, 0.0])):
         p.omega[i] = v
     return p, [tb, deg, ns, ic]

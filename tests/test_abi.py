@@ -65,6 +65,19 @@ def test_invalid_aitken_weights_are_rejected(omega):
     assert ei.value.status == -1
 
 
+@pytest.mark.parametrize("change,status", [
+    (dict(src="frac_longtime", alpha=2.0), -1), (dict(src="sin_decay", alpha=0.5), -1),
+    (dict(src="frac_longtime", alpha=0.5, dim=2, n=3), -2), (dict(src="frac_longtime", alpha=0.5, estimator="picard"), -2),
+    (dict(src="frac_longtime", alpha=0.5, quad="ball"), -2), (dict(src="frac_longtime", alpha=-1.0), -1),
+    (dict(src="frac_longtime", alpha=2.5), -1), (dict(src="frac_longtime", alpha=float("nan")), -1),
+    (dict(src="frac_longtime", alpha=0.5, ic="phi", ic_data=__import__("numpy").zeros((1, 4))), -2)])
+def test_invalid_fractional_problems_are_rejected(change, status):
+    wl = W.small(dim=1, n=4, M_deg=4, f="u_minus_u3").with_(**change)
+    with pytest.raises(H.HpsmcError) as ei:
+        H.Plan(wl)
+    assert ei.value.status == status
+
+
 def test_allocator_hooks_must_come_in_pairs():
     lib = H.lib()
     a = H.ALLOC_FN(lambda n, s, c: None)
