@@ -134,6 +134,8 @@ def run_other(name, args, torch):
         return run_aitken(args, torch)
     if name == "ballcmp":
         return run_ballcmp(args, torch)
+    if name == "frac":
+        return run_frac(args, torch)
     if name == "c1":
         wl = W.c1_single_step()
     elif name == "c2p":
@@ -253,6 +255,79 @@ def run_compare(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def flops_per_eval_frac(P, K, fp32):
+    """Algorithmic FP operations of one step of the fractional walk: the Newton
+    inverse of the incomplete beta (4 or 6 iterations of a 26- or 60-term series
+    at 3 flops a term, plus ~30 for the logarithms and the update), the Jacobi
+    recurrence with three contractions over P modes (9 flops a mode) and the
+    source series over K modes (4 flops a mode), ~40 for w, f and the source."""
+    nit, nt = (4, 26) if fp32 else (6, 60)
+    return nit * (3 * nt + 30) + 9 * P + 4 * K + 40
+
+
+def run_frac(args, torch):
+    """Ex. 2's fractional long-time problem: alpha = 0.4, 11 Gauss-Jacobi nodes
+    x 6 node times per interval, h = 0.5 to T = 10, M = 8192, 10 iterations per
+    interval, whole solve (both precisions on the same Philox words), error
+    against the exact solution (1-x^2)^{0.2} sin x e^{cos t}/(1+t^2)."""
+    from paper_2608_22190_amd import hpsmc, workloads as W
+    res = {}
+    stream = torch.cuda.Stream()
+    for prec in ("fp64", "fp32"):
+        wl = W.frac_long_time(iters=10, precision=prec)
+        with hpsmc.Plan(wl) as plan:
+            if args.tune_cache:   # tuned on the full sample count: one interval-iteration is small
+                plan.hpsmc_tune(0, wl.M, args.tune_cache, stream=stream)
+            plan.hpsmc_set_option("graph", 1)
+            plan.hpsmc_solve(stream=stream)       # warm-up solve (code loading, graph capture)
+            stream.synchronize()
+            plan.hpsmc_reset_stats(stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.hpsmc_solve(stream=stream)
+            stream.synchronize()
+            sec = time.perf_counter() - t0
+            st = plan.hpsmc_stats(stream=stream)
+            errs = []
+            for iv in range(wl.n_intervals):
+                x, t = plan.hpsmc_grid(iv)
+                ex = ((1 - x ** 2) ** (wl.alpha / 2) * np.sin(x))[:, None] * (np.exp(np.cos(t)) / (1 + t ** 2))[None, :]
+                errs.append(float(np.max(np.abs(plan.hpsmc_get_nodes(iv)[0] - ex))))
+            launch = plan.hpsmc_get_launch()
+            # the round kernel's own launch time, from eager iterations of the
+            # first interval (a graph replay records no per-launch events)
+            plan.hpsmc_set_option("graph", 0)
+            plan.hpsmc_start_interval(0, stream=stream)
+            plan.hpsmc_reset_stats(stream=stream)
+            for k in range(4):
+                plan.hpsmc_iterate(0, k, stream=stream)
+            stream.synchronize()
+            sk = plan.hpsmc_stats(stream=stream)
+        ns = wl.nodes_per_sweep * wl.M * wl.iters
+        k_ms = sk["sample_ms"] / max(1, sk["sample_launches"])
+        fpe = flops_per_eval_frac(wl.n, 40, prec == "fp32")
+        res[prec] = {"seconds": sec, "node_samples_per_s": ns / sec, "max_error": max(errs),
+                     "error_per_interval": errs, "path_steps": st["path_steps"],
+                     "mean_path_length": st["path_steps"] / max(1, st["node_samples"]),
+                     "avg_launch_ms": k_ms,
+                     "achieved_tflops": fpe * sk["path_steps"] / max(1, sk["sample_launches"]) / max(1e-9, k_ms * 1e-3) / 1e12,
+                     "lane_utilization": st["path_steps"] / max(1, st["lane_steps"]), "launch": list(launch)}
+        print(f"[bench] frac {prec}: {sec:.2f}s {ns / sec / 1e6:.2f} M node-samples/s, max error {max(errs):.3e}",
+              file=sys.stderr, flush=True)
+    r32, r64 = res["fp32"], res["fp64"]
+    line = {"metric": METRIC, "value": r32["node_samples_per_s"], "unit": "node-samples/s", "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": 1e3 * r32["seconds"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "fractional long-time problem (Ex. 2 shape): alpha = 0.4, 1-D, 11 Gauss-Jacobi "
+                                   "nodes x 6 node times per interval, h = 0.5 to T = 10, M = 8192, 10 iterations "
+                                   "per interval, whole solve"},
+            "roofline": {"bound": "alu", "achieved": r32["achieved_tflops"], "peak": FP32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": r32["achieved_tflops"] / FP32_PEAK_TFLOPS,
+                         "flops_per_eval": flops_per_eval_frac(11, 40, True)},
+            "speedup_fp32_vs_fp64": r64["seconds"] / r32["seconds"], "results": res}
+    print(json.dumps(line), flush=True)
+
+
 def run_ballcmp(args, torch):
     """Centre-point (eq. interIQ) against ball-point path quadrature on the
     single-step problem (1-D, u = e^{-t} sin(pi x), 16 x 16 nodes, M = 4096,
@@ -365,7 +440,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c2b", "c3", "c4", "c5", "compare", "aitken",
-                                                              "ballcmp"])
+                                                              "ballcmp", "frac"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--launch", type=str, default="",

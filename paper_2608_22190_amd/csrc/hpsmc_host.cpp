@@ -935,7 +935,10 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
         return fail(HPSMC_EINVAL, "slab chunk too large for this block size; use more waves per block");
     const int64_t nvec = chunk_elems * (plan->fp32 ? 4 : 8) / 16;
     const int mma = set_uses_mma(plan, set);
-    const size_t lds = mma ? advance_mma_lds_bytes(plan->PP) : (size_t)2 * ((nvec + 1) & ~1LL) * 16;
+    const size_t lds = mma ? advance_mma_lds_bytes(plan->PP)
+                     : plan->frac ? frac_lds_bytes(plan->fp32, plan->PP, plan->frac_kmax, plan->P, plan->frac_K,
+                                                   plan->frac_nt)
+                                  : (size_t)2 * ((nvec + 1) & ~1LL) * 16;
     const int C = plan->round_steps;
     const int R = (set.max_nstar + C - 1) / C;
     const int G = (int)set.ghost.size();

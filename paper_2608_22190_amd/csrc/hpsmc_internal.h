@@ -152,6 +152,7 @@ hipError_t launch_aitken(const NodeDesc *nodes, const int64_t *vbeg, int n_vec, 
 hipError_t launch_start_columns(double *U, const double *src, int64_t src_stride, int64_t src_off,
                                 int64_t dst_stride, int T1, int64_t count, int replicate, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
+size_t frac_lds_bytes(int fp32, int PP, int kmax, int P, int K, int nt);
 hipError_t launch_eval(const double *cu, const double *cv, int dim, int P, int T1, double t_prev, double h,
                        const double *pts, int64_t npts, double *out, hipStream_t s);
 hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t round, int32_t steps,

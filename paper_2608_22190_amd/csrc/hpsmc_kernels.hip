@@ -1818,11 +1818,14 @@ size_t advance_mma_lds_bytes(int PP) { return (size_t)2 * 2 * PP * kMmaRS * size
 
 // log x solving I_x(p, 1-p) = y for x <= 1/2: Newton on log x with the series
 // I_x = x^p (1-x)^{1-p} / (p B) sum_k t_k, t_{k+1} = t_k x (k+1)/(p+1+k)
-// (ratios rt[k] from the table), started from the small-x asymptote.
+// (ratios rt[k] from the block's LDS copy of the table), started from the
+// small-x asymptote.  FP64: 6 iterations of 60 terms; FP32: 4 of 26.
+template <typename T> struct FracIters { static constexpr int nit = sizeof(T) == 8 ? 6 : 4, nt = sizeof(T) == 8 ? 60 : 26; };
+
 template <typename T>
-__device__ __forceinline__ T ibeta_inv_log(T y, T p, T lpb, cptr<double> rt, int nt)
+__device__ __forceinline__ T ibeta_inv_log(T y, T p, T lpb, const T *rt)
 {
-    constexpr int NIT = sizeof(T) == 8 ? 6 : 4;
+    constexpr int NIT = FracIters<T>::nit, NT = FracIters<T>::nt;
     const T lhalf = (T)-0.69314718055994530942;
     const T ly = m_log(y);
     T z = (ly + lpb) / p;
@@ -1830,8 +1833,9 @@ __device__ __forceinline__ T ibeta_inv_log(T y, T p, T lpb, cptr<double> rt, int
     for (int it = 0; it < NIT; ++it) {
         const T x = m_exp(z);
         T S = (T)1, t = (T)1;
-        for (int k = 0; k < nt; ++k) {
-            t *= x * (T)rt[k];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            t *= x * rt[k];
             S += t;
         }
         const T l1 = sizeof(T) == 8 ? (T)log1p((double)-x) : (T)log1pf((float)-x);
@@ -1842,16 +1846,17 @@ __device__ __forceinline__ T ibeta_inv_log(T y, T p, T lpb, cptr<double> rt, int
     return z;
 }
 
+// one Newton solve per lane whichever half of (0,1) omega falls in (no
+// divergent second solve): x <= 1/2 solves I_x(a, 1-a) = omega for log x;
+// otherwise z = 1 - x solves I_z(1-a, a) = 1 - omega for log z
 template <typename T>
-__device__ __forceinline__ T frac_jump(const Physics &ph, T R, T om, cptr<double> ra, cptr<double> rb)
+__device__ __forceinline__ T frac_jump(const Physics &ph, T R, T om, const T *ra, const T *rb)
 {
     const T a = (T)ph.frac_a;
-    if (om <= (T)ph.frac_half) {
-        const T z = ibeta_inv_log<T>(om, a, (T)ph.frac_lpb1, ra, ph.frac_nt);   // log x
-        return R * m_exp((T)-0.5 * z);
-    }
-    const T z = ibeta_inv_log<T>((T)1 - om, (T)1 - a, (T)ph.frac_lpb2, rb, ph.frac_nt);   // log(1 - x)
-    return R / m_sqrt((T)1 - m_exp(z));
+    const bool lower = om <= (T)ph.frac_half;
+    const T z = ibeta_inv_log<T>(lower ? om : (T)1 - om, lower ? a : (T)1 - a,
+                                 lower ? (T)ph.frac_lpb1 : (T)ph.frac_lpb2, lower ? ra : rb);
+    return lower ? R * m_exp((T)-0.5 * z) : R / m_sqrt((T)1 - m_exp(z));
 }
 
 template <typename T>
@@ -1862,10 +1867,13 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
     __shared__ long long s_item;
     const Physics &ph = a.phys;
     const int P = a.P, PP = a.PP, K = ph.frac_K, kmax = ph.frac_kmax;
-    cptr<double> tab = as_const(ph.frac_tab);
-    cptr<double> tA = tab, tC = tab + kmax, tlam = tab + 2 * kmax, tsrc = tlam + P, ra = tsrc + K, rb = ra + ph.frac_nt;
     const int nv = 2 * PP * (int)sizeof(T) / 16;   // 16-byte vectors per slab
     const int cv = (nv + 1) & ~1;
+    // the tables, in the sampling precision, after the two slab buffers
+    T *tl = (T *)(lds + 2 * cv);
+    const int ntab = 2 * kmax + P + K + 2 * ph.frac_nt;
+    for (int i = tid; i < ntab; i += blockDim.x) tl[i] = (T)ph.frac_tab[i];
+    const T *tA = tl, *tC = tl + kmax, *tlam = tl + 2 * kmax, *tsrc = tlam + P, *ra = tsrc + K, *rb = ra + ph.frac_nt;
     cptr<GroupDesc> groups = as_const(a.groups);
     cptr<NodeDesc> nodes = as_const(a.nodes);
     const int64_t total = a.batch_prefix[a.n_groups];
@@ -1944,6 +1952,7 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
                     const T *S = (const T *)(lds + buf * cv);
                     const T wgt = m_exp(fa * m_log(((T)1 - X) * ((T)1 + X)));
                     T pm = (T)0, pc = (T)1, uj = (T)0, vj = (T)0, F = (T)0, Gs = (T)0;
+#pragma unroll 4
                     for (int k = 0; k < kmax; ++k) {
                         if (k < P) {
                             uj = m_fma(S[k], pc, uj);
@@ -2025,12 +2034,21 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
     }
 }
 
+// dynamic LDS of the fractional round kernel: two slab buffers and the tables
+size_t frac_lds_bytes(int fp32, int PP, int kmax, int P, int K, int nt)
+{
+    const int nv = 2 * PP * (fp32 ? 4 : 8) / 16, cv = (nv + 1) & ~1;
+    return (size_t)2 * cv * 16 + (size_t)(2 * kmax + P + K + 2 * nt) * (fp32 ? 4 : 8);
+}
+
 hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
                           size_t lds_bytes, int mma, hipStream_t s)
 {
     dim3 block(64 * waves_per_block), grid(blocks);
     if (a.phys.frac) {
-        if (a.phys.dim != 1 || a.batch != (int)block.x || a.P > a.PP || 2 * a.PP * (fp32 ? 4 : 8) / 16 > (int)block.x)
+        const int nt = fp32 ? FracIters<float>::nt : FracIters<double>::nt;
+        if (a.phys.dim != 1 || a.batch != (int)block.x || a.P > a.PP || 2 * a.PP * (fp32 ? 4 : 8) / 16 > (int)block.x ||
+            a.phys.frac_nt != nt || lds_bytes < frac_lds_bytes(fp32, a.PP, a.phys.frac_kmax, a.P, a.phys.frac_K, nt))
             return hipErrorInvalidValue;
         if (fp32)
             hipLaunchKernelGGL(frac_advance_kernel<float>, grid, block, lds_bytes, s, a);
