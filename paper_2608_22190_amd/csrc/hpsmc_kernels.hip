@@ -324,12 +324,11 @@ __device__ __forceinline__ T source_of(const Physics &ph, const T (&X)[D], T t)
 // The last dimension's L values sit in registers (Ll); the outer dimensions
 // run as loops whose L values advance by the recurrence on the fly.  Slab rows
 // are wave-uniform: [u: PP][v: PP] per multi-index of the first d-1 dims.
-// uo (wave-uniform) skips the v half: the Picard-form integrand needs u only.
+// UO skips the v half: the Picard-form integrand needs u only.
 // ---------------------------------------------------------------------------
-template <typename T, int D, int PMAX, int NS, int LV, typename SP>
+template <typename T, int D, int PMAX, int NS, int LV, typename SP, bool UO = false>
 __device__ __forceinline__ void contract(SP S, int P, int PP, const T (&X)[NS][D], const T (&W)[NS],
-                                         const T (&Ll)[NS][PMAX], T (&u)[NS], T (&v)[NS], int row,
-                                         bool uo = false)
+                                         const T (&Ll)[NS][PMAX], T (&u)[NS], T (&v)[NS], int row)
 {
     if constexpr (LV == D - 1) {
         // rows are padded with zeros to a multiple of 4 modes and read 4 at a time
@@ -337,7 +336,7 @@ __device__ __forceinline__ void contract(SP S, int P, int PP, const T (&X)[NS][D
         T tu[NS], tv[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) { tu[s] = (T)0; tv[s] = (T)0; }
-        if (uo) {
+        if constexpr (UO) {
 #pragma unroll
             for (int kb = 0; kb < PMAX / 4; ++kb) {
                 if (kb * 4 < P) {
@@ -398,7 +397,7 @@ __device__ __forceinline__ void contract(SP S, int P, int PP, const T (&X)[NS][D
             T W2[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) W2[s] = W[s] * Lc[s];
-            contract<T, D, PMAX, NS, LV + 1, SP>(S, P, PP, X, W2, Ll, u, v, row * P + k, uo);
+            contract<T, D, PMAX, NS, LV + 1, SP, UO>(S, P, PP, X, W2, Ll, u, v, row * P + k);
             const T ak = rec_a<T>(k), bk = rec_b<T>(k);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -1345,20 +1344,20 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
             }
             slots += NS;
             // ---- the point where step q's integrand is evaluated: the ball centre
-            // X_q (eq. interIQ) or the step's Green's-function ball point
-            T E[NS][D];
+            // X_q (eq. interIQ) or the step's Green's-function ball point, written
+            // over X (a live path moves to Y after the evaluation)
+            if (a.phys.ball) {
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
+                for (int s = 0; s < NS; ++s) {
+                    if (alive[s]) {
+                        T off[D];
+                        ball_offset<T, D>(c0[s], sample[s], q, c3, a.key0, a.key1, off);
 #pragma unroll
-                for (int i = 0; i < D; ++i) E[s][i] = X[s][i];
-                if (a.phys.ball && alive[s]) {
-                    T off[D];
-                    ball_offset<T, D>(c0[s], sample[s], q, c3, a.key0, a.key1, off);
-#pragma unroll
-                    for (int i = 0; i < D; ++i) E[s][i] = m_fma(J, off[i], X[s][i]);
+                        for (int i = 0; i < D; ++i) X[s][i] = m_fma(J, off[i], X[s][i]);
+                    }
                 }
             }
-            // ---- residual at E_q, time tau_q = t_{n,l} - q Delta: the slab of step q
+            // ---- residual at X_q, time tau_q = t_{n,l} - q Delta: the slab of step q
             // streams through LDS in NC chunks (double buffered along the chunk sequence)
             const bool wave_live = __ballot(any_live) != 0ull;
             T u[NS], v[NS];
@@ -1367,7 +1366,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
             T Ll[NS][PMAX];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const T x = E[s][D - 1];
+                const T x = X[s][D - 1];
                 Ll[s][0] = (T)1;
                 if (PMAX > 1) Ll[s][1] = x;
 #pragma unroll
@@ -1404,7 +1403,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                             for (int s = 0; s < NS; ++s) {
                                 T lp = (T)0, lc = (T)1;
                                 for (int m = 0; m < ki; ++m) {
-                                    const T nx = rec_a<T>(m) * E[s][i] * lc - rec_b<T>(m) * lp;
+                                    const T nx = rec_a<T>(m) * X[s][i] * lc - rec_b<T>(m) * lp;
                                     lp = lc;
                                     lc = nx;
                                 }
@@ -1412,7 +1411,10 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                             }
                         }
                     }
-                    contract<T, D, PMAX, NS, CF, const T *>(S, a.P, a.PP, E, Wc, Ll, u, v, 0, a.phys.picard != 0);
+                    if (a.phys.picard)
+                        contract<T, D, PMAX, NS, CF, const T *, true>(S, a.P, a.PP, X, Wc, Ll, u, v, 0);
+                    else
+                        contract<T, D, PMAX, NS, CF, const T *, false>(S, a.P, a.PP, X, Wc, Ll, u, v, 0);
                 }
                 if (has_next) {
                     u32x4 *dst = lds + (int64_t)(buf ^ 1) * cvec;
@@ -1429,7 +1431,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (alive[s]) {
-                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D>(a.phys, E[s], tf) +
+                        const T r = f_of<T>(a.phys, u[s]) + source_space<T, D>(a.phys, X[s], tf) +
                                     (a.phys.picard ? (T)0 : v[s]);
                         const T y = delta * r;
                         if constexpr (sizeof(T) == 4) {
@@ -1500,7 +1502,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                             }
                         }
                     }
-                    contract<T, D, PMAX, NS, CF, const T *>((const T *)lds, a.P, a.PP, X, Wc, Ll, u, v, 0, true);
+                    contract<T, D, PMAX, NS, CF, const T *, true>((const T *)lds, a.P, a.PP, X, Wc, Ll, u, v, 0);
                 }
             }
 #pragma unroll
