@@ -200,7 +200,9 @@ typedef struct {
 
 /* Sampling-kernel launch shape (chosen by hpsmc_tune or set directly). */
 typedef struct {
-    int32_t samples_per_lane;  /* 1, 2 or 4 (4 only for dim <= 2)               */
+    int32_t samples_per_lane;  /* 1, 2 or 4 (4 only for dim <= 2); plans with the
+                                  Picard form, the ball-point rule or the
+                                  fractional operator run 1 whatever is set     */
     int32_t waves_per_block;   /* 1..4                                            */
     int32_t blocks_per_cu;     /* persistent grid = CUs * blocks_per_cu          */
     int32_t round_steps;       /* walk steps per round of the path-advancing

@@ -925,9 +925,15 @@ static hpsmc_status aitken_reset(hpsmc_plan *plan, int iv, hipStream_t s)
     return HPSMC_OK;
 }
 
+static bool one_sample_per_lane(const hpsmc_plan *plan)
+{
+    return plan->frac || plan->pb.estimator == HPSMC_EST_PICARD || plan->pb.quad == HPSMC_QUAD_BALL;
+}
+
 static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
 {
-    const int ns = plan->frac ? 1 : plan->launch.samples_per_lane, waves = plan->launch.waves_per_block;
+    // the fractional kernel, the Picard form and the ball-point rule run one sample per lane
+    const int ns = one_sample_per_lane(plan) ? 1 : plan->launch.samples_per_lane, waves = plan->launch.waves_per_block;
     const int nthr = 64 * waves;
     int cf, n_chunks;
     int64_t chunk_elems;
@@ -1747,7 +1753,7 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     const int nsv[3] = {1, 2, 4};
     for (int a = 0; a < 3; ++a) {
         if (nsv[a] == 4 && plan->d > 2) continue;
-        if (nsv[a] != 1 && plan->frac) continue;   // the fractional kernel runs one path per lane
+        if (nsv[a] != 1 && one_sample_per_lane(plan)) continue;
         for (int w : {2, 4}) {
             // two-wave blocks of the matrix-core kernel: 1, 1.5, 2, 3, 4 waves per SIMD
             if (w == 2 && nsv[a] == 1 && plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 2)) {

@@ -1166,9 +1166,13 @@ __device__ __forceinline__ void mma_epilogue(const f32x16 &du0, const f32x16 &dv
     v = sv;
 }
 
-template <typename T, int D, int PMAX, int NS, int CF>
+// EXT: the Picard form and the ball-point rule are compiled in (selected at
+// run time by Physics); without it the residual form with the centre-point
+// rule carries none of their code.
+template <typename T, int D, int PMAX, int NS, int CF, bool EXT>
 __device__ __forceinline__ void advance_body(const RoundArgs &a)
 {
+    const bool picard = EXT && a.phys.picard, ball = EXT && a.phys.ball;
     constexpr int NSTG = kMaxStageVec;
     extern __shared__ u32x4 lds[];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
@@ -1346,7 +1350,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
             // ---- the point where step q's integrand is evaluated: the ball centre
             // X_q (eq. interIQ) or the step's Green's-function ball point, written
             // over X (a live path moves to Y after the evaluation)
-            if (a.phys.ball) {
+            if (ball) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (alive[s]) {
@@ -1411,7 +1415,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                             }
                         }
                     }
-                    if (a.phys.picard)
+                    if (picard)
                         contract<T, D, PMAX, NS, CF, const T *, true>(S, a.P, a.PP, X, Wc, Ll, u, v, 0);
                     else
                         contract<T, D, PMAX, NS, CF, const T *, false>(S, a.P, a.PP, X, Wc, Ll, u, v, 0);
@@ -1432,7 +1436,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                 for (int s = 0; s < NS; ++s) {
                     if (alive[s]) {
                         const T r = f_of<T>(a.phys, u[s]) + source_space<T, D>(a.phys, X[s], tf) +
-                                    (a.phys.picard ? (T)0 : v[s]);
+                                    (picard ? (T)0 : v[s]);
                         const T y = delta * r;
                         if constexpr (sizeof(T) == 4) {
                             const T yc = y - comp[s];
@@ -1454,7 +1458,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
         // ---- Picard form (eq. uast): a path still inside after all N* steps has
         // reached t_{n-1} and adds the interval's initial data u*(X_{N*}, t_{n-1}),
         // the slab of step N* (xi = -1), streamed through LDS like any step
-        if (a.phys.picard && q1 == nstar && q == q1) {
+        if (picard && q1 == nstar && q == q1) {
             bool any_live = false;
 #pragma unroll
             for (int s = 0; s < NS; ++s) any_live = any_live || alive[s];
@@ -1553,10 +1557,10 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
     }
 }
 
-template <typename T, int D, int PMAX, int NS, int CF>
+template <typename T, int D, int PMAX, int NS, int CF, bool EXT>
 __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
 {
-    advance_body<T, D, PMAX, NS, CF>(a);
+    advance_body<T, D, PMAX, NS, CF, EXT>(a);
 }
 
 // ===========================================================================
@@ -1740,8 +1744,16 @@ static hipError_t adv_cf(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, 
     // two or three fixed dimensions for d = 4, 5
     constexpr int C0 = D <= 3 ? 0 : D - 3;
     constexpr int C1 = D <= 1 ? 0 : (D <= 3 ? 1 : D - 2);
-    if (a.cf == C0) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C0>), grid, block, lds, s, a); return hipGetLastError(); }
-    if (a.cf == C1) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C1>), grid, block, lds, s, a); return hipGetLastError(); }
+    // the Picard form and the ball-point rule run one sample per lane
+    if (a.phys.picard || a.phys.ball) {
+        if constexpr (NS == 1) {
+            if (a.cf == C0) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C0, true>), grid, block, lds, s, a); return hipGetLastError(); }
+            if (a.cf == C1) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C1, true>), grid, block, lds, s, a); return hipGetLastError(); }
+        }
+        return hipErrorInvalidValue;
+    }
+    if (a.cf == C0) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C0, false>), grid, block, lds, s, a); return hipGetLastError(); }
+    if (a.cf == C1) { hipLaunchKernelGGL((advance_kernel<T, D, PMAX, NS, C1, false>), grid, block, lds, s, a); return hipGetLastError(); }
     return hipErrorInvalidValue;
 }
 
