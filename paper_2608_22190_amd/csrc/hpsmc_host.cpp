@@ -570,8 +570,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     const int64_t rows = ipow(plan->P, d - 1);
     const int64_t stride = rows * 2 * plan->PP;
     // plans the matrix-core round kernel can serve also get offsets in its slab layout
-    const bool mma_ok = advance_mma_eligible(plan->fp32, d, plan->P, 0, 1, 4) &&
-                        plan->pb.estimator == HPSMC_EST_RESIDUAL && plan->pb.quad == HPSMC_QUAD_CENTRE;
+    const bool mma_ok = advance_mma_eligible(plan->fp32, d, plan->P, 0, 1, 4);
     const int extra = plan->pb.estimator == HPSMC_EST_PICARD ? 1 : 0;   // the slab of q = N* (t = t_{n-1})
     const int64_t mstride = mma_slab_elems(plan->PP);
     int64_t slab_pos = 0, slab_pos_mma = 0, out = 0;
@@ -613,7 +612,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
                     set.host.push_back(nd);
                 }
                 slab_pos += (int64_t)(ns + extra) * stride;
-                if (mma_ok) slab_pos_mma += (int64_t)ns * mstride;
+                if (mma_ok) slab_pos_mma += (int64_t)(ns + extra) * mstride;
             }
         }
         out += (int64_t)plan->n_inst * plan->nsp * M;
@@ -884,6 +883,11 @@ static Physics physics_of(const hpsmc_plan *plan)
     return ph;
 }
 
+static bool one_sample_per_lane(const hpsmc_plan *plan)
+{
+    return plan->frac || plan->pb.estimator == HPSMC_EST_PICARD || plan->pb.quad == HPSMC_QUAD_BALL;
+}
+
 // Whether the rounds of this set run the matrix-core kernel with the current
 // launch shape (its slabs are then written in the matrix-core layout).
 static int set_uses_mma(const hpsmc_plan *plan, const NodeSet &set)
@@ -892,7 +896,8 @@ static int set_uses_mma(const hpsmc_plan *plan, const NodeSet &set)
     int cf, nc;
     int64_t ce;
     if (!pick_chunking(plan, 64 * plan->launch.waves_per_block, &cf, &ce, &nc)) return 0;
-    return advance_mma_eligible(plan->fp32, plan->d, plan->P, cf, plan->launch.samples_per_lane,
+    return advance_mma_eligible(plan->fp32, plan->d, plan->P, cf,
+                                one_sample_per_lane(plan) ? 1 : plan->launch.samples_per_lane,
                                 plan->launch.waves_per_block) ? 1 : 0;
 }
 
@@ -923,11 +928,6 @@ static hpsmc_status aitken_reset(hpsmc_plan *plan, int iv, hipStream_t s)
     const int64_t v0 = (int64_t)(seq ? 0 : iv) * plan->n_inst;
     HIP_TRY(launch_fill_u64((unsigned long long *)(set.ait + 2 * v0), 2 * (int64_t)plan->n_inst, 0ull, s));
     return HPSMC_OK;
-}
-
-static bool one_sample_per_lane(const hpsmc_plan *plan)
-{
-    return plan->frac || plan->pb.estimator == HPSMC_EST_PICARD || plan->pb.quad == HPSMC_QUAD_BALL;
 }
 
 static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
@@ -1671,7 +1671,7 @@ static std::string tune_key(const hpsmc_plan *plan, int iv, int64_t M)
     // plans that may run the matrix-core round kernel tune separately from those that may not
     const bool picard = plan->pb.estimator == HPSMC_EST_PICARD;
     const bool ball = plan->pb.quad == HPSMC_QUAD_BALL;
-    const bool mma = plan->sample_mma && !picard && !ball && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
+    const bool mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
     char buf[256];
     snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
              plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", picard ? "_picard" : "", ball ? "_ball" : "",

@@ -1108,8 +1108,8 @@ __device__ __forceinline__ void mma_operands(float x1, int P, float (&b0)[KH], f
     }
 }
 
-// the four products (u and v tables, both path halves)
-template <int KH>
+// the four products (u and v tables, both path halves); UO: the u table only
+template <int KH, bool UO = false>
 __device__ __forceinline__ void mma_issue(const float *Sb, int PP, int lane, const float (&b0)[KH],
                                           const float (&b1)[KH], f32x16 &du0, f32x16 &dv0, f32x16 &du1, f32x16 &dv1)
 {
@@ -1118,18 +1118,18 @@ __device__ __forceinline__ void mma_issue(const float *Sb, int PP, int lane, con
     du0 = f32x16{}; dv0 = f32x16{}; du1 = f32x16{}; dv1 = f32x16{};
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
-        const float au = Au[kk * kMmaRS], av = Av[kk * kMmaRS];
+        const float au = Au[kk * kMmaRS];
         du0 = __builtin_amdgcn_mfma_f32_32x32x2f32(au, b0[kk], du0, 0, 0, 0);
-        dv0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0[kk], dv0, 0, 0, 0);
+        if constexpr (!UO) dv0 = __builtin_amdgcn_mfma_f32_32x32x2f32(Av[kk * kMmaRS], b0[kk], dv0, 0, 0, 0);
         du1 = __builtin_amdgcn_mfma_f32_32x32x2f32(au, b1[kk], du1, 0, 0, 0);
-        dv1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1[kk], dv1, 0, 0, 0);
+        if constexpr (!UO) dv1 = __builtin_amdgcn_mfma_f32_32x32x2f32(Av[kk * kMmaRS], b1[kk], dv1, 0, 0, 0);
     }
 }
 
 // rows back to the owning lane and the contraction with Q_{k0}(x0) (rows >= P
 // of T are zero).  Registers r = 4g..4g+3 hold rows 8g..8g+3 (before the swap)
 // and 8g+4..8g+7 (after it): the Legendre values in x0 advance eight at a time.
-template <int KH>
+template <int KH, bool UO = false>
 __device__ __forceinline__ void mma_epilogue(const f32x16 &du0, const f32x16 &dv0, const f32x16 &du1,
                                              const f32x16 &dv1, float x0, float &u, float &v)
 {
@@ -1152,12 +1152,12 @@ __device__ __forceinline__ void mma_epilogue(const f32x16 &du0, const f32x16 &dv
             const int r = 4 * g + rr, ia = 8 * g + rr, ib = ia + 4;
             if (ia < K2) {
                 const auto pu = __builtin_amdgcn_permlane32_swap(__float_as_uint(du0[r]), __float_as_uint(du1[r]), false, false);
-                const auto pv = __builtin_amdgcn_permlane32_swap(__float_as_uint(dv0[r]), __float_as_uint(dv1[r]), false, false);
                 su = fmaf(Lb[rr], __uint_as_float(pu[0]), su);
-                sv = fmaf(Lb[rr], __uint_as_float(pv[0]), sv);
-                if (ib < K2) {
-                    su = fmaf(Lb[4 + rr], __uint_as_float(pu[1]), su);
-                    sv = fmaf(Lb[4 + rr], __uint_as_float(pv[1]), sv);
+                if (ib < K2) su = fmaf(Lb[4 + rr], __uint_as_float(pu[1]), su);
+                if constexpr (!UO) {
+                    const auto pv = __builtin_amdgcn_permlane32_swap(__float_as_uint(dv0[r]), __float_as_uint(dv1[r]), false, false);
+                    sv = fmaf(Lb[rr], __uint_as_float(pv[0]), sv);
+                    if (ib < K2) sv = fmaf(Lb[4 + rr], __uint_as_float(pv[1]), sv);
                 }
             }
         }
@@ -1574,9 +1574,14 @@ __global__ void __launch_bounds__(256) advance_kernel(RoundArgs a)
 // only for paths whose jump stayed inside -- the same walk, exit steps and
 // quadrature as the vector-unit kernel.
 // ===========================================================================
-template <int KH>
+// MODE bit 0: the Picard form (the u table only, the initial data at the end
+// point of paths that stay inside for all N* steps); bit 1: the ball-point
+// rule (the operands and the epilogue take the step's Green's-function ball
+// point, drawn one step ahead like the walk's next point).
+template <int KH, int MODE>
 __device__ __forceinline__ void advance_mma_body(const RoundArgs &a)
 {
+    constexpr bool PIC = (MODE & 1) != 0, BALL = (MODE & 2) != 0;
     extern __shared__ u32x4 lds[];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
     __shared__ long long s_item;
@@ -1642,8 +1647,17 @@ __device__ __forceinline__ void advance_mma_body(const RoundArgs &a)
         };
         fill_time(q0);
         mma_stage((const u32x4 *)(gtab + (int64_t)q0 * a.slab_stride), lds, mvec, tid, nthr);
+        float ex0 = x0, ex1 = x1;   // where the current step's integrand is evaluated
+        if constexpr (BALL) {
+            if (alive) {
+                float off[2];
+                ball_offset<float, 2>(c0, sample, q0, c3, a.key0, a.key1, off);
+                ex0 = fmaf(J, off[0], x0);
+                ex1 = fmaf(J, off[1], x1);
+            }
+        }
         float b0[KH], b1[KH];
-        mma_operands<KH>(x1, a.P, b0, b1);
+        mma_operands<KH>(ex1, a.P, b0, b1);
         mma_stage_wait();
         __syncthreads();
 
@@ -1662,28 +1676,39 @@ __device__ __forceinline__ void advance_mma_body(const RoundArgs &a)
             if (q + 1 < q1)
                 mma_stage((const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride), lds + (buf ^ 1) * mvec, mvec, tid,
                           nthr);
-            float u = 0.f, v = 0.f, y0 = x0, y1 = x1;
+            float u = 0.f, v = 0.f, y0 = x0, y1 = x1, nx0 = x0, nx1 = x1;
             bool inside = false;
             if (__ballot(alive) != 0ull) {
                 f32x16 du0, dv0, du1, dv1;
-                mma_issue<KH>((const float *)lds + buf * mbuf, a.PP, lane, b0, b1, du0, dv0, du1, dv1);
+                mma_issue<KH, PIC>((const float *)lds + buf * mbuf, a.PP, lane, b0, b1, du0, dv0, du1, dv1);
                 // under the products: direction, jump, exit test, next operands
                 float d0, d1;
                 angle_dir(u01(word, 0.f), d0, d1);
                 y0 = fmaf(J, d0, x0);
                 y1 = fmaf(J, d1, x1);
                 inside = fabsf(y0) < 1.f && fabsf(y1) < 1.f;
+                nx0 = y0;
+                nx1 = y1;
+                if constexpr (BALL) {
+                    if (alive && inside && q + 1 < q1) {
+                        float off[2];
+                        ball_offset<float, 2>(c0, sample, q + 1, c3, a.key0, a.key1, off);
+                        nx0 = fmaf(J, off[0], y0);
+                        nx1 = fmaf(J, off[1], y1);
+                    }
+                }
                 float nb0[KH], nb1[KH];
-                mma_operands<KH>(y1, a.P, nb0, nb1);
-                mma_epilogue<KH>(du0, dv0, du1, dv1, x0, u, v);
+                mma_operands<KH>(nx1, a.P, nb0, nb1);
+                mma_epilogue<KH, PIC>(du0, dv0, du1, dv1, ex0, u, v);
 #pragma unroll
                 for (int kk = 0; kk < KH; ++kk) { b0[kk] = nb0[kk]; b1[kk] = nb1[kk]; }
             }
             ++slots;
             if (alive) {
-                if (inside) {   // residual at X_q, time tau_q = t_{n,l} - q Delta
-                    const float X[2] = {x0, x1};
-                    const float r = f_of<float>(a.phys, u) + source_space<float, 2, true>(a.phys, X, s_tf[tslot]) + v;
+                if (inside) {   // residual at X_q (or its ball point), time tau_q = t_{n,l} - q Delta
+                    const float X[2] = {ex0, ex1};
+                    const float r = f_of<float>(a.phys, u) + source_space<float, 2, !BALL>(a.phys, X, s_tf[tslot]) +
+                                    (PIC ? 0.f : v);
                     const float y = delta * r;
                     const float yc = y - comp;
                     const float tt = acc + yc;
@@ -1691,6 +1716,8 @@ __device__ __forceinline__ void advance_mma_body(const RoundArgs &a)
                     acc = tt;
                     x0 = y0;
                     x1 = y1;
+                    ex0 = nx0;
+                    ex1 = nx1;
                     ++evals;
                 } else {        // path ended: L = q
                     alive = false;
@@ -1699,6 +1726,31 @@ __device__ __forceinline__ void advance_mma_body(const RoundArgs &a)
             }
             mma_stage_wait();
             if (__syncthreads_or(alive ? 1 : 0) == 0) { ++q; break; }
+        }
+
+        // ---- Picard form (eq. uast): a path still inside after all N* steps adds
+        // the interval's initial data u*(X_{N*}, t_{n-1}), the slab of step N*
+        if constexpr (PIC) {
+            if (q1 == nstar && q == q1) {
+                __syncthreads();
+                mma_stage((const u32x4 *)(gtab + (int64_t)nstar * a.slab_stride), lds, mvec, tid, nthr);
+                mma_stage_wait();
+                __syncthreads();
+                if (__ballot(alive) != 0ull) {
+                    float tb0[KH], tb1[KH];
+                    mma_operands<KH>(x1, a.P, tb0, tb1);
+                    f32x16 du0, dv0, du1, dv1;
+                    mma_issue<KH, true>((const float *)lds, a.PP, lane, tb0, tb1, du0, dv0, du1, dv1);
+                    float u = 0.f, v = 0.f;
+                    mma_epilogue<KH, true>(du0, dv0, du1, dv1, x0, u, v);
+                    if (alive) {
+                        const float yc = u - comp;
+                        const float tt = acc + yc;
+                        comp = (tt - acc) - yc;
+                        acc = tt;
+                    }
+                }
+            }
         }
 
         // ---- paths alive after the round: finished at N*, or carried to the next round
@@ -1731,10 +1783,10 @@ __device__ __forceinline__ void advance_mma_body(const RoundArgs &a)
     }
 }
 
-template <int KH>
+template <int KH, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) advance_mma_kernel(RoundArgs a)
 {
-    advance_mma_body<KH>(a);
+    advance_mma_body<KH, MODE>(a);
 }
 
 template <typename T, int D, int PMAX, int NS>
@@ -1797,14 +1849,14 @@ static hipError_t adv_d(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_
     return hipErrorInvalidValue;
 }
 
-template <int KH>
+template <int KH, int MODE>
 static hipError_t adv_mma(const RoundArgs &a, int kh, dim3 grid, dim3 block, size_t lds, hipStream_t s)
 {
     if constexpr (KH > 16) {
         return hipErrorInvalidValue;
     } else {
-        if (kh != KH) return adv_mma<KH + 1>(a, kh, grid, block, lds, s);
-        hipLaunchKernelGGL((advance_mma_kernel<KH>), grid, block, lds, s, a);
+        if (kh != KH) return adv_mma<KH + 1, MODE>(a, kh, grid, block, lds, s);
+        hipLaunchKernelGGL((advance_mma_kernel<KH, MODE>), grid, block, lds, s, a);
         return hipGetLastError();
     }
 }
@@ -2073,7 +2125,12 @@ hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, in
     if (mma) {
         if (!advance_mma_eligible(fp32, a.phys.dim, a.P, a.cf, samples_per_lane, waves_per_block))
             return hipErrorInvalidValue;
-        return adv_mma<2>(a, (a.P + 1) / 2, grid, block, lds_bytes, s);
+        switch ((a.phys.picard ? 1 : 0) | (a.phys.ball ? 2 : 0)) {
+        case 0: return adv_mma<2, 0>(a, (a.P + 1) / 2, grid, block, lds_bytes, s);
+        case 1: return adv_mma<2, 1>(a, (a.P + 1) / 2, grid, block, lds_bytes, s);
+        case 2: return adv_mma<2, 2>(a, (a.P + 1) / 2, grid, block, lds_bytes, s);
+        default: return adv_mma<2, 3>(a, (a.P + 1) / 2, grid, block, lds_bytes, s);
+        }
     }
     return fp32 ? adv_d<float>(a, samples_per_lane, grid, block, lds_bytes, s)
                 : adv_d<double>(a, samples_per_lane, grid, block, lds_bytes, s);

@@ -67,6 +67,50 @@ def test_mma_kernel_walks_the_vector_kernel_paths(n, deg, M):
     assert e_m <= 2.0 * e_v + 1e-5 * scale
 
 
+@pytest.mark.parametrize("estimator,quad,n,deg,M", [("picard", "centre", 3, 3, 96), ("picard", "centre", 24, 2, 33),
+                                                     ("residual", "ball", 4, 2, 130), ("residual", "ball", 11, 2, 64),
+                                                     ("picard", "ball", 5, 3, 64)])
+def test_mma_modes_walk_the_vector_kernel_paths(estimator, quad, n, deg, M):
+    """The Picard form (u table only, the initial data at the end point of
+    paths that stay inside for all N* steps) and the ball-point rule on the
+    matrix cores: the vector-unit kernel's walks, per-sample values within
+    FP32 rounding of them and no less accurate against the FP64 oracle."""
+    H = _hp()
+    wl = W.small(dim=2, n=n, M_deg=deg, M=M, T=0.5, f="sin", src="longtime", precision="fp32",
+                 estimator=estimator, quad=quad, nstar=40 if estimator == "picard" else None)
+    _say("mma modes", estimator, quad, n, deg, M)
+    U = np.random.default_rng(n + 1).standard_normal((1, wl.nsp, deg + 1)) * 0.5
+    mp = min(M, 8)
+    res = {}
+    for mma in (1, 0):
+        with H.Plan(wl) as plan:
+            plan.hpsmc_set_option("sample_mfma", mma)
+            plan.hpsmc_set_launch(1, 4, 4, 16)        # several rounds: the state is carried over
+            assert plan.hpsmc_get_option("sample_mfma_active") == mma
+            plan.hpsmc_set_probe(mp)
+            plan.hpsmc_set_nodes(0, U)
+            plan.hpsmc_iterate(0, 1)
+            res[mma] = (plan.hpsmc_get_probe(0)[0], plan.hpsmc_get_nodes(0)[0], plan.hpsmc_stats())
+    (pm, um, sm), (pv, uv, sv) = res[1], res[0]
+    assert sm["path_steps"] == sv["path_steps"]
+    scale = 1.0 + np.max(np.abs(pv))
+    dmv = np.max(np.abs(pm - pv))
+    print(f"max|S_mma - S_valu| = {dmv:.3e} (scale {scale:.3e})")
+    assert dmv <= 1e-4 * scale
+    assert np.max(np.abs(um - uv)) <= 1e-4 * scale
+    pb = O.Problem(wl)
+    Ut = O.reconstruct(2, n, deg, U[0].reshape(-1))
+    rng = np.random.default_rng(9)
+    e_m = e_v = 0.0
+    for node in rng.choice(pm.shape[0], size=min(6, pm.shape[0]), replace=False):
+        for smp in range(min(mp, 4)):
+            S, _ = pb.sample_path(Ut, 0, 0, 1, int(node), smp)
+            e_m = max(e_m, abs(pm[node, smp] - S))
+            e_v = max(e_v, abs(pv[node, smp] - S))
+    print(f"vs oracle: mma {e_m:.3e} valu {e_v:.3e}")
+    assert e_m <= 2.0 * e_v + 1e-5 * scale
+
+
 def test_mma_fp32_statistical_parity_r24():
     """Reading R24 with the matrix-core kernel: same Philox words as the FP64
     solve; e32 <= e64 + 3 sigma and |u32 - u64| <= 3 sigma + 1e-5."""

@@ -79,6 +79,7 @@ def test_picard_fp32_within_monte_carlo_noise():
     res = {}
     for prec in ("fp64", "fp32"):
         with H.Plan(wl.with_(precision=prec)) as plan:
+            plan.hpsmc_set_option("sample_mfma", 0)   # the vector-unit kernel (the matrix-core one: test_gpu_mma)
             plan.hpsmc_set_launch(1, 4, 4)
             assert plan.hpsmc_get_option("sample_mfma_active") == 0
             plan.hpsmc_solve()
