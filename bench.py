@@ -449,7 +449,7 @@ def main():
                     help="autotuner cache (looked up; tuned and written when the entry is missing)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (one process, one device).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (one process, one device).",
               file=sys.stderr)
         sys.exit(2)
 
