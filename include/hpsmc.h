@@ -1,7 +1,8 @@
 /*
  * hpsmc.h -- C ABI of the MI355X hot path of the hp-version time-stepping
  * spectral Monte Carlo method for u_t = Lap u + f(u) + s on (-1,1)^d with
- * homogeneous Dirichlet data (arXiv 2608.22190).
+ * homogeneous Dirichlet data, and u_t = -(-Lap)^{alpha/2} u + f(u) + s on
+ * (-1,1) with u = 0 outside (arXiv 2608.22190).
  *
  * The library estimates, at every space-time node (x_j, t_{n,l}) of an
  * interval, the residual increment eps of eq. varepsilon_1 by Monte Carlo
@@ -32,7 +33,14 @@
  *     counter (node id, sample, step block, instance<<16 | interval<<8 | tag),
  *     tag = iteration (or sweep) index when fresh_per_iter, else 0.  d = 1 uses
  *     one bit per step (128 steps per block), d = 2 one word (4 steps per
- *     block), d = 3, 4 one block per step, d = 5 two blocks per step.
+ *     block), d = 3, 4 one block per step, d = 5 two blocks per step; the
+ *     fractional walk (d = 1) two words per step (2 steps per block); the
+ *     ball-point rule draws from step blocks with bit 31 set.
+ *   - Variants of the method selected per plan (hpsmc_problem): the estimator
+ *     (residual form, eq. varepsilon_1, or the Picard form, eq. uast), the
+ *     update (plain, or Aitken-relaxed), the path quadrature (centre point,
+ *     eq. interIQ, or the Green's-function ball point), and the order of the
+ *     operator (the Laplacian, or the fractional Laplacian in 1-D).
  */
 #ifndef HPSMC_H
 #define HPSMC_H
@@ -306,10 +314,13 @@ hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_
  *   "sample_mfma"       1 (default): 2-D FP32 plans with P = n + 2 <= 32 and one
  *                       sample per lane run the path-advancing kernel with the
  *                       slab contraction of eq. ufg_ep1 on the matrix cores
- *                       (v_mfma_f32_32x32x2f32); 0: always on the vector units.
- *                       Same walks and exit steps either way; the FP32 sums
- *                       differ only by rounding order.  Changing it discards a
- *                       captured graph.
+ *                       (v_mfma_f32_32x32x2f32) -- the residual and Picard
+ *                       forms, the centre-point and ball-point rules (plans of
+ *                       the Picard form or the ball rule count as one sample
+ *                       per lane); 0: always on the vector units.  Same walks
+ *                       and exit steps either way; the FP32 sums differ only
+ *                       by rounding order.  Changing it discards a captured
+ *                       graph.
  *   "graph"             1: hpsmc_solve captures the whole solve into a hipGraph
  *                       on its first call (on a stream of the plan) and replays
  *                       it on this and later calls; 0 (default): eager launches.
