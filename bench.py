@@ -136,6 +136,8 @@ def run_other(name, args, torch):
         return run_ballcmp(args, torch)
     if name == "frac":
         return run_frac(args, torch)
+    if name == "fraccmp":
+        return run_fraccmp(args, torch)
     if name == "c1":
         wl = W.c1_single_step()
     elif name == "c2p":
@@ -328,6 +330,49 @@ def run_frac(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def run_fraccmp(args, torch):
+    """The paper's long-time contrast on its fractional problem (Ex. 2): the
+    residual form against the Picard (classical Monte Carlo) form, alpha = 0.4,
+    11 x 6 nodes per interval, h = 0.5 to T = 50, M = 8192, 10 iterations per
+    interval, FP64, the same walks; error against the exact solution per
+    interval, absolute and relative to max |u_ex| on the interval."""
+    from paper_2608_22190_amd import hpsmc, workloads as W
+    out = {}
+    stream = torch.cuda.Stream()
+    for est in ("residual", "picard"):
+        wl = W.frac_long_time(iters=10, n_intervals=100, precision="fp64", estimator=est)
+        with hpsmc.Plan(wl) as plan:
+            if args.tune_cache:
+                plan.hpsmc_tune(0, wl.M, args.tune_cache, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.hpsmc_solve(stream=stream)
+            stream.synchronize()
+            sec = time.perf_counter() - t0
+            err, rel = [], []
+            for iv in range(wl.n_intervals):
+                x, t = plan.hpsmc_grid(iv)
+                ex = ((1 - x ** 2) ** (wl.alpha / 2) * np.sin(x))[:, None] * (np.exp(np.cos(t)) / (1 + t ** 2))[None, :]
+                e = float(np.max(np.abs(plan.hpsmc_get_nodes(iv)[0] - ex)))
+                err.append(e)
+                rel.append(e / float(np.max(np.abs(ex))))
+        out[est] = {"seconds": sec, "max_error": max(err), "final_error": err[-1], "final_relative_error": rel[-1],
+                    "error_at_T": {str(T): err[int(2 * T) - 1] for T in (1, 5, 10, 25, 50)},
+                    "relative_error_at_T": {str(T): rel[int(2 * T) - 1] for T in (1, 5, 10, 25, 50)}}
+        print(f"[bench] fraccmp {est}: {sec:.2f}s, max error {max(err):.3e}, relative error at T=50 {rel[-1]:.3e}",
+              file=sys.stderr, flush=True)
+    wl = W.frac_long_time(iters=10, n_intervals=100)
+    ns = wl.nodes_per_sweep * wl.M * wl.iters
+    line = {"metric": METRIC, "value": ns / out["residual"]["seconds"], "unit": "node-samples/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": 1e3 * out["residual"]["seconds"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "fractional long-time problem (Ex. 2 shape) to T = 50: residual form against the "
+                                   "Picard (classical Monte Carlo) form, alpha = 0.4, 11 x 6 nodes per interval, "
+                                   "h = 0.5, M = 8192, 10 iterations per interval, FP64"},
+            "comparison": out}
+    print(json.dumps(line), flush=True)
+
+
 def run_ballcmp(args, torch):
     """Centre-point (eq. interIQ) against ball-point path quadrature on the
     single-step problem (1-D, u = e^{-t} sin(pi x), 16 x 16 nodes, M = 4096,
@@ -440,7 +485,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c2b", "c3", "c4", "c5", "compare", "aitken",
-                                                              "ballcmp", "frac"])
+                                                              "ballcmp", "frac", "fraccmp"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--launch", type=str, default="",

@@ -172,9 +172,9 @@ typedef struct {
                                   (alpha/2, alpha/2), basis (1-x^2)^{alpha/2}
                                   P_p^{(alpha/2,alpha/2)}, p < n, the alpha-stable
                                   walk (jumps from the exit law of a ball whose
-                                  mean exit time is Delta).  Residual estimator,
-                                  centre-point rule, initial data IC_EXACT or
-                                  IC_NODAL; no gradient, no hpsmc_eval or
+                                  mean exit time is Delta).  Residual or Picard
+                                  form, centre-point rule, initial data IC_EXACT
+                                  or IC_NODAL; no gradient, no hpsmc_eval or
                                   hpsmc_get_coeffs                              */
 } hpsmc_problem;
 

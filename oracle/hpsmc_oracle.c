@@ -849,7 +849,8 @@ static double or_picard_integrand(const or_problem *pb, int interval, const doub
     double t0 = pb->t_breaks[interval], h = pb->t_breaks[interval + 1] - t0;
     double xi = 2.0 * (tau - t0) / h - 1.0;
     double v[3];
-    or_eval(pb->dim, pb->n, pb->degree[interval], h, Ut, X, xi, v);
+    if (or_is_frac(pb)) or_frac_eval(pb->alpha, pb->n, pb->degree[interval], h, Ut, X[0], xi, v);
+    else or_eval(pb->dim, pb->n, pb->degree[interval], h, Ut, X, xi, v);
     return or_f(pb, v[0]) + or_source(pb, X, tau);
 }
 
@@ -908,7 +909,8 @@ static double or_path(const or_problem *pb, const double *Ut, int inst, int inte
     }
     if (pb->estimator == OR_EST_PICARD && q == nd->nstar) {
         double h = pb->t_breaks[interval + 1] - t0, v[3];
-        or_eval(d, pb->n, pb->degree[interval], h, Ut, X, -1.0, v);   /* t = t_{n-1}: xi = -1 */
+        if (or_is_frac(pb)) or_frac_eval(pb->alpha, pb->n, pb->degree[interval], h, Ut, X[0], -1.0, v);
+        else or_eval(d, pb->n, pb->degree[interval], h, Ut, X, -1.0, v);   /* t = t_{n-1}: xi = -1 */
         acc += v[0];
     }
     if (L_out) *L_out = q;
@@ -955,7 +957,7 @@ int or_estimate(const or_problem *pb, int inst, int interval, int iter_tag,
     if (cnt <= 0 || m_lo < 0) return -1;
     if (or_is_frac(pb)) {
         /* the fractional form: d = 1, residual estimator, centre-point rule */
-        if (d != 1 || pb->estimator != OR_EST_RESIDUAL || pb->quad != OR_QUAD_CENTRE) return -2;
+        if (d != 1 || pb->quad != OR_QUAD_CENTRE) return -2;
         int rc = or_frac_prepare(pb);
         if (rc) return rc;
     }

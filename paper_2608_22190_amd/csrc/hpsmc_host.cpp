@@ -483,8 +483,8 @@ static hpsmc_status validate(const hpsmc_problem *pb)
         if (pb->dim != 1) return fail(HPSMC_ENOTSUP, "the fractional operator is built for d = 1");
         if (pb->src_kind != HPSMC_SRC_NONE && pb->src_kind < HPSMC_SRC_FRAC_LONGTIME)
             return fail(HPSMC_EINVAL, "the Laplacian's manufactured sources do not solve the fractional problem");
-        if (pb->estimator != HPSMC_EST_RESIDUAL || pb->quad != HPSMC_QUAD_CENTRE)
-            return fail(HPSMC_ENOTSUP, "the fractional form takes the residual estimator and the centre-point rule");
+        if (pb->quad != HPSMC_QUAD_CENTRE)
+            return fail(HPSMC_ENOTSUP, "the fractional form takes the centre-point rule");
         if (pb->ic_kind != HPSMC_IC_EXACT && pb->ic_kind != HPSMC_IC_NODAL)
             return fail(HPSMC_ENOTSUP, "the fractional form takes IC_EXACT or IC_NODAL");
     } else if (pb->src_kind >= HPSMC_SRC_FRAC_LONGTIME) {

@@ -2052,7 +2052,8 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
                         }
                         src = wgt * gx * Tp + Gs * Tt - f_of<T>(ph, wgt * gx * Tt);
                     }
-                    const T r = f_of<T>(ph, wgt * uj) + src + wgt * vj - F;
+                    // Picard form (eq. uast): the integrand f(u*) + s only
+                    const T r = ph.picard ? f_of<T>(ph, wgt * uj) + src : f_of<T>(ph, wgt * uj) + src + wgt * vj - F;
                     const T y = delta * r;
                     if constexpr (sizeof(T) == 4) {
                         const T yc = y - comp;
@@ -2069,6 +2070,33 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
             }
             ++slots;
             if (__syncthreads_or(any_live ? 1 : 0) == 0) { ++q; break; }
+        }
+
+        // ---- Picard form (eq. uast): a path still inside after all N* steps adds
+        // the interval's initial data u*(X_{N*}, t_{n-1}), the slab of step N*
+        if (ph.picard && q1 == nstar && q == q1) {
+            __syncthreads();
+            if (tid < nv) lds[tid] = ((const u32x4 *)(gtab + (int64_t)nstar * a.slab_stride))[tid];
+            __syncthreads();
+            if (alive) {
+                const T *S = (const T *)lds;
+                T pm = (T)0, pc = (T)1, uj = (T)0;
+                for (int k = 0; k < P; ++k) {
+                    uj = m_fma(S[k], pc, uj);
+                    const T pn = tA[k] * X * pc - tC[k] * pm;
+                    pm = pc;
+                    pc = pn;
+                }
+                const T y = m_exp(fa * m_log(((T)1 - X) * ((T)1 + X))) * uj;
+                if constexpr (sizeof(T) == 4) {
+                    const T yc = y - comp;
+                    const T tt = acc + yc;
+                    comp = (tt - acc) - yc;
+                    acc = tt;
+                } else {
+                    acc += y;
+                }
+            }
         }
 
         // ---- paths alive after the round: finished at N*, or carried to the next round

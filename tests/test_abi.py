@@ -67,8 +67,8 @@ def test_invalid_aitken_weights_are_rejected(omega):
 
 @pytest.mark.parametrize("change,status", [
     (dict(src="frac_longtime", alpha=2.0), -1), (dict(src="sin_decay", alpha=0.5), -1),
-    (dict(src="frac_longtime", alpha=0.5, dim=2, n=3), -2), (dict(src="frac_longtime", alpha=0.5, estimator="picard"), -2),
-    (dict(src="frac_longtime", alpha=0.5, quad="ball"), -2), (dict(src="frac_longtime", alpha=-1.0), -1),
+    (dict(src="frac_longtime", alpha=0.5, dim=2, n=3), -2), (dict(src="frac_longtime", alpha=0.5, quad="ball"), -2),
+    (dict(src="frac_longtime", alpha=-1.0), -1),
     (dict(src="frac_longtime", alpha=2.5), -1), (dict(src="frac_longtime", alpha=float("nan")), -1),
     (dict(src="frac_longtime", alpha=0.5, ic="phi", ic_data=__import__("numpy").zeros((1, 4))), -2)])
 def test_invalid_fractional_problems_are_rejected(change, status):

@@ -58,6 +58,45 @@ def test_frac_iteration_matches_oracle_fp64(alpha, n, deg, M, waves):
             assert abs(pr[node, smp] - S) <= TOL * (1 + abs(S))
 
 
+@pytest.mark.parametrize("alpha,n,deg,M", [(0.5, 7, 3, 97), (1.4, 9, 4, 64)])
+def test_frac_picard_matches_oracle_fp64(alpha, n, deg, M):
+    """The Picard form with the alpha-stable walk: integrand f(u*) + s, the
+    initial data at the end point of paths that stay inside for all N* steps,
+    the estimate replacing the iterate; short rounds carry paths over."""
+    H = _hp()
+    wl = W.small(dim=1, n=n, M_deg=deg, M=M, T=0.5, f="u_minus_u3", src="frac_longtime", alpha=alpha,
+                 estimator="picard")
+    _say("frac picard", alpha, n, deg, M)
+    U = np.random.default_rng(n + 3).standard_normal((1, n, deg + 1)) * 0.4
+    with H.Plan(wl) as plan:
+        plan.hpsmc_set_launch(1, 4, 4, 16)
+        plan.hpsmc_set_probe(min(M, 6))
+        plan.hpsmc_set_nodes(0, U)
+        plan.hpsmc_iterate(0, 1)
+        Ug = plan.hpsmc_get_nodes(0)[0]
+        pr = plan.hpsmc_get_probe(0)[0]
+        st = plan.hpsmc_stats()
+    pb = O.Problem(wl)
+    Uo, _, steps = pb.iterate(U[0].reshape(-1), iter_tag=1)
+    assert _close(Ug, Uo.reshape(n, deg + 1))
+    assert np.array_equal(Ug[:, 0], U[0][:, 0])
+    assert st["path_steps"] == steps
+    Ut = O.frac_reconstruct(alpha, n, deg, U[0].reshape(-1))
+    for node in np.random.default_rng(2).choice(pr.shape[0], size=5, replace=False):
+        for smp in range(pr.shape[1]):
+            S, _ = pb.sample_path(Ut, 0, 0, 1, int(node), smp)
+            assert abs(pr[node, smp] - S) <= TOL * (1 + abs(S))
+    # two intervals: the terminal data come from the first interval's last column
+    wl2 = W.small(dim=1, n=6, M_deg=[3, 3], M=48, iters=2, T=0.8, n_intervals=2, f="u_minus_u3",
+                  src="frac_longtime", alpha=alpha, estimator="picard")
+    with H.Plan(wl2) as plan:
+        plan.hpsmc_solve()
+        got = [plan.hpsmc_get_nodes(iv)[0] for iv in range(2)]
+    Uo2, _ = O.Problem(wl2).solve()
+    for iv in range(2):
+        assert _close(got[iv], Uo2[iv]), iv
+
+
 def test_frac_solves_match_oracle_fp64():
     H = _hp()
     cases = [W.small(dim=1, n=7, M_deg=[3, 4], M=80, iters=3, T=1.0, n_intervals=2, f="u_minus_u3",

@@ -159,3 +159,21 @@ def test_fractional_iteration_decreases_geometrically():
     ex = np.array([[pb.exact([xj], tl) for tl in t] for xj in x])
     assert np.all(mx[1:] < 0.6 * mx[:-1]), mx
     assert np.max(np.abs(U[0] - ex)) < 0.05 * np.max(np.abs(ex))
+
+
+def test_fractional_picard_form_keeps_the_noise_the_residual_form_removes():
+    """The classical (Picard-form) estimator with the alpha-stable walk: its
+    iterate is the Monte Carlo estimate of the solution itself, so its error
+    stays at the sampling noise of |u| (and the walk's bias), while the residual
+    form's increments shrink with the residual -- the paper's contrast (Ex. 2)."""
+    res = {}
+    for est in ("residual", "picard"):
+        wl = W.small(dim=1, n=6, M_deg=3, M=300, iters=6, T=0.5, f="u_minus_u3", src="frac_longtime", alpha=1.3,
+                     estimator=est)
+        pb = O.Problem(wl)
+        U, _ = pb.solve()
+        x, t = pb.grid(0)
+        ex = np.array([[pb.exact([xj], tl) for tl in t] for xj in x])
+        res[est] = np.max(np.abs(U[0] - ex))
+    assert res["residual"] < 1e-3, res
+    assert res["picard"] > 10 * res["residual"] and res["picard"] < 0.5, res
