@@ -138,6 +138,8 @@ def run_other(name, args, torch):
         return run_frac(args, torch)
     if name == "fraccmp":
         return run_fraccmp(args, torch)
+    if name == "fracexp":
+        return run_fracexp(args, torch)
     if name == "c1":
         wl = W.c1_single_step()
     elif name == "c2p":
@@ -373,6 +375,64 @@ def run_fraccmp(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def run_fracexp(args, torch):
+    """Accuracy studies of the fractional examples, FP64, M = 8192:
+    (a) Ex. 2 to T = 25 with step sizes h = 1, 0.5, 0.2, 0.1 (M_n = 6, 11
+        nodes, 10 iterations per interval; at most 255 intervals, the
+        counter's interval field): max error over all nodes;
+    (b) Ex. 3 (rho = 0.51, T = 0.5): the geometric mesh t_n = T 0.2^{N-n} with
+        degrees M_1 = 1, M_n = floor(1.5 n), N = 2..8, against uniform steps
+        h = T/N with the same largest degree; 12 iterations per interval."""
+    from paper_2608_22190_amd import hpsmc, workloads as W
+    stream = torch.cuda.Stream()
+
+    def solve_err(wl, exact):
+        with hpsmc.Plan(wl) as plan:
+            if args.tune_cache:
+                plan.hpsmc_tune(0, min(wl.M, 1024), args.tune_cache, stream=stream)
+            t0 = time.perf_counter()
+            plan.hpsmc_solve(stream=stream)
+            stream.synchronize()
+            sec = time.perf_counter() - t0
+            err = 0.0
+            for iv in range(wl.n_intervals):
+                x, t = plan.hpsmc_grid(iv)
+                err = max(err, float(np.max(np.abs(plan.hpsmc_get_nodes(iv)[0] - exact(x, t)))))
+        return err, sec
+
+    a = wl_alpha = 0.4
+    ex2 = lambda x, t: ((1 - x ** 2) ** (a / 2) * np.sin(x))[:, None] * (np.exp(np.cos(t)) / (1 + t ** 2))[None, :]
+    ex3 = lambda x, t: ((1 - x ** 2) ** (a / 2) * np.cos(x ** 3 + 1) / (10 * x ** 2 + 1))[:, None] * (t ** 0.51)[None, :]
+    res = {"ex2_step_size": {}, "ex3_geometric": {}, "ex3_uniform": {}}
+    total = 0.0
+    for h in (1.0, 0.5, 0.2, 0.1):
+        wl = W.frac_long_time(iters=10, n_intervals=int(round(25 / h)), h=h, alpha=wl_alpha)
+        e, sec = solve_err(wl, ex2)
+        total += sec
+        res["ex2_step_size"][str(h)] = e
+        print(f"[bench] fracexp Ex.2 h={h}: max error {e:.3e} ({sec:.1f}s)", file=sys.stderr, flush=True)
+    for N in range(2, 9):
+        wg = W.frac_singular(iters=12, N=N, T=0.5, alpha=wl_alpha, rho=0.51)
+        eg, sec = solve_err(wg, ex3)
+        total += sec
+        tb = [0.5 * k / N for k in range(N + 1)]
+        wu = W._mk("frac_singular_uniform", 1, 11, tb, [max(wg.degree)] * N, f="u_minus_u3", src="frac_singular",
+                   src_param=[0.51, 0, 0, 0, 0, 0, 0, 0], ic="exact", M=8192, iters=12, seed=0, precision="fp64",
+                   alpha=wl_alpha)
+        eu, sec = solve_err(wu, ex3)
+        total += sec
+        res["ex3_geometric"][str(N)] = eg
+        res["ex3_uniform"][str(N)] = eu
+        print(f"[bench] fracexp Ex.3 N={N}: geometric {eg:.3e}, uniform {eu:.3e}", file=sys.stderr, flush=True)
+    line = {"metric": METRIC, "value": None, "unit": "node-samples/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": 1e3 * total, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "accuracy studies of the fractional examples (Ex. 2 step sizes to T = 25, Ex. 3 "
+                                   "geometric against uniform meshes), FP64, M = 8192"},
+            "results": res}
+    print(json.dumps(line), flush=True)
+
+
 def run_ballcmp(args, torch):
     """Centre-point (eq. interIQ) against ball-point path quadrature on the
     single-step problem (1-D, u = e^{-t} sin(pi x), 16 x 16 nodes, M = 4096,
@@ -485,7 +545,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c2b", "c3", "c4", "c5", "compare", "aitken",
-                                                              "ballcmp", "frac", "fraccmp"])
+                                                              "ballcmp", "frac", "fraccmp", "fracexp"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--launch", type=str, default="",
