@@ -140,6 +140,8 @@ def run_other(name, args, torch):
         return run_fraccmp(args, torch)
     if name == "fracexp":
         return run_fracexp(args, torch)
+    if name == "ex1":
+        return run_ex1(args, torch)
     if name == "c1":
         wl = W.c1_single_step()
     elif name == "c2p":
@@ -375,6 +377,44 @@ def run_fraccmp(args, torch):
     print(json.dumps(line), flush=True)
 
 
+def run_ex1(args, torch):
+    """Ex. 1's convergence studies on the GPU (FP64, one interval [0, 0.5], f = u sin u,
+    exact solution e^{-t} sin(pi x)): (a) error against n (spatial nodes) with
+    M_1 = 6; (b) against M_1 with n = 19; both with M = 4096 and 30 iterations;
+    (c) error after K = 1..30 iterations for M = 100, 1000, 10000 (n = 11, M_1 = 6)."""
+    from paper_2608_22190_amd import hpsmc, workloads as W
+    stream = torch.cuda.Stream()
+
+    def run(n, deg, M, iters):
+        wl = W._mk("ex1", 1, n, [0.0, 0.5], [deg], f="u_sin_u", src="sin_decay", ic="exact", M=M, iters=iters,
+                   seed=0, precision="fp64")
+        with hpsmc.Plan(wl) as plan:
+            plan.hpsmc_solve(stream=stream)
+            stream.synchronize()
+            x, t = plan.hpsmc_grid(0)
+            ex = np.sin(np.pi * x)[:, None] * np.exp(-t)[None, :]
+            return float(np.max(np.abs(plan.hpsmc_get_nodes(0)[0] - ex)))
+
+    t0 = time.perf_counter()
+    res = {"error_vs_n": {}, "error_vs_M1": {}, "error_vs_K": {}}
+    for n in (4, 6, 8, 10, 12, 14, 16, 19):
+        res["error_vs_n"][str(n)] = run(n, 6, 4096, 30)
+    for deg in (2, 3, 4, 5, 6, 8, 10):
+        res["error_vs_M1"][str(deg)] = run(19, deg, 4096, 30)
+    for M in (100, 1000, 10000):
+        res["error_vs_K"][str(M)] = [run(11, 6, M, K) for K in (1, 2, 4, 8, 12, 16, 20, 30)]
+    sec = time.perf_counter() - t0
+    for k, v in res.items():
+        print(f"[bench] ex1 {k}: {v}", file=sys.stderr, flush=True)
+    line = {"metric": METRIC, "value": None, "unit": "node-samples/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+            "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "convergence studies of Ex. 1 (1-D, one interval, f = u sin u): error against n, "
+                                   "against the temporal degree, and against the iteration count for several M"},
+            "results": res}
+    print(json.dumps(line), flush=True)
+
+
 def run_fracexp(args, torch):
     """Accuracy studies of the fractional examples, FP64, M = 8192:
     (a) Ex. 2 to T = 25 with step sizes h = 1, 0.5, 0.2, 0.1 (M_n = 6, 11
@@ -545,7 +585,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c2b", "c3", "c4", "c5", "compare", "aitken",
-                                                              "ballcmp", "frac", "fraccmp", "fracexp"])
+                                                              "ballcmp", "frac", "fraccmp", "fracexp", "ex1"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--launch", type=str, default="",
