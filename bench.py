@@ -639,7 +639,7 @@ def main():
         "roofline": {"bound": "mfma" if r32["mma"] else "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": measured_traffic(r32["launch"]),
-                     "kernel": (f"advance_mma_kernel<{(P + 1) // 2}> (v_mfma_f32_32x32x2f32)"
+                     "kernel": (f"advance_mma_kernel<{(P + 1) // 2},0> (v_mfma_f32_32x32x2f32)"
                                 if r32["mma"] else "advance_kernel<float,2,28,NS,0,0> (vector units)"),
                      "flops_per_eval": fpe,
                      "evals_per_launch": evals_per_launch, "avg_launch_ms": k_ms,
