@@ -698,60 +698,81 @@ hipError_t launch_mode_product(const double *in, double *out, int64_t outer, int
 // ---------------------------------------------------------------------------
 // Slabs: for group g = (inst, iv, l) and step q < N*, the spatial coefficient
 // rows of u* and v* at the reference time xi = 2 (span - q Delta)/h - 1.
+// A block takes kSlabQ consecutive steps of one group: the Legendre values
+// L_k(xi_q) of its steps go to LDS once, and every entry's T1 time
+// coefficients are loaded once into registers and contracted with each step's
+// values (the same products in the same order as entry by entry).
 // ---------------------------------------------------------------------------
+constexpr int kSlabQ = 32;
+
 template <typename T>
-__global__ void slab_kernel(SlabArgs a)
+__global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
 {
+    __shared__ double Lq[kSlabQ][kMaxDeg + 2];
     const int g = blockIdx.y;
-    const int nstar = a.nstar[g];
+    const int nq = a.nstar[g] + a.extra;
     const int T1 = a.deg[g] + 1;
     const bool mma = a.layout == 1;
     const int64_t stride = mma ? a.mma_stride : a.slab_stride;
     const int64_t base = mma ? a.slab_off_mma[g] : a.slab_off[g];
-    const int64_t total = (int64_t)(nstar + a.extra) * stride;
     T *table = (T *)a.slab_table;
     const double *cu = a.cu + a.coef_off[g], *cv = a.cv + a.coef_off[g];
     const double span = a.span[g], delta = a.delta[g], h2 = a.h2[g];
-    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = idx / stride;
-        const int64_t e = idx - q * stride;
-        int64_t row;
-        int uv, kl;
-        if (mma) {   // column c = uv * PP + k1 of kMmaRows rows k0
-            const int c = (int)(e / kMmaRows);
-            row = e - (int64_t)c * kMmaRows;
-            uv = c / a.PP;
-            kl = c - uv * a.PP;
-        } else {
-            row = e / (2 * a.PP);
-            const int rem = (int)(e - row * 2 * a.PP);
-            uv = rem / a.PP;
-            kl = rem - uv * a.PP;
-        }
-        double val = 0.0;
-        if (kl < a.P && row < a.rows) {
-            const double *c = (uv ? cv : cu) + (row * a.P + kl) * T1;
-            const double xi = h2 * (span - (double)q * delta) - 1.0;
+    for (int q0 = blockIdx.x * kSlabQ; q0 < nq; q0 += gridDim.x * kSlabQ) {
+        const int qn = min(kSlabQ, nq - q0);
+        __syncthreads();   // the previous chunk's reads of Lq are over
+        if ((int)threadIdx.x < qn) {
+            const double xi = h2 * (span - (double)(q0 + (int)threadIdx.x) * delta) - 1.0;
             double lp = 0.0, lc = 1.0;
             for (int k = 0; k < T1; ++k) {
-                val = fma(c[k], lc, val);
+                Lq[threadIdx.x][k] = lc;
                 const double nx = c_rec.ad[k] * xi * lc - c_rec.bd[k] * lp;
                 lp = lc;
                 lc = nx;
             }
         }
-        if (mma) val *= c_rec.mu[kl] * c_rec.mu[row];   // coefficients of Q_{k0}(x0) Q_{k1}(x1)
-        table[base + q * stride + e] = (T)val;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) {
+            int64_t row;
+            int uv, kl;
+            if (mma) {   // column c = uv * PP + k1 of kMmaRows rows k0
+                const int c = (int)(e / kMmaRows);
+                row = e - (int64_t)c * kMmaRows;
+                uv = c / a.PP;
+                kl = c - uv * a.PP;
+            } else {
+                row = e / (2 * a.PP);
+                const int rem = (int)(e - row * 2 * a.PP);
+                uv = rem / a.PP;
+                kl = rem - uv * a.PP;
+            }
+            const bool live = kl < a.P && row < a.rows;
+            double c[kMaxDeg + 1];
+            if (live) {
+                const double *cp = (uv ? cv : cu) + (row * a.P + kl) * T1;
+#pragma unroll
+                for (int k = 0; k <= kMaxDeg; ++k) c[k] = k < T1 ? cp[k] : 0.0;
+            }
+            const double sc = mma && live ? c_rec.mu[kl] * c_rec.mu[row] : 1.0;   // coefficients of Q_{k0} Q_{k1}
+            for (int j = 0; j < qn; ++j) {
+                double val = 0.0;
+                if (live) {
+#pragma unroll
+                    for (int k = 0; k <= kMaxDeg; ++k)
+                        if (k < T1) val = fma(c[k], Lq[j][k], val);
+                }
+                if (mma) val *= sc;
+                table[base + (int64_t)(q0 + j) * stride + e] = (T)val;
+            }
+        }
     }
 }
 
 hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t s)
 {
     if (a.n_groups <= 0) return hipSuccess;
-    int64_t per = (int64_t)(max_nstar + a.extra) * (a.layout == 1 ? a.mma_stride : a.slab_stride);
-    int64_t bx = (per + 255) / 256;
-    if (bx > 16384) bx = 16384;
+    int64_t bx = (max_nstar + a.extra + kSlabQ - 1) / kSlabQ;
+    if (bx > 65535) bx = 65535;
     dim3 grid((unsigned)bx, (unsigned)a.n_groups);
     if (fp32)
         hipLaunchKernelGGL(slab_kernel<float>, grid, dim3(256), 0, s, a);
