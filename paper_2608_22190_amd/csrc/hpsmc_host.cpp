@@ -1978,8 +1978,10 @@ hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t 
 static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hipStream_t s)
 {
     const int G = (int)set.ghost.size();
-    // the matrix-core form sums four waves' outer products in LDS before its
-    // atomics into the slab-adjoint table; the vector form sums one wave's
+    // the matrix-core form needs four waves: each forms one of the two weighted
+    // tables over half of the block's samples, and the halves meet in LDS
+    // before the atomics into the slab-adjoint table; the vector form sums one
+    // wave's
     const int mfma = plan->fp32 && plan->adj_use_mfma;
     const int waves = mfma ? 4 : 1;
     const int nthr = 64 * waves;

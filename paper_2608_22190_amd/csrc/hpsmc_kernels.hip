@@ -2238,7 +2238,7 @@ size_t adjoint_lds_bytes(int fp32, int mfma, int dim, int P, int nthr, int64_t s
     const size_t T = fp32 ? 4 : 8;
     const int64_t nvec = slab_stride * (int64_t)T / 16;
     const size_t slab = (size_t)2 * ((nvec + 1) & ~1LL) * 16;
-    if (mfma) return slab + (size_t)nthr * (2 * P + 2) * 4 + 2 * 32 * 32 * 4;
+    if (mfma) return slab + (size_t)nthr * (2 * (P | 1) + 2) * 4 + 2 * 32 * 32 * 4;
     const int R = dim == 1 ? 1 : P;
     const int RS = (std::max(R, P) + 3) & ~3;
     return slab + (size_t)nthr * 3 * RS * T;
@@ -2255,15 +2255,17 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
     const int P = a.P, PP = a.PP;
     const int R = D == 1 ? 1 : P;
     // vector path: weighted rows Au, Av and columns Bm per sample (stride RS);
-    // matrix-core path: basis rows Am and columns Bm (stride P) and the two
-    // weights Wm per sample, the products' block sum gsum [2][32][32]
+    // matrix-core path: basis rows Am and columns Bm (odd stride PS, so that a
+    // wave's row writes fall in distinct banks) and the two
+    // weights Wm per sample, the upper half's tiles gsum [2][16][64]
     const int RS = MFMA ? P : (((R > P ? R : P) + 3) & ~3);
     T *Au = (T *)(lds + 2 * svec);
     T *Av = Au + (int64_t)nthr * RS;
     T *Bm = Av + (int64_t)nthr * RS;
+    const int PS = P | 1;
     float *Am = (float *)(lds + 2 * svec);
-    float *Bmm = Am + (int64_t)nthr * P;
-    float *Wm = Bmm + (int64_t)nthr * P;
+    float *Bmm = Am + (int64_t)nthr * PS;
+    float *Wm = Bmm + (int64_t)nthr * PS;
     float *gsum = MFMA ? Wm + 2 * (int64_t)nthr : nullptr;
     __shared__ long long s_item;
     cptr<GroupDesc> groups = as_const(a.groups);
@@ -2274,9 +2276,6 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
     State *sout = (State *)a.state_out;
     T *sbar = (T *)aa.slab_bar;
     const int E = 2 * R * P;
-    if constexpr (MFMA) {
-        for (int e = tid; e < 2 * 32 * 32; e += nthr) gsum[e] = 0.f;
-    }
 
     for (;;) {
         __syncthreads();
@@ -2395,7 +2394,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
             }
             // ---- outer-product factors of this sample: rows L(X_0) weighted, columns L(X_{d-1})
             if constexpr (MFMA) {
-                float *am = Am + (int64_t)tid * P, *bm = Bmm + (int64_t)tid * P;
+                float *am = Am + (int64_t)tid * PS, *bm = Bmm + (int64_t)tid * PS;
                 Wm[2 * tid] = wu;
                 Wm[2 * tid + 1] = wv;
                 if constexpr (D == 1) {
@@ -2450,33 +2449,34 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
             // ---- block sum of the outer products into the slab adjoint of step q
             T *dstq = gbar + (int64_t)q * a.slab_stride;
             if constexpr (MFMA) {
-                // K = the wave's 64 samples, two per product; the four waves meet in gsum
-                f32x16 cu = {}, cv = {};
-                const int i = lane & 31;
+                // wave w forms tile w & 1 (0: the f'(u)-weighted table, 1: the
+                // plain one) over half w >> 1 of the block's samples, two samples
+                // per product; the upper half hands its tile to the lower one
+                // through LDS with plain stores, which then adds into the table
+                const int tile = wave & 1, half = wave >> 1, i = lane & 31;
                 const bool row = i < P;
+                constexpr int hs = 128;   // the matrix-core form runs four waves per block
+                f32x16 c = {};
 #pragma unroll 4
-                for (int kk = 0; kk < 32; ++kk) {
-                    const int sidx = wave * 64 + 2 * kk + (lane >> 5);
-                    const float am = row ? Am[sidx * P + i] : 0.f, bb = row ? Bmm[sidx * P + i] : 0.f;
-                    cu = __builtin_amdgcn_mfma_f32_32x32x2f32(Wm[2 * sidx] * am, bb, cu, 0, 0, 0);
-                    cv = __builtin_amdgcn_mfma_f32_32x32x2f32(Wm[2 * sidx + 1] * am, bb, cv, 0, 0, 0);
+                for (int kk = 0; kk < hs / 2; ++kk) {
+                    const int sidx = half * hs + 2 * kk + (lane >> 5);
+                    const float am = row ? Am[sidx * PS + i] : 0.f, bb = row ? Bmm[sidx * PS + i] : 0.f;
+                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(Wm[2 * sidx + tile] * am, bb, c, 0, 0, 0);
                 }
-                const int j = lane & 31;
+                float *cm = gsum + tile * 16 * 64 + lane;
+                if (half == 1) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int ii = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (ii < R && j < P) {
-                        atomicAdd(&gsum[ii * 32 + j], cu[r]);
-                        atomicAdd(&gsum[1024 + ii * 32 + j], cv[r]);
-                    }
+                    for (int r = 0; r < 16; ++r) cm[r * 64] = c[r];
                 }
                 __syncthreads();
-                for (int e = tid; e < E; e += nthr) {
-                    const int uv = e / (R * P), rem = e - uv * R * P, ii = rem / P, jj = rem - ii * P;
-                    float *gp = gsum + uv * 1024 + ii * 32 + jj;
-                    const float val = *gp;
-                    *gp = 0.f;
-                    if (val != 0.f) atomicAdd(dstq + (int64_t)ii * 2 * PP + uv * PP + jj, (T)val);
+                if (half == 0) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int ii = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        const float val = c[r] + cm[r * 64];
+                        if (ii < R && i < P && val != 0.f)
+                            atomicAdd(dstq + (int64_t)ii * 2 * PP + tile * PP + i, (T)val);
+                    }
                 }
             } else {
                 for (int e = tid; e < E; e += nthr) {

@@ -67,10 +67,11 @@ def test_gradient_matches_central_differences_fp64():
             assert np.max(np.abs(fd - grad[:, k]) / (1 + np.abs(grad[:, k]))) <= 1e-6, (k, fd, grad[:, k])
 
 
-def test_fp32_mfma_and_vector_outer_products_agree():
+@pytest.mark.parametrize("dim,n", [(1, 9), (2, 6), (2, 7)])
+def test_fp32_mfma_and_vector_outer_products_agree(dim, n):
     H = _hp()
-    wl, c0, target = _problem(dim=2, n=6, deg=3, M=96, precision="fp32", I=3)
-    _say("mfma vs valu")
+    wl, c0, target = _problem(dim=dim, n=n, deg=3, M=96, precision="fp32", I=3)
+    _say("mfma vs valu", dim, n)
     res = {}
     for mf in (1, 0):
         with H.Plan(wl) as plan:
