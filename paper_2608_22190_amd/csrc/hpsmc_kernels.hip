@@ -2468,7 +2468,10 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) cm[r * 64] = c[r];
                 }
-                __syncthreads();
+                // past this barrier no wave reads this step's factors again, and
+                // the upper half writes its next tile only after the next step's
+                // first barrier: it also closes the step
+                const int any_alive = __syncthreads_or(alive ? 1 : 0);
                 if (half == 0) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
@@ -2478,6 +2481,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
                             atomicAdd(dstq + (int64_t)ii * 2 * PP + tile * PP + i, (T)val);
                     }
                 }
+                if (any_alive == 0) break;
             } else {
                 for (int e = tid; e < E; e += nthr) {
                     const int uv = e / (R * P), rem = e - uv * R * P, ii = rem / P, jj = rem - ii * P;
@@ -2486,8 +2490,8 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
                     for (int sidx = 0; sidx < nthr; ++sidx) sum = m_fma(A[sidx * RS + ii], Bm[sidx * RS + jj], sum);
                     if (sum != (T)0) atomicAdd(dstq + (int64_t)ii * 2 * PP + uv * PP + jj, sum);
                 }
+                if (__syncthreads_or(alive ? 1 : 0) == 0) break;
             }
-            if (__syncthreads_or(alive ? 1 : 0) == 0) break;
         }
         // survivors to the next round
         {
