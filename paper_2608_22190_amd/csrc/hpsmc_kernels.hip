@@ -161,16 +161,37 @@ __device__ __forceinline__ void ball_offset(uint32_t c0, uint32_t c1, int q, uin
 // ---------------------------------------------------------------------------
 // Problem terms.
 // ---------------------------------------------------------------------------
+// sin(u) for the nonlinearity: FP32 arguments with |u| <= 2 take the sine's
+// Maclaurin series to u^17/17! (truncation below 4e-10 there, no range
+// reduction); larger ones and FP64 the library sine
+__device__ __forceinline__ double sin_of_u(double u) { return sin(u); }
+__device__ __forceinline__ float sin_of_u(float u)
+{
+    if (fabsf(u) <= 2.f) {
+        const float z = u * u;
+        float p = (float)(1.0 / 355687428096000.0);         // +1/17!
+        p = fmaf(p, z, (float)(-1.0 / 1307674368000.0));   // -1/15!
+        p = fmaf(p, z, (float)(1.0 / 6227020800.0));       // +1/13!
+        p = fmaf(p, z, (float)(-1.0 / 39916800.0));        // -1/11!
+        p = fmaf(p, z, (float)(1.0 / 362880.0));           // +1/9!
+        p = fmaf(p, z, (float)(-1.0 / 5040.0));            // -1/7!
+        p = fmaf(p, z, (float)(1.0 / 120.0));              // +1/5!
+        p = fmaf(p, z, (float)(-1.0 / 6.0));               // -1/3!
+        return fmaf(p * z, u, u);
+    }
+    return sinf(u);
+}
+
 template <typename T>
 __device__ __forceinline__ T f_of(const Physics &ph, T u)
 {
     switch (ph.f_kind) {
     case 0: return (T)ph.f_param[0] * u + (T)ph.f_param[1];
     case 1: return u - u * u * u;
-    case 2: return m_sin(u);
+    case 2: return sin_of_u(u);
     case 3: return u * u / ((T)1 + u * u);
     case 4: return -u * u * u;
-    case 5: return u * m_sin(u);
+    case 5: return u * sin_of_u(u);
     }
     return (T)0;
 }
