@@ -2585,6 +2585,7 @@ __global__ void slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t
     const T *tab = (const T *)a.slab_table;
     double accq[kMaxDeg + 1];
     const int T1 = a.deg[inst * groups_per_inst] + 1;
+#pragma unroll
     for (int m = 0; m <= kMaxDeg; ++m) accq[m] = 0.0;
     for (int gl = 0; gl < groups_per_inst; ++gl) {
         const int g = inst * groups_per_inst + gl;
@@ -2596,16 +2597,22 @@ __global__ void slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t
             if (val == 0.0) continue;
             const double xi = h2 * (span - (double)q * delta) - 1.0;
             double lp = 0.0, lc = 1.0;
-            for (int m = 0; m < T1; ++m) {
-                accq[m] = fma(val, lc, accq[m]);
-                const double nx = c_rec.ad[m] * xi * lc - c_rec.bd[m] * lp;
-                lp = lc;
-                lc = nx;
+            // fully unrolled with a guard so that accq stays in registers
+#pragma unroll
+            for (int m = 0; m <= kMaxDeg; ++m) {
+                if (m < T1) {
+                    accq[m] = fma(val, lc, accq[m]);
+                    const double nx = c_rec.ad[m] * xi * lc - c_rec.bd[m] * lp;
+                    lp = lc;
+                    lc = nx;
+                }
             }
         }
     }
     double *out = (uv ? cbar_v : cbar_u) + (int64_t)inst * coef_inst_stride + k * T1;
-    for (int m = 0; m < T1; ++m) out[m] = accq[m];
+#pragma unroll
+    for (int m = 0; m <= kMaxDeg; ++m)
+        if (m < T1) out[m] = accq[m];
 }
 
 hipError_t launch_slab_adjoint(const SlabArgs &a, int32_t groups_per_inst, int32_t n_inst, int fp32, double *cbar_u,
