@@ -2474,14 +2474,16 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
                 // plain one) over half w >> 1 of the block's samples, two samples
                 // per product; the upper half hands its tile to the lower one
                 // through LDS with plain stores, which then adds into the table
+                // operand rows and columns i >= P read the next sample's factors
+                // (inside the LDS block): they only reach output rows or columns
+                // >= P, which are not written out
                 const int tile = wave & 1, half = wave >> 1, i = lane & 31;
-                const bool row = i < P;
                 constexpr int hs = 128;   // the matrix-core form runs four waves per block
                 f32x16 c = {};
 #pragma unroll 4
                 for (int kk = 0; kk < hs / 2; ++kk) {
                     const int sidx = half * hs + 2 * kk + (lane >> 5);
-                    const float am = row ? Am[sidx * PS + i] : 0.f, bb = row ? Bmm[sidx * PS + i] : 0.f;
+                    const float am = Am[sidx * PS + i], bb = Bmm[sidx * PS + i];
                     c = __builtin_amdgcn_mfma_f32_32x32x2f32(Wm[2 * sidx + tile] * am, bb, c, 0, 0, 0);
                 }
                 float *cm = gsum + tile * 16 * 64 + lane;
