@@ -810,6 +810,17 @@ static void or_stream_init(or_stream *st, uint64_t seed, int64_t node, int64_t s
     st->blk = -1;
 }
 
+/* The directions a walk draws, step by step, exactly as or_path draws them. */
+int or_walk_directions(int dim, uint64_t seed, int64_t node, int64_t sample, int inst,
+                       int interval, int iter_tag, int64_t q0, int64_t nq, double *out)
+{
+    if (dim < 1 || dim > OR_MAXD || q0 < 0 || nq < 0) return -1;
+    or_stream st;
+    or_stream_init(&st, seed, node, sample, inst, interval, iter_tag);
+    for (int64_t k = 0; k < nq; ++k) or_direction(&st, dim, q0 + k, out + k * dim);
+    return 0;
+}
+
 /* node geometry: the spatial point and (ell, span, N*) of a node id */
 typedef struct { double X[OR_MAXD]; int ell; int nstar; double span; double delta; } or_node;
 

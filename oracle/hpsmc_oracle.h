@@ -202,6 +202,12 @@ int or_loss_grad(const or_problem *pb, int inst, const double *c0,
 double or_exit_fraction(int dim, double T, int nstar, const double *starts,
                         int64_t nwalk, uint64_t seed);
 
+/* Unit jump directions of one walk (Lemma 2.1, reading R9, counter layout
+ * R22): the walk of sample `sample` from node id `node` of (inst, interval,
+ * iter_tag) under `seed`, steps q0 .. q0+nq-1, written to out[nq][dim]. */
+int or_walk_directions(int dim, uint64_t seed, int64_t node, int64_t sample, int inst,
+                       int interval, int iter_tag, int64_t q0, int64_t nq, double *out);
+
 int or_num_threads(void);
 
 #ifdef __cplusplus

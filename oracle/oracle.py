@@ -80,6 +80,8 @@ def lib():
             "or_loss_grad": (C.c_int, [pp, C.c_int, p, p, p, p]),
             "or_exit_fraction": (d, [C.c_int, d, C.c_int, p, i64, C.c_uint64]),
             "or_num_threads": (C.c_int, []),
+            "or_walk_directions": (C.c_int, [C.c_int, C.c_uint64, i64, i64, C.c_int, C.c_int, C.c_int,
+                                             i64, i64, p]),
             "or_gauss_jacobi": (C.c_int, [C.c_int, d, p, p]), "or_jacobi_aa": (d, [C.c_int, d, d]),
             "or_frac_lambda": (d, [C.c_int, d]), "or_ibeta": (d, [d, d, d]), "or_ibeta_inv": (d, [d, d, d]),
             "or_frac_jump": (d, [d, d, d]),
@@ -190,6 +192,14 @@ def frac_evaluate(alpha, n, M, h, Ut, x, xi):
 def exit_fraction(dim, T, nstar, starts, seed=0):
     starts = np.ascontiguousarray(starts, dtype=np.float64)
     return lib().or_exit_fraction(dim, float(T), int(nstar), _ptr(starts), starts.shape[0], seed)
+
+
+def walk_directions(dim, seed, node, sample, q0, nq, inst=0, interval=0, iter_tag=0):
+    """Jump directions of one walk, steps q0..q0+nq-1, as [nq][dim]."""
+    out = np.zeros((int(nq), int(dim)))
+    _check(lib().or_walk_directions(int(dim), int(seed), int(node), int(sample), int(inst), int(interval),
+                                    int(iter_tag), int(q0), int(nq), _ptr(out)), "walk_directions")
+    return out
 
 
 def num_threads():
