@@ -494,6 +494,9 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     if (pb->schedule < 0 || pb->schedule > 1) return fail(HPSMC_EINVAL, "unknown schedule");
     if (pb->precision < 0 || pb->precision > 1) return fail(HPSMC_EINVAL, "unknown precision");
     if (!std::isfinite(pb->tol) || pb->tol < 0.0) return fail(HPSMC_EINVAL, "tol must be finite and >= 0");
+    if (pb->tol > 0.0 && pb->schedule == HPSMC_SEQUENTIAL && (int64_t)pb->n_intervals * pb->iters > 4096)
+        return fail(HPSMC_EINVAL, "tolerance mode keeps one max|eps| record per (interval, iteration): "
+                                  "n_intervals * iters must be <= 4096");
     if (pb->estimator < 0 || pb->estimator > 1) return fail(HPSMC_EINVAL, "unknown estimator");
     if (pb->accel < 0 || pb->accel > 1) return fail(HPSMC_EINVAL, "unknown accel");
     if (pb->quad < 0 || pb->quad > 1) return fail(HPSMC_EINVAL, "unknown quad");
@@ -642,8 +645,10 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
             gd.c3 = set.host[g * per].c3;
             set.ghost.push_back(gd);
         }
-    } else {
-        // longest expected paths first (stable for determinism)
+    } else if (plan->pb.accel != HPSMC_ACCEL_AITKEN) {
+        // longest expected paths first (stable for determinism); the Aitken
+        // update reads its vectors as contiguous ranges of the generation order,
+        // so relaxed plans keep that order
         std::stable_sort(set.host.begin(), set.host.end(), [d](const NodeDesc &a, const NodeDesc &b) {
             return expected_cost(a, d) > expected_cost(b, d);
         });
@@ -1385,6 +1390,11 @@ static hpsmc_status solve_body(hpsmc_plan *plan, hipStream_t s)
     const int K = plan->pb.iters;
     const double tol = plan->pb.tol;
     bool unconverged = false;
+    // the records this solve writes start from zero (their maxima are taken with
+    // atomics); a fill kernel rather than a memset, so a captured solve replays it
+    const int64_t n_rec = std::min<int64_t>(4096, plan->pb.schedule == HPSMC_SEQUENTIAL
+                                                       ? (int64_t)plan->n_iv * K : (int64_t)K);
+    HIP_TRY(launch_fill_u64(plan->maxbits, n_rec, 0ull, s));
     if (plan->pb.schedule == HPSMC_SEQUENTIAL) {
         for (int iv = 0; iv < plan->n_iv; ++iv) {
             if ((st = start_interval(plan, iv, 1, s))) return st;

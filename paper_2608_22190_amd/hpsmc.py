@@ -137,6 +137,25 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def _is_device(a):
+    return a is not None and hasattr(a, "data_ptr")
+
+
+def _device_f64(t, count, what):
+    """Check that a torch tensor handed over as a device buffer is a contiguous
+    float64 GPU tensor of `count` elements (the library copies count * 8 bytes)."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{what}: expected a GPU tensor (a host array is passed as a NumPy array)")
+    import torch
+    if t.dtype != torch.float64:
+        raise ValueError(f"{what}: expected float64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous tensor")
+    if t.numel() != count:
+        raise ValueError(f"{what}: expected {count} elements, got {t.numel()}")
+    return t
+
+
 def make_problem(wl):
     """hpsmc_problem from a workload description; returns (struct, keep-alive list)."""
     tb = np.ascontiguousarray(wl.t_breaks, dtype=np.float64)
@@ -263,26 +282,34 @@ class Plan:
         return (self.wl.n_instances, self.nsp, self.wl.degree[iv] + 1)
 
     def hpsmc_get_nodes(self, iv, out=None, stream=None):
-        on_dev = out is not None and hasattr(out, "data_ptr")
+        on_dev = _is_device(out)
+        if on_dev:
+            _device_f64(out, int(np.prod(self._nodes_shape(iv))), "hpsmc_get_nodes out")
         if out is None:
             out = np.zeros(self._nodes_shape(iv))
         _check(lib().hpsmc_get_nodes(self.h, iv, _ptr(out), int(on_dev), _stream(stream)), "hpsmc_get_nodes")
         return out
 
     def hpsmc_set_nodes(self, iv, values, stream=None):
-        on_dev = hasattr(values, "data_ptr")
-        if not on_dev:
+        on_dev = _is_device(values)
+        if on_dev:
+            _device_f64(values, int(np.prod(self._nodes_shape(iv))), "hpsmc_set_nodes values")
+        else:
             values = np.ascontiguousarray(values, dtype=np.float64).reshape(self._nodes_shape(iv))
         _check(lib().hpsmc_set_nodes(self.h, iv, _ptr(values), int(on_dev), _stream(stream)), "hpsmc_set_nodes")
 
     def hpsmc_set_initial_nodes(self, u0, stream=None):
-        on_dev = hasattr(u0, "data_ptr")
-        if not on_dev:
+        on_dev = _is_device(u0)
+        if on_dev:
+            _device_f64(u0, self.wl.n_instances * self.nsp, "hpsmc_set_initial_nodes u0")
+        else:
             u0 = np.ascontiguousarray(u0, dtype=np.float64).reshape(self.wl.n_instances, self.nsp)
         _check(lib().hpsmc_set_initial_nodes(self.h, _ptr(u0), int(on_dev), _stream(stream)), "hpsmc_set_initial_nodes")
 
     def hpsmc_get_coeffs(self, iv, out=None, stream=None):
-        on_dev = out is not None and hasattr(out, "data_ptr")
+        on_dev = _is_device(out)
+        if on_dev:
+            _device_f64(out, int(np.prod(self._nodes_shape(iv))), "hpsmc_get_coeffs out")
         if out is None:
             out = np.zeros(self._nodes_shape(iv))
         _check(lib().hpsmc_get_coeffs(self.h, iv, _ptr(out), int(on_dev), _stream(stream)), "hpsmc_get_coeffs")
@@ -349,16 +376,19 @@ class Plan:
 
     # -- gradient
     def hpsmc_set_initial_coeffs(self, c0, stream=None):
-        on_dev = hasattr(c0, "data_ptr")
-        if not on_dev:
+        on_dev = _is_device(c0)
+        if on_dev:
+            _device_f64(c0, self.wl.n_instances * self.nsp, "hpsmc_set_initial_coeffs c0")
+        else:
             c0 = np.ascontiguousarray(c0, dtype=np.float64).reshape(self.wl.n_instances, self.nsp)
         _check(lib().hpsmc_set_initial_coeffs(self.h, _ptr(c0), int(on_dev), _stream(stream)),
                "hpsmc_set_initial_coeffs")
 
     def hpsmc_loss_grad_c0(self, target, stream=None):
-        on_dev = hasattr(target, "data_ptr")
+        on_dev = _is_device(target)
         I = self.wl.n_instances
         if on_dev:
+            _device_f64(target, I * self.nsp, "hpsmc_loss_grad_c0 target")
             import torch
             loss = torch.zeros(I, dtype=torch.float64, device=target.device)
             grad = torch.zeros((I, self.nsp), dtype=torch.float64, device=target.device)
@@ -380,9 +410,11 @@ def smc_loss_function():
     class SMCLoss(torch.autograd.Function):
         @staticmethod
         def forward(ctx, c0, plan, target, stream=None):
-            c0 = c0.detach().contiguous()
+            # the library reads float64 device buffers; other dtypes are converted
+            c0 = c0.detach().to(torch.float64).contiguous()
             plan.hpsmc_set_initial_coeffs(c0, stream=stream)
-            loss, grad = plan.hpsmc_loss_grad_c0(target.detach().contiguous(), stream=stream)
+            loss, grad = plan.hpsmc_loss_grad_c0(target.detach().to(c0.device, torch.float64).contiguous(),
+                                                 stream=stream)
             ctx.save_for_backward(grad)
             return loss
 
