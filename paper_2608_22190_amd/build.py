@@ -3,19 +3,23 @@
     python -m paper_2608_22190_amd.build
 
 Packed FP32 instructions are disabled (-packed-fp32-ops) for every HIP
-translation unit.
+translation unit.  The units compile in parallel (one process each, at most
+one per CPU and at most 16).
 """
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhpsmc.so")
-SOURCES = ["hpsmc_kernels.hip", "hpsmc_host.cpp"]
+SOURCES = ["hpsmc_kern_valu_f32.hip", "hpsmc_kern_valu_f64.hip", "hpsmc_kern_mma.hip", "hpsmc_kern_adjoint.hip",
+           "hpsmc_kern_frac.hip", "hpsmc_kernels.hip", "hpsmc_host.cpp"]
+HEADERS = ["hpsmc_internal.h", "hpsmc_device.h", "hpsmc_round.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -25,21 +29,27 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
 def build(verbose: bool = False, incremental: bool = False) -> str:
     """Compile every source (incremental=True skips objects newer than their
     source and the shared headers)."""
-    objs = []
-    headers = [os.path.join(CSRC, "hpsmc_internal.h"), os.path.join(ROOT, "include", "hpsmc.h")]
+    headers = [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(ROOT, "include", "hpsmc.h")]
+    jobs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, "_build", src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
+        objs.append(obj)
         deps = [os.path.join(CSRC, src)] + headers
         if incremental and os.path.exists(obj) and all(os.path.getmtime(obj) > os.path.getmtime(d) for d in deps):
-            objs.append(obj)
             continue
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+        jobs.append([HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+
+    def run(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        for f in [ex.submit(run, c) for c in jobs]:
+            f.result()
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)

@@ -1,0 +1,338 @@
+// Adjoint of the residual estimator (gradient with respect to the initial data).
+#include "hpsmc_device.h"
+
+namespace hpsmc {
+
+hipError_t set_rec_tables_adjoint() { return upload_recurrence_tables(); }
+
+// ===========================================================================
+// Adjoint of the residual estimator under common random numbers.
+//
+// For iteration k the estimator is eps_node = (1/M) sum_paths sum_{q<L}
+// Delta r(X_q, tau_q), with r = f(u*) + s + v* and u*, v* linear in the
+// slabs of step q.  With a nodal adjoint lambda (the adjoint of eps), the
+// adjoint of the slab of group g at step q is
+//   Sbar^u_{g,q}[k] = sum_paths (lambda_node Delta/M) f'(u*(X_q)) Psi_k(X_q),
+//   Sbar^v_{g,q}[k] = sum_paths (lambda_node Delta/M) Psi_k(X_q),
+// Psi_k(X) = prod_i L_{k_i}(X_i).  The kernel regenerates the forward paths
+// (same Philox counters, same arithmetic) and, per step, accumulates the sum
+// of the block's weighted outer products Psi = L(X_0) (x) L(X_1) into the
+// slab-adjoint table: on the matrix cores (FP32, v_mfma_f32_32x32x2f32 with
+// the samples as the reduction dimension) or on the vector units.
+// ===========================================================================
+size_t adjoint_lds_bytes(int fp32, int mfma, int dim, int P, int nthr, int64_t slab_stride)
+{
+    const size_t T = fp32 ? 4 : 8;
+    const int64_t nvec = slab_stride * (int64_t)T / 16;
+    const size_t slab = (size_t)2 * ((nvec + 1) & ~1LL) * 16;
+    if (mfma) return slab + (size_t)nthr * (2 * (P | 1) + 2) * 4 + 2 * 32 * 32 * 4;
+    const int R = dim == 1 ? 1 : P;
+    const int RS = (std::max(R, P) + 3) & ~3;
+    return slab + (size_t)nthr * 3 * RS * T;
+}
+
+template <typename T, int D, int PMAX, bool MFMA>
+__global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
+{
+    const RoundArgs &a = aa.r;
+    extern __shared__ u32x4 lds[];
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t nvec = a.slab_stride * (int64_t)sizeof(T) / 16;
+    const int64_t svec = (nvec + 1) & ~(int64_t)1;
+    const int P = a.P, PP = a.PP;
+    const int R = D == 1 ? 1 : P;
+    // vector path: weighted rows Au, Av and columns Bm per sample (stride RS);
+    // matrix-core path: basis rows Am and columns Bm (odd stride PS, so that a
+    // wave's row writes fall in distinct banks) and the two
+    // weights Wm per sample, the upper half's tiles gsum [2][16][64]
+    const int RS = MFMA ? P : (((R > P ? R : P) + 3) & ~3);
+    T *Au = (T *)(lds + 2 * svec);
+    T *Av = Au + (int64_t)nthr * RS;
+    T *Bm = Av + (int64_t)nthr * RS;
+    const int PS = P | 1;
+    float *Am = (float *)(lds + 2 * svec);
+    float *Bmm = Am + (int64_t)nthr * PS;
+    float *Wm = Bmm + (int64_t)nthr * PS;
+    float *gsum = MFMA ? Wm + 2 * (int64_t)nthr : nullptr;
+    __shared__ long long s_item;
+    cptr<GroupDesc> groups = as_const(a.groups);
+    cptr<NodeDesc> nodes = as_const(a.nodes);
+    const int64_t total = a.batch_prefix[a.n_groups];
+    using State = PathState<T, D>;
+    const State *sin = (const State *)a.state_in;
+    State *sout = (State *)a.state_out;
+    T *sbar = (T *)aa.slab_bar;
+    const int E = 2 * R * P;
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (long long)atomicAdd(a.work, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;
+        int lo = 0, hi = a.n_groups - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.batch_prefix[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const int g = lo;
+        const int64_t b = item - a.batch_prefix[g];
+        cptr<GroupDesc> G = groups + g;
+        const int nstar = G->nstar;
+        const int q0 = a.round * a.steps;
+        const int q1 = min(q0 + a.steps, nstar);
+        const T J = (T)G->jump;
+        const double ddelta = G->delta;
+        const uint32_t c3 = G->c3 | (uint32_t)a.tag;
+        const int64_t live = a.round == 0 ? (int64_t)G->node_count * a.mcount : (int64_t)a.live_in[g];
+        const T *gtab = (const T *)a.slab_table + G->slab;
+        T *gbar = sbar + G->slab;
+
+        T X[1][D], Y[1][D], acc[1], comp[1];
+        bool alive;
+        uint32_t node = 0, sample = 0, c0 = 0;
+        T lam = (T)0;
+        {
+            const int64_t p = b * a.batch + tid;
+            alive = p < live;
+            acc[0] = (T)0; comp[0] = (T)0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) X[0][i] = (T)0;
+            if (alive) {
+                if (a.round == 0) {
+                    node = (uint32_t)(G->node_begin + p / a.mcount);
+                    sample = (uint32_t)(a.m0 + p % a.mcount);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) X[0][i] = (T)nodes[node].x0[i];
+                } else {
+                    const State st = sin[G->path_off + p];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) X[0][i] = st.x[i];
+                    node = st.node;
+                    sample = st.sample;
+                }
+                c0 = nodes[node].c0;
+                lam = (T)(aa.lambda[nodes[node].u_index] * ddelta * aa.inv_M);
+            }
+        }
+        u32x4 stage[kMaxStageVec];
+        {
+            const u32x4 *src = (const u32x4 *)(gtab + (int64_t)q0 * a.slab_stride);
+#pragma unroll
+            for (int k = 0; k < kMaxStageVec; ++k) {
+                const int64_t v = tid + (int64_t)k * nthr;
+                if (v < nvec) lds[v] = src[v];
+            }
+        }
+        __syncthreads();
+
+        uint32_t w[1][4];
+        for (int q = q0; q < q1; ++q) {
+            const int buf = (q - q0) & 1;
+            if (q + 1 < q1) {
+                const u32x4 *src = (const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride);
+#pragma unroll
+                for (int k = 0; k < kMaxStageVec; ++k) {
+                    const int64_t v = tid + (int64_t)k * nthr;
+                    if (v < nvec) stage[k] = src[v];
+                }
+            }
+            T dir[1][D];
+            if constexpr (D == 1) {
+                if ((q & 127) == 0 || q == q0) philox(c0, sample, (uint32_t)(q >> 7), c3, a.key0, a.key1, w[0]);
+                const int wi = (q >> 5) & 3, bb = q & 31;
+                const uint32_t word = wi == 0 ? w[0][0] : wi == 1 ? w[0][1] : wi == 2 ? w[0][2] : w[0][3];
+                dir[0][0] = ((word >> bb) & 1u) ? (T)1 : (T)-1;
+            } else {
+                if ((q & 3) == 0 || q == q0) philox(c0, sample, (uint32_t)(q >> 2), c3, a.key0, a.key1, w[0]);
+                const int wi = q & 3;
+                const uint32_t word = wi == 0 ? w[0][0] : wi == 1 ? w[0][1] : wi == 2 ? w[0][2] : w[0][3];
+                angle_dir(u01(word, (T)0), dir[0][0], dir[0][1]);
+            }
+            if (alive) {
+                bool inside = true;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    Y[0][i] = m_fma(J, dir[0][i], X[0][i]);
+                    inside = inside && (fabs(Y[0][i]) < (T)1);
+                }
+                alive = inside;
+            }
+            // ---- weights of this evaluation: lambda Delta/M f'(u*(X_q)) and lambda Delta/M
+            T wu = (T)0, wv = (T)0;
+            const T *S = (const T *)(lds + (int64_t)buf * svec);
+            T Ll[1][PMAX];
+            {
+                const T x = X[0][D - 1];
+                Ll[0][0] = (T)1;
+                if (PMAX > 1) Ll[0][1] = x;
+#pragma unroll
+                for (int k = 1; k + 1 < PMAX; ++k)
+                    Ll[0][k + 1] = (T)((2.0 * k + 1.0) / (k + 1.0)) * x * Ll[0][k] - (T)(k / (k + 1.0)) * Ll[0][k - 1];
+            }
+            if (__ballot(alive) != 0ull) {
+                T u[1], v[1], W1[1];
+                u[0] = (T)0; v[0] = (T)0; W1[0] = (T)1;
+                contract<T, D, PMAX, 1, 0, const T *>(S, P, PP, X, W1, Ll, u, v, 0);
+                if (alive) {
+                    wv = lam;
+                    wu = lam * fprime_of<T>(a.phys, u[0]);
+                }
+            }
+            // ---- outer-product factors of this sample: rows L(X_0) weighted, columns L(X_{d-1})
+            if constexpr (MFMA) {
+                float *am = Am + (int64_t)tid * PS, *bm = Bmm + (int64_t)tid * PS;
+                Wm[2 * tid] = wu;
+                Wm[2 * tid + 1] = wv;
+                if constexpr (D == 1) {
+                    for (int i = 0; i < P; ++i) am[i] = i == 0 ? 1.f : 0.f;
+                } else {
+                    float lp = 0.f, lc = 1.f;
+                    const float x0 = X[0][0];
+                    for (int i = 0; i < P; ++i) {
+                        am[i] = lc;
+                        const float nx = rec_a<float>(i) * x0 * lc - rec_b<float>(i) * lp;
+                        lp = lc;
+                        lc = nx;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < PMAX; ++j)
+                    if (j < P) bm[j] = Ll[0][j];
+            } else {
+                T *au = Au + (int64_t)tid * RS, *av = Av + (int64_t)tid * RS, *bm = Bm + (int64_t)tid * RS;
+                if constexpr (D == 1) {
+                    for (int i = 0; i < RS; ++i) { au[i] = i == 0 ? wu : (T)0; av[i] = i == 0 ? wv : (T)0; }
+                } else {
+                    T lp = (T)0, lc = (T)1;
+                    const T x0 = X[0][0];
+                    for (int i = 0; i < RS; ++i) {
+                        const bool in = i < P;
+                        au[i] = in ? wu * lc : (T)0;
+                        av[i] = in ? wv * lc : (T)0;
+                        const T nx = rec_a<T>(i < kMaxP ? i : 0) * x0 * lc - rec_b<T>(i < kMaxP ? i : 0) * lp;
+                        lp = lc;
+                        lc = nx;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < PMAX; ++j)
+                    if (j < RS) bm[j] = j < P ? Ll[0][j] : (T)0;
+                for (int j = PMAX; j < RS; ++j) bm[j] = (T)0;
+            }
+            if (alive) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) X[0][i] = Y[0][i];
+            }
+            if (q + 1 < q1) {
+                u32x4 *dst = lds + (int64_t)(buf ^ 1) * svec;
+#pragma unroll
+                for (int k = 0; k < kMaxStageVec; ++k) {
+                    const int64_t v = tid + (int64_t)k * nthr;
+                    if (v < nvec) dst[v] = stage[k];
+                }
+            }
+            __syncthreads();
+            // ---- block sum of the outer products into the slab adjoint of step q
+            T *dstq = gbar + (int64_t)q * a.slab_stride;
+            if constexpr (MFMA) {
+                // wave w forms tile w & 1 (0: the f'(u)-weighted table, 1: the
+                // plain one) over half w >> 1 of the block's samples, two samples
+                // per product; the upper half hands its tile to the lower one
+                // through LDS with plain stores, which then adds into the table
+                // operand rows and columns i >= P read the next sample's factors
+                // (inside the LDS block): they only reach output rows or columns
+                // >= P, which are not written out
+                const int tile = wave & 1, half = wave >> 1, i = lane & 31;
+                constexpr int hs = 128;   // the matrix-core form runs four waves per block
+                f32x16 c = {};
+#pragma unroll 4
+                for (int kk = 0; kk < hs / 2; ++kk) {
+                    const int sidx = half * hs + 2 * kk + (lane >> 5);
+                    const float am = Am[sidx * PS + i], bb = Bmm[sidx * PS + i];
+                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(Wm[2 * sidx + tile] * am, bb, c, 0, 0, 0);
+                }
+                float *cm = gsum + tile * 16 * 64 + lane;
+                if (half == 1) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) cm[r * 64] = c[r];
+                }
+                // past this barrier no wave reads this step's factors again, and
+                // the upper half writes its next tile only after the next step's
+                // first barrier: it also closes the step
+                const int any_alive = __syncthreads_or(alive ? 1 : 0);
+                if (half == 0) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int ii = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        const float val = c[r] + cm[r * 64];
+                        if (ii < R && i < P && val != 0.f)
+                            atomicAdd(dstq + (int64_t)ii * 2 * PP + tile * PP + i, (T)val);
+                    }
+                }
+                if (any_alive == 0) break;
+            } else {
+                for (int e = tid; e < E; e += nthr) {
+                    const int uv = e / (R * P), rem = e - uv * R * P, ii = rem / P, jj = rem - ii * P;
+                    const T *A = uv ? Av : Au;
+                    T sum = (T)0;
+                    for (int sidx = 0; sidx < nthr; ++sidx) sum = m_fma(A[sidx * RS + ii], Bm[sidx * RS + jj], sum);
+                    if (sum != (T)0) atomicAdd(dstq + (int64_t)ii * 2 * PP + uv * PP + jj, sum);
+                }
+                if (__syncthreads_or(alive ? 1 : 0) == 0) break;
+            }
+        }
+        // survivors to the next round
+        {
+            const bool carry = alive && q1 < nstar;
+            const unsigned long long mask = __ballot(carry);
+            if (mask != 0ull) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(a.live_out + g, (uint32_t)__popcll(mask));
+                base = __shfl(base, 0, 64);
+                if (carry) {
+                    const uint32_t off = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                    State st;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) st.x[i] = X[0][i];
+                    st.acc = (T)0;
+                    st.comp = (T)0;
+                    st.node = node;
+                    st.sample = sample;
+                    sout[G->path_off + off] = st;
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int D, int PMAX>
+static hipError_t adj_mfma(const AdjointArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (a.use_mfma) { hipLaunchKernelGGL((adjoint_kernel<T, D, PMAX, true>), grid, block, lds, s, a); return hipGetLastError(); }
+    }
+    hipLaunchKernelGGL((adjoint_kernel<T, D, PMAX, false>), grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t adj_p(const AdjointArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    if (a.r.P <= 12) return adj_mfma<T, D, 12>(a, grid, block, lds, s);
+    if (a.r.P <= 20) return adj_mfma<T, D, 20>(a, grid, block, lds, s);
+    if (a.r.P <= 28) return adj_mfma<T, D, 28>(a, grid, block, lds, s);
+    if (a.r.P <= 32) return adj_mfma<T, D, 32>(a, grid, block, lds, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adjoint(const AdjointArgs &a, int fp32, int waves_per_block, int blocks, size_t lds_bytes,
+                          hipStream_t s)
+{
+    dim3 block(64 * waves_per_block), grid(blocks);
+    if (a.r.phys.dim == 1) return fp32 ? adj_p<float, 1>(a, grid, block, lds_bytes, s) : adj_p<double, 1>(a, grid, block, lds_bytes, s);
+    if (a.r.phys.dim == 2) return fp32 ? adj_p<float, 2>(a, grid, block, lds_bytes, s) : adj_p<double, 2>(a, grid, block, lds_bytes, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace hpsmc
