@@ -263,6 +263,19 @@ hpsmc_status hpsmc_get_increment(const hpsmc_plan *plan, int32_t iv, double *eps
 hpsmc_status hpsmc_eval(hpsmc_plan *plan, int32_t iv, int32_t inst, const double *pts, int64_t npts,
                         double *out, void *stream);
 
+/* hpsmc_eval for callers that cannot allocate device memory (serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, layouts and results,
+ * but the points and values are staged in a static 16 MiB device array
+ * instead of per-call allocations -- no hipMalloc, hipFree or other
+ * allocating call.  Each GPU holds its own copy of the array until the
+ * process ends; the current device must be the plan's.  npts * (dim + 3)
+ * doubles must fit in 16 MiB (npts <= 524288 for dim = 1, 262144 for dim = 5),
+ * else EINVAL before any device work.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other threads or streams) race
+ * and must be serialized by the caller.  Synchronizes the stream. */
+hpsmc_status hpsmc_eval_noalloc(hpsmc_plan *plan, int32_t iv, int32_t inst, const double *pts, int64_t npts,
+                                double *out, void *stream);
+
 /* Keep the per-sample values S_i of samples i < m_probe of every node of the
  * next iterations (0 disables); read them as [instance][node id][i]. */
 hpsmc_status hpsmc_set_probe(hpsmc_plan *plan, int64_t m_probe);

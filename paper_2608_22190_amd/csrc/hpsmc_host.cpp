@@ -1551,6 +1551,64 @@ hpsmc_status hpsmc_eval(hpsmc_plan *plan, int32_t iv, int32_t inst, const double
     return HPSMC_OK;
 }
 
+// ---- evaluation without allocation ----------------------------------------
+// Staging of hpsmc_eval_noalloc (the points in, the values out): one copy per
+// GPU, held until the process ends and shared by every call on that GPU.  In
+// host code `scratch` names a host-side stand-in, so kernels and copies take
+// the device address that hipGetSymbolAddress returns for the current device,
+// looked up once per device on its first call.
+constexpr size_t kNoAllocBytes = (size_t)16 << 20;
+static __device__ __align__(256) double scratch[kNoAllocBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double *g_scratch_dev[kMaxDevices];
+
+static hpsmc_status scratch_of_current_device(double **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(HPSMC_EDEVICE, "no current device for the static scratch array");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(HPSMC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (double *)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_eval_noalloc(hpsmc_plan *plan, int32_t iv, int32_t inst, const double *pts, int64_t npts,
+                                double *out, void *stream)
+{
+    CHECK_PLAN(plan);
+    if (plan->frac) return fail(HPSMC_ENOTSUP, "hpsmc_eval_noalloc covers the Laplacian's basis");
+    if (iv < 0 || iv >= plan->n_iv || inst < 0 || inst >= plan->n_inst || npts < 0 || (npts && (!pts || !out)))
+        return fail(HPSMC_EINVAL, "bad eval arguments");
+    const int64_t per_pt = plan->d + 1 + 2;   // doubles staged per point: coordinates and time in, (u, v) out
+    if (npts > (int64_t)(kNoAllocBytes / sizeof(double)) / per_pt)
+        return fail(HPSMC_EINVAL, "npts exceeds the static scratch of hpsmc_eval_noalloc (" +
+                                      std::to_string((kNoAllocBytes / sizeof(double)) / per_pt) + " points)");
+    if (npts == 0) return HPSMC_OK;
+    double *base = nullptr;
+    if (hpsmc_status st = scratch_of_current_device(&base)) return st;
+    hipStream_t s = (hipStream_t)stream;
+    double *dp = base, *dout = base + npts * (plan->d + 1);   // both regions are written in full before any read
+    const size_t pb = (size_t)npts * (plan->d + 1) * 8, ob = (size_t)npts * 2 * 8;
+    const int T1 = plan->degree[iv] + 1;
+    const int64_t co = plan->c_off[iv] + (int64_t)inst * plan->psp * T1;
+    hipError_t e = hipMemcpyAsync(dp, pts, pb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_eval(plan->cu + co, plan->cv + co, plan->d, plan->P, T1, plan->t_breaks[iv],
+                        plan->t_breaks[iv + 1] - plan->t_breaks[iv], dp, npts, dout, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, ob, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(HPSMC_EDEVICE, std::string("eval: ") + hipGetErrorString(e));
+    return HPSMC_OK;
+}
+
 hpsmc_status hpsmc_set_probe(hpsmc_plan *plan, int64_t m_probe)
 {
     CHECK_PLAN(plan);

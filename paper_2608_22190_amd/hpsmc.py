@@ -81,6 +81,8 @@ _SIGS = {
     "hpsmc_set_nodes": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
     "hpsmc_get_increment": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hpsmc_eval": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "hpsmc_eval_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_void_p]),
     "hpsmc_set_probe": (C.c_int, [C.c_void_p, C.c_int64]),
     "hpsmc_get_probe": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "hpsmc_set_launch": (C.c_int, [C.c_void_p, C.POINTER(hpsmc_launch)]),
@@ -325,6 +327,13 @@ class Plan:
         pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, self.wl.dim + 1)
         out = np.zeros((pts.shape[0], 2))
         _check(lib().hpsmc_eval(self.h, iv, inst, _ptr(pts), pts.shape[0], _ptr(out), _stream(stream)), "hpsmc_eval")
+        return out
+
+    def hpsmc_eval_noalloc(self, iv, inst, pts, stream=None):
+        pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, self.wl.dim + 1)
+        out = np.zeros((pts.shape[0], 2))
+        _check(lib().hpsmc_eval_noalloc(self.h, iv, inst, _ptr(pts), pts.shape[0], _ptr(out), _stream(stream)),
+               "hpsmc_eval_noalloc")
         return out
 
     def hpsmc_set_probe(self, m_probe):
