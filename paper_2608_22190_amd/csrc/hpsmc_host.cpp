@@ -2080,7 +2080,10 @@ static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hi
     aa.slab_bar = plan->slab_bar;
     aa.inv_M = 1.0 / (double)plan->pb.M;
     aa.use_mfma = mfma;
-    const int blocks = std::max(1, plan->cus * (8 / waves));
+    // the matrix-core form is compiled for three waves per SIMD: three
+    // four-wave blocks per CU when their LDS fits in the CU's 160 KiB
+    const int per_cu = mfma ? (3 * lds <= (size_t)160 * 1024 ? 3 : 2) : 8 / waves;
+    const int blocks = std::max(1, plan->cus * per_cu);
     for (int64_t m0 = 0; m0 < plan->pb.M; m0 += set.ms) {
         const int64_t mc = std::min<int64_t>(set.ms, plan->pb.M - m0);
         a.m0 = m0;

@@ -25,14 +25,14 @@ size_t adjoint_lds_bytes(int fp32, int mfma, int dim, int P, int nthr, int64_t s
     const size_t T = fp32 ? 4 : 8;
     const int64_t nvec = slab_stride * (int64_t)T / 16;
     const size_t slab = (size_t)2 * ((nvec + 1) & ~1LL) * 16;
-    if (mfma) return slab + (size_t)nthr * (2 * (P | 1) + 2) * 4 + 2 * 32 * 32 * 4;
+    if (mfma) return slab + ((size_t)2 * P * (nthr + 4) + 2 * nthr) * 4 + 2 * 32 * 32 * 4;
     const int R = dim == 1 ? 1 : P;
     const int RS = (std::max(R, P) + 3) & ~3;
     return slab + (size_t)nthr * 3 * RS * T;
 }
 
 template <typename T, int D, int PMAX, bool MFMA>
-__global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFMA ? 3 : 1))) adjoint_kernel(AdjointArgs aa)
 {
     const RoundArgs &a = aa.r;
     extern __shared__ u32x4 lds[];
@@ -42,17 +42,19 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
     const int P = a.P, PP = a.PP;
     const int R = D == 1 ? 1 : P;
     // vector path: weighted rows Au, Av and columns Bm per sample (stride RS);
-    // matrix-core path: basis rows Am and columns Bm (odd stride PS, so that a
-    // wave's row writes fall in distinct banks) and the two
-    // weights Wm per sample, the upper half's tiles gsum [2][16][64]
+    // matrix-core path: the basis values L_i(x_0) (Am) and L_j(x_{d-1}) (Bm)
+    // as [i][sample] tables of row stride NST = nthr + 4 (rows start four banks
+    // apart, so the 16-byte reads of a half-wave, one row per lane, are free of
+    // bank conflicts), the two weights Wm [2][sample], and the upper half's
+    // tiles gsum [2][16][64]
     const int RS = MFMA ? P : (((R > P ? R : P) + 3) & ~3);
     T *Au = (T *)(lds + 2 * svec);
     T *Av = Au + (int64_t)nthr * RS;
     T *Bm = Av + (int64_t)nthr * RS;
-    const int PS = P | 1;
+    const int NST = nthr + 4;
     float *Am = (float *)(lds + 2 * svec);
-    float *Bmm = Am + (int64_t)nthr * PS;
-    float *Wm = Bmm + (int64_t)nthr * PS;
+    float *Bmm = Am + (int64_t)P * NST;
+    float *Wm = Bmm + (int64_t)P * NST;
     float *gsum = MFMA ? Wm + 2 * (int64_t)nthr : nullptr;
     __shared__ long long s_item;
     cptr<GroupDesc> groups = as_const(a.groups);
@@ -181,16 +183,16 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
             }
             // ---- outer-product factors of this sample: rows L(X_0) weighted, columns L(X_{d-1})
             if constexpr (MFMA) {
-                float *am = Am + (int64_t)tid * PS, *bm = Bmm + (int64_t)tid * PS;
-                Wm[2 * tid] = wu;
-                Wm[2 * tid + 1] = wv;
+                Wm[tid] = wu;
+                Wm[nthr + tid] = wv;
                 if constexpr (D == 1) {
-                    for (int i = 0; i < P; ++i) am[i] = i == 0 ? 1.f : 0.f;
+                    for (int i = 0; i < P; ++i) Am[(int64_t)i * NST + tid] = i == 0 ? 1.f : 0.f;
                 } else {
                     float lp = 0.f, lc = 1.f;
                     const float x0 = X[0][0];
-                    for (int i = 0; i < P; ++i) {
-                        am[i] = lc;
+#pragma unroll
+                    for (int i = 0; i < PMAX; ++i) {
+                        if (i < P) Am[(int64_t)i * NST + tid] = lc;
                         const float nx = rec_a<float>(i) * x0 * lc - rec_b<float>(i) * lp;
                         lp = lc;
                         lc = nx;
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
                 }
 #pragma unroll
                 for (int j = 0; j < PMAX; ++j)
-                    if (j < P) bm[j] = Ll[0][j];
+                    if (j < P) Bmm[(int64_t)j * NST + tid] = Ll[0][j];
             } else {
                 T *au = Au + (int64_t)tid * RS, *av = Av + (int64_t)tid * RS, *bm = Bm + (int64_t)tid * RS;
                 if constexpr (D == 1) {
@@ -238,19 +240,28 @@ __global__ void __launch_bounds__(256) adjoint_kernel(AdjointArgs aa)
             if constexpr (MFMA) {
                 // wave w forms tile w & 1 (0: the f'(u)-weighted table, 1: the
                 // plain one) over half w >> 1 of the block's samples, two samples
-                // per product; the upper half hands its tile to the lower one
-                // through LDS with plain stores, which then adds into the table
-                // operand rows and columns i >= P read the next sample's factors
-                // (inside the LDS block): they only reach output rows or columns
+                // per product (the reduction index k of a product is the lane
+                // half: lanes 0-31 take samples base .. base + 63, lanes 32-63 the
+                // next 64, four at a time from one 16-byte read per table); the
+                // upper half hands its tile to the lower one through LDS with
+                // plain stores, which then adds into the table.  Lanes of rows
+                // i >= P read row P - 1: they only reach output rows or columns
                 // >= P, which are not written out
                 const int tile = wave & 1, half = wave >> 1, i = lane & 31;
                 constexpr int hs = 128;   // the matrix-core form runs four waves per block
+                const int ri = i < P ? i : P - 1;
+                const int base = half * hs + (lane >> 5) * (hs / 2);
+                const float4 *ap = (const float4 *)(Am + (int64_t)ri * NST + base);
+                const float4 *bp = (const float4 *)(Bmm + (int64_t)ri * NST + base);
+                const float4 *wp = (const float4 *)(Wm + (int64_t)tile * nthr + base);
                 f32x16 c = {};
-#pragma unroll 4
-                for (int kk = 0; kk < hs / 2; ++kk) {
-                    const int sidx = half * hs + 2 * kk + (lane >> 5);
-                    const float am = Am[sidx * PS + i], bb = Bmm[sidx * PS + i];
-                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(Wm[2 * sidx + tile] * am, bb, c, 0, 0, 0);
+#pragma unroll
+                for (int m = 0; m < hs / 8; ++m) {
+                    const float4 a4 = ap[m], b4 = bp[m], w4 = wp[m];
+                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.x * a4.x, b4.x, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.y * a4.y, b4.y, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.z * a4.z, b4.z, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.w * a4.w, b4.w, c, 0, 0, 0);
                 }
                 float *cm = gsum + tile * 16 * 64 + lane;
                 if (half == 1) {
