@@ -209,7 +209,7 @@ def run_other(name, args, torch):
     out = {"metric": METRIC, "value": per_step * args.steps / sec, "unit": "node-samples/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * sec / args.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64" if wl.precision == "fp64" else "f32",
-           "data": "synthetic", "config": {"workload": desc, "max_nstar": int(max(wl.nstar)),
+           "data": "synthetic", "config": {"workload": desc, "max_nstar": int(hpsmc.resolve_nstar(wl)[0].max()),
                                            "launch": list(plan_launch)}}
     if name != "c5":
         out["roofline"] = {"bound": "mfma" if mma else "alu", "achieved": fpe * st["path_steps"] / launches / max(1e-9, k_ms * 1e-3) / 1e12
@@ -599,7 +599,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2608_22190_amd import workloads as W
+    from paper_2608_22190_amd import hpsmc, workloads as W
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
@@ -635,7 +635,7 @@ def main():
                                f"all {nodes} nodes (24x24 JG(1,1) x 16 LGL times) x samples 0..{base.M - 1} "
                                f"of M=65536; FP32 sampling, FP64 reconstruction/update",
                    "dim": 2, "n": 24, "temporal_degree": 16, "nodes": nodes, "samples_per_node": base.M,
-                   "max_nstar": int(max(base.nstar)), "launch": list(r32["launch"])},
+                   "max_nstar": int(hpsmc.resolve_nstar(base)[0].max()), "launch": list(r32["launch"])},
         "roofline": {"bound": "mfma" if r32["mma"] else "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
                      "traffic": measured_traffic(r32["launch"]),

@@ -82,8 +82,13 @@ enum { HPSMC_SRC_NONE = 0,        /* s = 0 */
           source s = u_t + (-Delta)^{alpha/2} u - f(u) (Ex. 2-3): */
        HPSMC_SRC_FRAC_LONGTIME = 5, /* g = sin x, T = e^{cos t}/(1+t^2)                   */
        HPSMC_SRC_FRAC_SINGULAR = 6, /* g = cos(x^3+1)/(10x^2+1), T = t^rho, rho = src_param[0] */
-       HPSMC_SRC_FRAC_POLY = 7 };   /* g = p0 + p1 x + p2 x^2, T = 1 + c t,
+       HPSMC_SRC_FRAC_POLY = 7,     /* g = p0 + p1 x + p2 x^2, T = 1 + c t,
                                        src_param = {p0, p1, p2, c}                         */
+       /* a given polynomial source (the Laplacian only): per interval a tensor-Legendre
+          polynomial of P = n+2 modes per dimension and degree M_n in time (src_coeffs,
+          src_len); it enters the time contraction of v* = Lap u* - d_t u*, so a path
+          step costs no more; no exact solution (no IC_EXACT); residual form only */
+       HPSMC_SRC_POLY = 8 };
 
 /* initial data */
 enum { HPSMC_IC_EXACT = 0,        /* u_ex(x, t_0) of the source's exact solution */
@@ -131,6 +136,20 @@ enum { HPSMC_QUAD_CENTRE = 0,     /* eq. interIQ: a walk step adds Delta * r at 
                                      Y_q may lie outside Omega.  Vector-unit round
                                      kernel only; no gradient                     */
 
+/* path lengths N* of the node times (eq. time division: N* depends on h_n and
+ * on l).  A rule gives N*_{n,l} = max(nstar_min, ceil((t_{n,l} - t_{n-1}) /
+ * Delta_max)) with the same Delta_max for every node time of interval n: */
+enum { HPSMC_NSTAR_ARRAY = 0,     /* the `nstar` array, one entry per node time    */
+       HPSMC_NSTAR_DT = 1,        /* Delta_max = dt_max                            */
+       HPSMC_NSTAR_SPECTRAL = 2 };/* Delta_max = nstar_c / rho(A_h) per interval,
+                                     rho the spectral radius of the interval's
+                                     discrete operator A_h = d_t - Lap_h (or
+                                     d_t + (-Lap)^{alpha/2}_h) on the nodal values
+                                     of l >= 1 (the residual estimator scales an
+                                     error mode of eigenvalue lambda by about
+                                     1 - Delta lambda per iteration), computed at
+                                     set-up                                       */
+
 enum { HPSMC_FP64 = 0,            /* everything in FP64                            */
        HPSMC_FP32_SAMPLING = 1 }; /* paths and basis evaluation in FP32 with
                                      compensated accumulation; reconstruction,
@@ -144,7 +163,8 @@ typedef struct {
     const double *t_breaks;    /* host, N_h+1 strictly increasing               */
     const int32_t *degree;     /* host, N_h entries M_n in 1..31                */
     const int32_t *nstar;      /* host, sum_n M_n entries: N* of node time l>=1
-                                  of interval n (eq. time division), 1..2^24-1 */
+                                  of interval n (eq. time division), 1..2^24-1;
+                                  read only with nstar_mode HPSMC_NSTAR_ARRAY  */
     int32_t f_kind, src_kind, ic_kind, schedule;
     double f_param[4], src_param[8], ic_param[4];
     const double *ic_data;     /* host, [instance][n^d] for IC_PHI / IC_NODAL   */
@@ -176,6 +196,18 @@ typedef struct {
                                   form, centre-point rule, initial data IC_EXACT
                                   or IC_NODAL; no gradient, no hpsmc_eval or
                                   hpsmc_get_coeffs                              */
+    int32_t nstar_mode;        /* HPSMC_NSTAR_ARRAY (default), _DT or _SPECTRAL  */
+    int32_t nstar_min;         /* rules: smallest N* (0 selects 4)              */
+    double nstar_c;            /* HPSMC_NSTAR_SPECTRAL: Delta_max = nstar_c/rho
+                                  (0 selects 0.25)                              */
+    double dt_max;             /* HPSMC_NSTAR_DT: Delta_max, > 0                 */
+    const double *src_coeffs;  /* HPSMC_SRC_POLY: host, the source's tensor-Legendre
+                                  coefficients, per interval n a block
+                                  [k_0..k_{d-1}][q] of P^d (M_n+1) values (P = n+2
+                                  modes per dimension), s(x, t) = sum c
+                                  prod_i L_{k_i}(x_i) L_q(xi), xi = 2(t -
+                                  t_{n-1})/h_n - 1; shared by all instances      */
+    int64_t src_len;           /* HPSMC_SRC_POLY: sum_n P^d (M_n+1)             */
 } hpsmc_problem;
 
 typedef struct hpsmc_plan hpsmc_plan;
@@ -231,6 +263,17 @@ hpsmc_status hpsmc_set_allocator(hpsmc_alloc_fn alloc, hpsmc_free_fn free_, void
  * EINVAL on any out-of-range field; ENOTSUP for unsupported combinations. */
 hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out);
 void hpsmc_destroy(hpsmc_plan *plan);
+
+/* Resolve the path lengths of a problem without a plan or a device (the rule
+ * that hpsmc_create applies, eq. time division): nstar (host, sum_n M_n
+ * entries) receives N* of every node time l >= 1 of every interval, dt_max
+ * (host, n_intervals entries, may be NULL) the rule's Delta_max per interval
+ * (0 for HPSMC_NSTAR_ARRAY).  Validates the problem like hpsmc_create; EINVAL
+ * also when the rule gives N* >= 2^24. */
+hpsmc_status hpsmc_resolve_nstar(const hpsmc_problem *pb, int32_t *nstar, double *dt_max);
+
+/* The plan's resolved path lengths, as hpsmc_resolve_nstar returns them. */
+hpsmc_status hpsmc_get_nstar(const hpsmc_plan *plan, int32_t *nstar, double *dt_max);
 
 /* Spatial nodes (n, host) and temporal nodes of interval iv (M_iv+1, host). */
 hpsmc_status hpsmc_grid(const hpsmc_plan *plan, int32_t iv, double *x_nodes, double *t_nodes);

@@ -629,9 +629,43 @@ double or_exact(const or_problem *pb, const double *X, double t)
 /* s = u_t - Lap u - f(u) at the exact solution, so that the exact solution
  * satisfies u_t = Lap u + f(u) + s (fractional kinds: -(-Delta)^{alpha/2} in
  * place of Lap) */
+/* OR_SRC_POLY: the interval's tensor-Legendre polynomial evaluated term by term */
+static double or_source_poly(const or_problem *pb, int interval, const double *X, double t)
+{
+    const int d = pb->dim, P = pb->n + 2;
+    const int64_t pd = or_ipow(P, d);
+    int64_t off = 0;
+    for (int i = 0; i < interval; ++i) off += pd * (pb->degree[i] + 1);
+    const int T1 = pb->degree[interval] + 1;
+    const double t0 = pb->t_breaks[interval], h = pb->t_breaks[interval + 1] - t0;
+    const double xi = 2.0 * (t - t0) / h - 1.0;
+    double s = 0.0;
+    for (int64_t k = 0; k < pd; ++k) {
+        double sp = 1.0;
+        int64_t r = k;
+        for (int i = d - 1; i >= 0; --i) {
+            sp *= or_legendre((int)(r % P), X[i]);
+            r /= P;
+        }
+        for (int q = 0; q < T1; ++q) s += pb->src_coeffs[off + k * T1 + q] * sp * or_legendre(q, xi);
+    }
+    return s;
+}
+
+double or_source_iv(const or_problem *pb, int interval, const double *X, double t)
+{
+    if (pb->src_kind == OR_SRC_POLY) return or_source_poly(pb, interval, X, t);
+    return or_source(pb, X, t);
+}
+
 double or_source(const or_problem *pb, const double *X, double t)
 {
     if (pb->src_kind == OR_SRC_NONE) return 0.0;
+    if (pb->src_kind == OR_SRC_POLY) {   /* the first interval whose closure holds t */
+        int iv = 0;
+        while (iv + 1 < pb->n_intervals && t > pb->t_breaks[iv + 1]) ++iv;
+        return or_source_poly(pb, iv, X, t);
+    }
     double u, ut, lap;
     or_exact_parts(pb, X, t, &u, &ut, &lap);
     return ut - lap - or_f(pb, u);
@@ -647,7 +681,7 @@ double or_residual(const or_problem *pb, int interval, const double *Ut,
     double v[3];
     if (or_is_frac(pb)) or_frac_eval(pb->alpha, pb->n, pb->degree[interval], h, Ut, X[0], xi, v);
     else or_eval(pb->dim, pb->n, pb->degree[interval], h, Ut, X, xi, v);
-    return or_f(pb, v[0]) + or_source(pb, X, tau) - v[1] + v[2];
+    return or_f(pb, v[0]) + or_source_iv(pb, interval, X, tau) - v[1] + v[2];
 }
 
 int or_grid(const or_problem *pb, int interval, double *x_nodes, double *t_nodes)
@@ -862,7 +896,7 @@ static double or_picard_integrand(const or_problem *pb, int interval, const doub
     double v[3];
     if (or_is_frac(pb)) or_frac_eval(pb->alpha, pb->n, pb->degree[interval], h, Ut, X[0], xi, v);
     else or_eval(pb->dim, pb->n, pb->degree[interval], h, Ut, X, xi, v);
-    return or_f(pb, v[0]) + or_source(pb, X, tau);
+    return or_f(pb, v[0]) + or_source_iv(pb, interval, X, tau);
 }
 
 /* One path of the estimator.  Reading R6: the time of step q runs

@@ -51,7 +51,12 @@ enum { OR_SRC_NONE = 0,        /* s = 0                                         
        /* fractional operator (alpha in (0,2), d = 1), u_ex = (1-x^2)_+^{alpha/2} g(x) T(t): */
        OR_SRC_FRAC_LONGTIME = 5, /* g = sin x, T = e^{cos t}/(1+t^2) (Ex. 2)             */
        OR_SRC_FRAC_SINGULAR = 6, /* g = cos(x^3+1)/(10x^2+1), T = t^rho, rho = src_param[0] (Ex. 3) */
-       OR_SRC_FRAC_POLY = 7 };   /* g = p0 + p1 x + p2 x^2, T = 1 + c t, src_param = {p0,p1,p2,c} */
+       OR_SRC_FRAC_POLY = 7,     /* g = p0 + p1 x + p2 x^2, T = 1 + c t, src_param = {p0,p1,p2,c} */
+       OR_SRC_POLY = 8 };        /* s given per interval n by tensor-Legendre coefficients
+                                    src_coeffs: block n (after the blocks of the intervals
+                                    before it) holds c[k_1..k_d][q], k_i < n+2, q <= M_n, and
+                                    s(x, t) = sum c prod_i L_{k_i}(x_i) L_q(xi),
+                                    xi = 2 (t - t_{n-1}) / h_n - 1; no exact solution        */
 
 /* initial data u0 */
 enum { OR_IC_EXACT = 0,        /* u0 = u_ex(x, 0) of the source's exact solution     */
@@ -81,6 +86,8 @@ typedef struct {
     double alpha;             /* order of the operator: 2 (or 0) the Laplacian;
                                  (0,2) the fractional Laplacian (-Delta)^{alpha/2}
                                  with the alpha-stable walk, d = 1 only         */
+    const double *src_coeffs; /* OR_SRC_POLY: sum_n (n+2)^d (M_n+1) coefficients  */
+    int64_t src_len;
 } or_problem;
 
 /* acceleration of the fixed-point iteration (the remark after Algorithm 1):
@@ -196,6 +203,10 @@ int or_iterate_aitken(const or_problem *pb, int inst, int interval, int iter_tag
  * every sample path fixed (common random numbers). */
 int or_loss_grad(const or_problem *pb, int inst, const double *c0,
                  const double *target, double *loss, double *grad);
+
+/* the source at (X, t) on interval `interval` (OR_SRC_POLY needs the interval;
+ * the other kinds ignore it) */
+double or_source_iv(const or_problem *pb, int interval, const double *X, double t);
 
 /* fraction of walks started at `starts` ([nwalk][dim]) that leave Omega within
  * nstar steps of length J = sqrt(2 d T/nstar) (Table 1 setting). */

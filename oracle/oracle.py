@@ -7,6 +7,7 @@ from ``hpsmc_oracle.c`` with gcc) and shares no code with the GPU library.
 from __future__ import annotations
 
 import ctypes as C
+import functools
 import os
 import subprocess
 
@@ -18,7 +19,7 @@ _SRC = os.path.join(_HERE, "hpsmc_oracle.c")
 
 F_KINDS = {"affine": 0, "u_minus_u3": 1, "sin": 2, "u2_over_1pu2": 3, "neg_u3": 4, "u_sin_u": 5}
 SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4, "frac_longtime": 5,
-             "frac_singular": 6, "frac_poly": 7}
+             "frac_singular": 6, "frac_poly": 7, "poly": 8}
 IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
 SCHEDULES = {"sequential": 0, "sweeps": 1}
 
@@ -40,7 +41,7 @@ class _Problem(C.Structure):
         ("ic_data", C.POINTER(C.c_double)),
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
         ("estimator", C.c_int32), ("accel", C.c_int32), ("quad", C.c_int32), ("omega", C.c_double * 3),
-        ("alpha", C.c_double),
+        ("alpha", C.c_double), ("src_coeffs", C.POINTER(C.c_double)), ("src_len", C.c_int64),
     ]
 
 
@@ -69,6 +70,7 @@ def lib():
             "or_residual": (d, [pp, C.c_int, p, p, d]),
             "or_f": (d, [pp, d]), "or_fprime": (d, [pp, d]),
             "or_source": (d, [pp, p, d]), "or_exact": (d, [pp, p, d]),
+            "or_source_iv": (d, [pp, C.c_int, p, d]),
             "or_grid": (C.c_int, [pp, C.c_int, p, p]),
             "or_ic_nodes": (C.c_int, [pp, C.c_int, p]),
             "or_sample_path": (d, [pp, p, C.c_int, C.c_int, C.c_int, i64, i64, p]),
@@ -206,6 +208,128 @@ def num_threads():
     return lib().or_num_threads()
 
 
+# ---------------------------------------------------------------- path lengths
+def spatial_operator(n, alpha=2.0):
+    """The one-dimensional spatial collocation operator on the n nodes:
+    -d^2/dx^2 of the interpolant in the phi basis (Sec. 2.3: -phi_p'' =
+    (p+1)(p+2) P_p^{(1,1)}, nodal -> phi coefficients by the matrix A of
+    eq. spacelag), or for 0 < alpha < 2 the fractional Laplacian of the
+    interpolant in the basis w P_p^{(a,a)}, a = alpha/2 (eigen-relation
+    (-Delta)^{alpha/2}[w P_p] = lambda_p P_p).  Returns (nodes, K) with
+    (K u)_m the operator's value at node m."""
+    if 0.0 < alpha < 2.0:
+        a = 0.5 * alpha
+        x, _ = gauss_jacobi(n, a)
+        # spatial coefficients of each nodal unit vector (time-constant data of degree 1)
+        G = np.zeros((n, n))
+        for j in range(n):
+            U = np.zeros((n, 2))
+            U[j, :] = 1.0
+            G[:, j] = frac_reconstruct(alpha, n, 1, U.reshape(-1)).reshape(n, 2)[:, 0]
+        L = lib()
+        V = np.array([[L.or_frac_lambda(p, alpha) * L.or_jacobi_aa(p, a, xm) for p in range(n)] for xm in x])
+        return x, V @ G
+    x, _ = jg11(n)
+    A = matrix_A(n).reshape(n, n)
+    V = np.array([[(p + 1) * (p + 2) * jacobi11(p, xm) for p in range(n)] for xm in x])
+    return x, V @ A
+
+
+def temporal_derivative(M):
+    """d/dxi of the Lobatto interpolant (eq. timeLag: nodal -> Legendre by the
+    matrix B, then L_q'), on the node times l = 1..M with column 0 held at 0."""
+    xi, _ = lgl(M)
+    B = matrix_B(M).reshape(M + 1, M + 1)
+    Ld = np.array([[legendre_deriv(q, z) for q in range(M + 1)] for z in xi])
+    return xi, (Ld @ B)[1:, 1:]
+
+
+@functools.lru_cache(maxsize=None)
+def lobatto_derivative_eigs(M):
+    """Eigenvalues of temporal_derivative(M) at 50 digits, by a route of its
+    own: the Lobatto nodes refined by Newton's method on L_M' (Bonnet's
+    recurrence in mpmath, starting from the oracle's double nodes), the
+    barycentric differentiation matrix D_lk = (w_k / w_l) / (xi_l - xi_k),
+    D_ll = -sum_k D_lk, restricted to l, k >= 1, and mpmath's eigen-solver
+    (the matrix is far from normal: double precision loses five digits at
+    M = 31)."""
+    import mpmath as mp
+    with mp.workdps(50):
+        def dleg(x):
+            # L_M'(x) and L_M''(x) from (1 - x^2) L'' = 2 x L' - M (M + 1) L
+            a, b = mp.mpf(1), x
+            for m in range(1, M):
+                a, b = b, ((2 * m + 1) * x * b - m * a) / (m + 1)
+            L, Lm1 = (b, a) if M >= 1 else (mp.mpf(1), mp.mpf(0))
+            d1 = M * (Lm1 - x * L) / (1 - x * x)
+            d2 = (2 * x * d1 - M * (M + 1) * L) / (1 - x * x)
+            return d1, d2
+        xi_d, _ = lgl(M)
+        nodes = [mp.mpf(-1)]
+        for x0 in xi_d[1:-1]:
+            x = mp.mpf(float(x0))
+            for _ in range(8):
+                d1, d2 = dleg(x)
+                x = x - d1 / d2
+            nodes.append(x)
+        nodes.append(mp.mpf(1))
+        T1 = M + 1
+        w = [1 / mp.fprod([nodes[k] - nodes[m] for m in range(T1) if m != k]) for k in range(T1)]
+        D = mp.matrix(M, M)
+        for l in range(1, T1):
+            row = mp.mpf(0)
+            for k in range(T1):
+                if k != l:
+                    v = (w[k] / w[l]) / (nodes[l] - nodes[k])
+                    row -= v
+                    if k >= 1:
+                        D[l - 1, k - 1] = v
+            D[l - 1, l - 1] = row
+        if M == 1:
+            return (complex(D[0, 0]),)
+        ev = mp.eig(D, left=False, right=False)
+        return tuple(complex(e) for e in ev)
+
+
+def spectral_radius(dim, n, M, h, alpha=2.0):
+    """rho of the interval's discrete operator A_h = d_t - Lap_h (or
+    d_t + (-Lap)^{alpha/2}_h) on the nodal values of node times l >= 1:
+    A_h is the Kronecker sum of (2/h) D_t and one spatial operator per
+    dimension, so its eigenvalues are (2/h) mu_j + kappa_{m_1} + ... +
+    kappa_{m_d}; every combination is formed and the largest modulus taken."""
+    _, K = spatial_operator(n, alpha)
+    kap = np.linalg.eigvals(K)
+    mu = np.array(lobatto_derivative_eigs(M))
+    S = np.zeros(1, dtype=complex)
+    for _ in range(dim if not (0.0 < alpha < 2.0) else 1):
+        S = (S[:, None] + kap[None, :]).reshape(-1)
+    return float(np.max(np.abs((2.0 / h) * mu[:, None] + S[None, :])))
+
+
+def nstar_rule(wl):
+    """N* of every node time l >= 1 of every interval (eq. time division:
+    Delta_{n,l} = (t_{n,l} - t_{n-1}) / N*): max(nstar_min, ceil(span /
+    Delta_max)) with Delta_max = nstar_c / rho(A_h) per interval ("spectral"),
+    or the given dt_max ("dt"); an explicit list is returned as is."""
+    mode = getattr(wl, "nstar_mode", "array")
+    if mode == "array":
+        return [int(v) for v in wl.nstar]
+    nmin = wl.nstar_min if wl.nstar_min > 0 else 4
+    out = []
+    for iv, M in enumerate(wl.degree):
+        h = wl.t_breaks[iv + 1] - wl.t_breaks[iv]
+        if mode == "spectral":
+            c = wl.nstar_c if wl.nstar_c > 0 else 0.25
+            dt = c / spectral_radius(wl.dim, wl.n, M, h, getattr(wl, "alpha", 2.0))
+        else:
+            dt = wl.dt_max
+        xi, _ = lgl(M)
+        for ell in range(1, M + 1):
+            # a quotient within rounding of an integer is not carried to the next one
+            out.append(max(nmin, int(np.ceil((1.0 - 1e-12) * 0.5 * (xi[ell] + 1.0) * h / dt))))
+    return out
+
+
 # ---------------------------------------------------------------- problems
 class Problem:
     """Holds an ``or_problem`` and the arrays it points into.
@@ -217,7 +341,7 @@ class Problem:
         self.wl = wl
         self.t_breaks = np.ascontiguousarray(wl.t_breaks, dtype=np.float64)
         self.degree = np.ascontiguousarray(wl.degree, dtype=np.int32)
-        self.nstar = np.ascontiguousarray(wl.nstar, dtype=np.int32)
+        self.nstar = np.ascontiguousarray(nstar_rule(wl), dtype=np.int32)
         ic = wl.ic_data
         self.ic_data = None if ic is None else np.ascontiguousarray(ic, dtype=np.float64).reshape(-1)
         s = _Problem()
@@ -241,6 +365,11 @@ class Problem:
         s.accel = ACCELS[getattr(wl, "accel", "none")]
         s.quad = QUADS[getattr(wl, "quad", "centre")]
         s.alpha = float(getattr(wl, "alpha", 2.0))
+        sc = getattr(wl, "src_coeffs", None)
+        self.src_coeffs = None if sc is None else np.ascontiguousarray(sc, dtype=np.float64).reshape(-1)
+        s.src_coeffs = (self.src_coeffs.ctypes.data_as(C.POINTER(C.c_double)) if self.src_coeffs is not None
+                        else C.POINTER(C.c_double)())
+        s.src_len = 0 if self.src_coeffs is None else self.src_coeffs.size
         for i, v in enumerate(getattr(wl, "omega", [0.0, 0.0, 0.0])):
             s.omega[i] = v
         self.s = s
@@ -276,6 +405,10 @@ class Problem:
     def source(self, X, t):
         X = np.ascontiguousarray(X, dtype=np.float64)
         return lib().or_source(self.ref, _ptr(X), float(t))
+
+    def source_iv(self, iv, X, t):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        return lib().or_source_iv(self.ref, int(iv), _ptr(X), float(t))
 
     def exact(self, X, t):
         X = np.ascontiguousarray(X, dtype=np.float64)

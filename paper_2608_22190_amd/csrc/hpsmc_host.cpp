@@ -2,6 +2,7 @@
 // quadrature and transform set-up, device memory, node scheduling, the
 // iteration / interval / sweep drivers and the C ABI of include/hpsmc.h.
 #include "hpsmc_internal.h"
+#include "hpsmc_lobatto_eigs.h"
 #include "../../include/hpsmc.h"
 
 #include <algorithm>
@@ -331,7 +332,8 @@ struct hpsmc_plan {
     void *alloc_ctx = nullptr;
     int64_t ainv_off = 0;                // nodal -> phi-coefficient matrix A = Phi^{-1} (n x n)
     std::vector<double> t_breaks;
-    std::vector<int32_t> degree, nstar;
+    std::vector<int32_t> degree, nstar;   // N* resolved at creation (explicit array or the rule)
+    std::vector<double> dt_max;           // per interval: the rule's step bound (0: explicit array)
     std::vector<double> ic_data;
     int d = 0, n = 0, P = 0, PP = 0, n_iv = 0, n_inst = 0;
     int64_t nsp = 0, psp = 0;   // n^d, P^d
@@ -366,6 +368,9 @@ struct hpsmc_plan {
     bool frac = false;
     double *frac_tab = nullptr;
     int32_t frac_kmax = 0, frac_K = 0, frac_nt = 0;
+    // polynomial source: per interval [P^d][T1] tensor-Legendre coefficients
+    double *src_poly = nullptr;
+    std::vector<int64_t> src_off;
     double frac_half = 0.0, frac_lpb1 = 0.0, frac_lpb2 = 0.0;
     bool capturing = false;
     hipStream_t own_stream = nullptr;
@@ -462,7 +467,16 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     if (pb->n < 1 || pb->n > kMaxN) return fail(HPSMC_EINVAL, "n must be 1..32");
     if (pb->n_intervals < 1 || pb->n_intervals > 255) return fail(HPSMC_EINVAL, "n_intervals must be 1..255");
     if (pb->n_instances < 1 || pb->n_instances > 65535) return fail(HPSMC_EINVAL, "n_instances must be 1..65535");
-    if (!pb->t_breaks || !pb->degree || !pb->nstar) return fail(HPSMC_EINVAL, "t_breaks/degree/nstar is NULL");
+    if (pb->nstar_mode < HPSMC_NSTAR_ARRAY || pb->nstar_mode > HPSMC_NSTAR_SPECTRAL)
+        return fail(HPSMC_EINVAL, "unknown nstar_mode");
+    if (!pb->t_breaks || !pb->degree || (pb->nstar_mode == HPSMC_NSTAR_ARRAY && !pb->nstar))
+        return fail(HPSMC_EINVAL, "t_breaks/degree/nstar is NULL");
+    if (pb->nstar_mode != HPSMC_NSTAR_ARRAY && (pb->nstar_min < 0 || pb->nstar_min >= (1 << 24)))
+        return fail(HPSMC_EINVAL, "nstar_min must be 0 (4) .. 2^24-1");
+    if (pb->nstar_mode == HPSMC_NSTAR_DT && !(std::isfinite(pb->dt_max) && pb->dt_max > 0.0))
+        return fail(HPSMC_EINVAL, "dt_max must be finite and > 0");
+    if (pb->nstar_mode == HPSMC_NSTAR_SPECTRAL && !(std::isfinite(pb->nstar_c) && pb->nstar_c >= 0.0))
+        return fail(HPSMC_EINVAL, "nstar_c must be finite and >= 0 (0 selects 0.25)");
     for (int i = 0; i <= pb->n_intervals; ++i)
         if (!std::isfinite(pb->t_breaks[i])) return fail(HPSMC_EINVAL, "t_breaks must be finite");
     for (int i = 0; i < pb->n_intervals; ++i) {
@@ -471,12 +485,13 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     }
     int64_t tot = 0;
     for (int i = 0; i < pb->n_intervals; ++i) tot += pb->degree[i];
-    for (int64_t k = 0; k < tot; ++k)
-        if (pb->nstar[k] < 1 || pb->nstar[k] >= (1 << 24)) return fail(HPSMC_EINVAL, "nstar must be 1..2^24-1");
+    if (pb->nstar_mode == HPSMC_NSTAR_ARRAY)
+        for (int64_t k = 0; k < tot; ++k)
+            if (pb->nstar[k] < 1 || pb->nstar[k] >= (1 << 24)) return fail(HPSMC_EINVAL, "nstar must be 1..2^24-1");
     if (pb->M < 1 || pb->M > (int64_t)0xFFFFFFFFll) return fail(HPSMC_EINVAL, "M must be 1..2^32-1");
     if (pb->iters < 1 || pb->iters > 255) return fail(HPSMC_EINVAL, "iters must be 1..255");
     if (pb->f_kind < 0 || pb->f_kind > 5) return fail(HPSMC_EINVAL, "unknown f_kind");
-    if (pb->src_kind < 0 || pb->src_kind > 7) return fail(HPSMC_EINVAL, "unknown src_kind");
+    if (pb->src_kind < 0 || pb->src_kind > HPSMC_SRC_POLY) return fail(HPSMC_EINVAL, "unknown src_kind");
     if (!std::isfinite(pb->alpha) || pb->alpha < 0.0 || pb->alpha > 2.0)
         return fail(HPSMC_EINVAL, "alpha must be 0 (the Laplacian) or in (0, 2]");
     if (is_frac(*pb)) {
@@ -487,8 +502,22 @@ static hpsmc_status validate(const hpsmc_problem *pb)
             return fail(HPSMC_ENOTSUP, "the fractional form takes the centre-point rule");
         if (pb->ic_kind != HPSMC_IC_EXACT && pb->ic_kind != HPSMC_IC_NODAL)
             return fail(HPSMC_ENOTSUP, "the fractional form takes IC_EXACT or IC_NODAL");
-    } else if (pb->src_kind >= HPSMC_SRC_FRAC_LONGTIME) {
+    } else if (pb->src_kind >= HPSMC_SRC_FRAC_LONGTIME && pb->src_kind <= HPSMC_SRC_FRAC_POLY) {
         return fail(HPSMC_EINVAL, "fractional sources need 0 < alpha < 2");
+    }
+    if (pb->src_kind == HPSMC_SRC_POLY) {
+        if (is_frac(*pb)) return fail(HPSMC_ENOTSUP, "the polynomial source is built for the Laplacian");
+        if (pb->estimator != HPSMC_EST_RESIDUAL)
+            return fail(HPSMC_ENOTSUP, "the polynomial source enters the residual form's v* slab only");
+        if (!pb->src_coeffs) return fail(HPSMC_EINVAL, "src_coeffs is NULL");
+        const int64_t P = pb->n + 2;
+        int64_t len = 0, pd = 1;
+        for (int i = 0; i < pb->dim; ++i) pd *= P;
+        for (int i = 0; i < pb->n_intervals; ++i) len += pd * (pb->degree[i] + 1);
+        if (pb->src_len != len) return fail(HPSMC_EINVAL, "src_len must be sum_n (n+2)^dim (M_n+1)");
+        for (int64_t k = 0; k < len; ++k)
+            if (!std::isfinite(pb->src_coeffs[k])) return fail(HPSMC_EINVAL, "src_coeffs must be finite");
+        if (pb->ic_kind == HPSMC_IC_EXACT) return fail(HPSMC_EINVAL, "the polynomial source has no exact solution");
     }
     if (pb->ic_kind < 0 || pb->ic_kind > 3) return fail(HPSMC_EINVAL, "unknown ic_kind");
     if (pb->schedule < 0 || pb->schedule > 1) return fail(HPSMC_EINVAL, "unknown schedule");
@@ -567,7 +596,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     const int d = plan->d;
     set.ivs = ivs;
     set.host.clear();
-    std::vector<int64_t> coef_off, slab_off, slab_off_mma;
+    std::vector<int64_t> coef_off, slab_off, slab_off_mma, src_goff;
     std::vector<double> span, delta, h2;
     std::vector<int32_t> nst, deg;
     const int64_t rows = ipow(plan->P, d - 1);
@@ -590,6 +619,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
                 const double dl = sp / ns;
                 const int g = (int)coef_off.size();
                 coef_off.push_back(plan->c_off[iv] + (int64_t)inst * plan->psp * (M + 1));
+                src_goff.push_back(plan->src_poly ? plan->src_off[iv] : 0);
                 slab_off.push_back(slab_pos);
                 slab_off_mma.push_back(slab_pos_mma);
                 span.push_back(sp);
@@ -659,7 +689,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     hpsmc_status st;
     if ((st = dalloc(plan, (void **)&set.dev, sizeof(NodeDesc) * set.n))) return st;
     const size_t G = set.n_groups;
-    const size_t gbytes = G * (3 * sizeof(int64_t) + 3 * sizeof(double) + 2 * sizeof(int32_t));
+    const size_t gbytes = G * (4 * sizeof(int64_t) + 3 * sizeof(double) + 2 * sizeof(int32_t));
     if ((st = dalloc(plan, &set.group_mem, gbytes))) return st;
     std::vector<char> gh(gbytes);
     char *p = gh.data();
@@ -668,6 +698,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     put(span.data(), G * 8); put(delta.data(), G * 8); put(h2.data(), G * 8);
     put(nst.data(), G * 4); put(deg.data(), G * 4);
     put(slab_off_mma.data(), G * 8);
+    put(src_goff.data(), G * 8);
     if (hipMemcpy(set.group_mem, gh.data(), gbytes, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(set.dev, set.host.data(), sizeof(NodeDesc) * set.n, hipMemcpyHostToDevice) != hipSuccess)
         return fail(HPSMC_EDEVICE, "upload of node descriptors failed");
@@ -683,6 +714,8 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     sa.nstar = (const int32_t *)(gb + G * 40);
     sa.deg = (const int32_t *)(gb + G * 44);
     sa.slab_off_mma = mma_ok ? (const int64_t *)(gb + G * 48) : nullptr;
+    sa.cs = plan->src_poly;
+    sa.cs_off = (const int64_t *)(gb + G * 56);
     sa.mma_stride = mstride;
     sa.layout = 0;
     sa.extra = extra;
@@ -748,6 +781,140 @@ static std::vector<double> frac_nodal_to_modal(const std::vector<double> &x, con
         for (int p = 0; p < n; ++p) M[(size_t)p * n + j] = Pv[p] * w[j] / (wt * jacobi_norm2(p, a));
     }
     return M;
+}
+
+// ---------------------------------------------------------------------------
+// Path lengths N* (eq. time division: N* depends on h_n and l).  The residual
+// estimator weighs the node itself with Delta, so a nodal error mode of the
+// interval's discrete operator A_h = d_t - Lap_h (or d_t + (-Lap)^{alpha/2}_h)
+// with eigenvalue lambda is scaled by about (1 - Delta lambda) per iteration;
+// the rule keeps Delta_{n,l} <= c / rho(A_h).  A_h is the Kronecker sum of the
+// temporal collocation derivative (2/h) D_t on the Lobatto times l >= 1
+// (column 0 is held) and d copies of the spatial collocation operator K
+// (-Lap_h, or the fractional Laplacian, on the Jacobi-Gauss nodes).  Its
+// eigenvalues are (2/h) mu_j + sum_i kappa_i; K has real positive eigenvalues
+// and D_t eigenvalues of positive real part, so the largest modulus takes
+// kappa_i = rho(K) in every dimension: rho(A_h) = max_j |(2/h) mu_j + d rho(K)|.
+// rho(K) comes from Gelfand's formula (||K^m||^{1/m}, m = 2^k by repeated
+// squaring; K is close enough to normal for it); the mu_j of D_t, whose
+// eigen-problem is too ill-conditioned for double precision at high degree,
+// come from a table computed once at 60 digits (gen_lobatto_eigs.py).
+// ---------------------------------------------------------------------------
+static_assert(kLobattoEigMaxDeg >= kMaxDeg, "the Lobatto eigenvalue table must cover every temporal degree");
+
+static double spectral_radius(std::vector<double> A, int n)
+{
+    auto fro = [](const std::vector<double> &B) {
+        double s = 0.0;
+        for (double v : B) s += v * v;
+        return std::sqrt(s);
+    };
+    double c = fro(A);
+    if (!(c > 0.0) || !std::isfinite(c)) return c > 0.0 ? c : 0.0;
+    for (double &v : A) v /= c;
+    // A^{2^k} = prod_j c_j^{2^{k-j}} A_k with ||A_k|| = 1: log rho ~ sum_j 2^{-j} log c_j
+    double logr = std::log(c), scale = 1.0;
+    std::vector<double> B((size_t)n * n);
+    for (int k = 1; k <= 64; ++k) {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double t = 0.0;
+                for (int m = 0; m < n; ++m) t += A[(size_t)i * n + m] * A[(size_t)m * n + j];
+                B[(size_t)i * n + j] = t;
+            }
+        const double c2 = fro(B);
+        if (!(c2 > 0.0)) return 0.0;   // nilpotent
+        scale *= 0.5;
+        const double inc = scale * std::log(c2);
+        logr += inc;
+        for (double &v : B) v /= c2;
+        std::swap(A, B);
+        if (k >= 12 && std::fabs(inc) < 1e-18) break;
+    }
+    return std::exp(logr);
+}
+
+// spatial collocation operator on the n nodes: -Lap_h in one dimension
+// (Legendre route: nodal -> Legendre coefficients of phi-space interpolant,
+// second derivative, values at the nodes), or the fractional Laplacian
+// (nodal -> Jacobi coefficients of u/w, eigenvalues lambda_p, values of P_p)
+static std::vector<double> spatial_operator(const hpsmc_problem &pb, const std::vector<double> &x,
+                                            const std::vector<double> &w)
+{
+    const int n = (int)x.size();
+    std::vector<double> K((size_t)n * n, 0.0);
+    if (is_frac(pb)) {
+        const double a = 0.5 * pb.alpha;
+        const auto G = frac_nodal_to_modal(x, w, a);
+        std::vector<double> A, C, Pv(n);
+        jacobi_rec(n, a, A, C);
+        for (int m = 0; m < n; ++m) {
+            jacobi_values(n, A, C, x[m], Pv.data());
+            for (int p = 0; p < n; ++p) {
+                const double lp = std::exp(std::lgamma(p + pb.alpha + 1.0) - std::lgamma(p + 1.0)) * Pv[p];
+                for (int j = 0; j < n; ++j) K[(size_t)m * n + j] += lp * G[(size_t)p * n + j];
+            }
+        }
+        return K;
+    }
+    const int P = n + 2;
+    const auto G = spatial_to_legendre(x, P);
+    const auto D2 = legendre_d2(P);
+    std::vector<double> DG((size_t)P * n, 0.0), L(P + 1);
+    for (int k = 0; k < P; ++k)
+        for (int m = 0; m < P; ++m)
+            if (D2[(size_t)k * P + m] != 0.0)
+                for (int j = 0; j < n; ++j) DG[(size_t)k * n + j] += D2[(size_t)k * P + m] * G[(size_t)m * n + j];
+    for (int m = 0; m < n; ++m) {
+        legendre_values(P, x[m], L.data());
+        for (int k = 0; k < P; ++k)
+            for (int j = 0; j < n; ++j) K[(size_t)m * n + j] -= L[k] * DG[(size_t)k * n + j];
+    }
+    return K;
+}
+
+// N* of every node time l >= 1 of every interval, and the step bound per
+// interval (0 for explicit arrays)
+static hpsmc_status resolve_nstar(const hpsmc_problem &pb, std::vector<int32_t> &nstar, std::vector<double> &dt_max)
+{
+    const int NH = pb.n_intervals;
+    int64_t tot = 0;
+    for (int i = 0; i < NH; ++i) tot += pb.degree[i];
+    nstar.clear();
+    dt_max.assign(NH, 0.0);
+    if (pb.nstar_mode == HPSMC_NSTAR_ARRAY) {
+        nstar.assign(pb.nstar, pb.nstar + tot);
+        return HPSMC_OK;
+    }
+    const int nmin = pb.nstar_min > 0 ? pb.nstar_min : 4;
+    double kappa = 0.0;
+    if (pb.nstar_mode == HPSMC_NSTAR_SPECTRAL) {
+        std::vector<double> x, w;
+        if (is_frac(pb)) gauss_jacobi_aa(pb.n, 0.5 * pb.alpha, x, w);
+        else jacobi_gauss11(pb.n, x, w);
+        kappa = (is_frac(pb) ? 1.0 : (double)pb.dim) * spectral_radius(spatial_operator(pb, x, w), pb.n);
+    }
+    for (int iv = 0; iv < NH; ++iv) {
+        const int M = pb.degree[iv];
+        const double h = pb.t_breaks[iv + 1] - pb.t_breaks[iv];
+        std::vector<double> xi, wt;
+        lobatto(M, xi, wt);
+        double dt = pb.dt_max;
+        if (pb.nstar_mode == HPSMC_NSTAR_SPECTRAL) {
+            double rho = 0.0;
+            for (int k = kLobattoEigOff[M]; k < kLobattoEigOff[M + 1]; ++k)
+                rho = std::max(rho, std::hypot(2.0 / h * kLobattoEig[k][0] + kappa, 2.0 / h * kLobattoEig[k][1]));
+            dt = (pb.nstar_c > 0.0 ? pb.nstar_c : 0.25) / rho;
+        }
+        dt_max[iv] = dt;
+        for (int l = 1; l <= M; ++l) {
+            // a quotient within rounding of an integer is not carried to the next one
+            const double steps = std::ceil((1.0 - 1e-12) * 0.5 * (xi[l] + 1.0) * h / dt);
+            if (!(steps < (double)(1 << 24))) return fail(HPSMC_EINVAL, "the path-length rule gives N* >= 2^24");
+            nstar.push_back(std::max(nmin, (int32_t)steps));
+        }
+    }
+    return HPSMC_OK;
 }
 
 // tables of the fractional round kernel: recurrence, eigenvalues, the source
@@ -870,7 +1037,7 @@ static Physics physics_of(const hpsmc_plan *plan)
     Physics ph{};
     ph.dim = plan->d;
     ph.f_kind = plan->pb.f_kind;
-    ph.src_kind = plan->pb.src_kind;
+    ph.src_kind = plan->pb.src_kind == HPSMC_SRC_POLY ? HPSMC_SRC_NONE : plan->pb.src_kind;   // in the v slab
     ph.picard = plan->pb.estimator == HPSMC_EST_PICARD;
     ph.ball = plan->pb.quad == HPSMC_QUAD_BALL;
     ph.frac = plan->frac ? 1 : 0;
@@ -1045,7 +1212,7 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
     a.stats = plan->counters + 1;
     a.phys.dim = plan->d;
     a.phys.f_kind = plan->pb.f_kind;
-    a.phys.src_kind = plan->pb.src_kind;
+    a.phys.src_kind = plan->pb.src_kind == HPSMC_SRC_POLY ? HPSMC_SRC_NONE : plan->pb.src_kind;
     memcpy(a.phys.f_param, plan->pb.f_param, sizeof(a.phys.f_param));
     memcpy(a.phys.src_param, plan->pb.src_param, sizeof(a.phys.src_param));
     const int blocks = std::max(1, plan->cus * plan->launch.blocks_per_cu);
@@ -1100,7 +1267,7 @@ void hpsmc_destroy(hpsmc_plan *plan)
     void *ptrs[] = {plan->U, plan->cu, plan->cv, plan->tmp0, plan->tmp1, plan->ic, plan->mats,
                     plan->slab_table, plan->part, plan->counters, plan->maxbits, plan->hist_u, plan->hist_v,
                     plan->lam, plan->cbar_u, plan->cbar_v, plan->dtarget, plan->dloss, plan->dgrad, plan->slab_bar,
-                    plan->frac_tab};
+                    plan->frac_tab, plan->src_poly};
     for (void *p : ptrs) dfree(plan, p);
     delete plan;
 }
@@ -1131,14 +1298,15 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
     plan->fp32 = pb->precision == HPSMC_FP32_SAMPLING;
     plan->t_breaks.assign(pb->t_breaks, pb->t_breaks + pb->n_intervals + 1);
     plan->degree.assign(pb->degree, pb->degree + pb->n_intervals);
-    int64_t tot = 0;
-    for (int d : plan->degree) tot += d;
-    plan->nstar.assign(pb->nstar, pb->nstar + tot);
+    std::vector<double> dtm;
+    if ((st = resolve_nstar(*pb, plan->nstar, dtm))) return st;
+    plan->dt_max = dtm;
     if (pb->ic_data && (pb->ic_kind == HPSMC_IC_PHI || pb->ic_kind == HPSMC_IC_NODAL))
         plan->ic_data.assign(pb->ic_data, pb->ic_data + (size_t)pb->n_instances * plan->nsp);
     plan->pb.t_breaks = plan->t_breaks.data();
     plan->pb.degree = plan->degree.data();
     plan->pb.nstar = plan->nstar.data();
+    plan->pb.nstar_mode = HPSMC_NSTAR_ARRAY;   // resolved
     plan->pb.ic_data = plan->ic_data.empty() ? nullptr : plan->ic_data.data();
 
     // grid
@@ -1184,6 +1352,17 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
     if ((st = dalloc(pl, (void **)&pl->counters, 4 * 8))) return st;
     if ((st = dalloc(pl, (void **)&pl->maxbits, 4096 * 8))) return st;
     if (pl->frac && (st = frac_tables(pl))) return st;
+    if (pb->src_kind == HPSMC_SRC_POLY) {
+        int64_t off = 0;
+        for (int iv = 0; iv < plan->n_iv; ++iv) {
+            plan->src_off.push_back(off);
+            off += plan->psp * (plan->degree[iv] + 1);
+        }
+        if ((st = dalloc(pl, (void **)&pl->src_poly, off * 8))) return st;
+        if (hipMemcpy(pl->src_poly, pb->src_coeffs, off * 8, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(HPSMC_EDEVICE, "source coefficient upload failed");
+        plan->pb.src_coeffs = nullptr;   // the caller's array is not kept
+    }
 
     // transform matrices
     std::vector<double> mats;
@@ -1304,6 +1483,28 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
         if (!(p)) return fail(HPSMC_EINVAL, "plan is NULL");                     \
         if ((p)->poisoned) return fail(HPSMC_EDEVICE, "plan is poisoned");       \
     } while (0)
+
+hpsmc_status hpsmc_resolve_nstar(const hpsmc_problem *pb, int32_t *nstar, double *dt_max)
+{
+    if (!nstar) return fail(HPSMC_EINVAL, "nstar is NULL");
+    hpsmc_status st = validate(pb);
+    if (st) return st;
+    std::vector<int32_t> ns;
+    std::vector<double> dtm;
+    if ((st = resolve_nstar(*pb, ns, dtm))) return st;
+    std::copy(ns.begin(), ns.end(), nstar);
+    if (dt_max) std::copy(dtm.begin(), dtm.end(), dt_max);
+    return HPSMC_OK;
+}
+
+hpsmc_status hpsmc_get_nstar(const hpsmc_plan *plan, int32_t *nstar, double *dt_max)
+{
+    CHECK_PLAN(plan);
+    if (!nstar) return fail(HPSMC_EINVAL, "nstar is NULL");
+    std::copy(plan->nstar.begin(), plan->nstar.end(), nstar);
+    if (dt_max) std::copy(plan->dt_max.begin(), plan->dt_max.end(), dt_max);
+    return HPSMC_OK;
+}
 
 hpsmc_status hpsmc_grid(const hpsmc_plan *plan, int32_t iv, double *x_nodes, double *t_nodes)
 {

@@ -119,6 +119,9 @@ struct AdjointArgs {
 // One group = one (instance, interval, node time l).
 struct SlabArgs {
     const double *cu, *cv;       // Legendre tensors, blocks of [P^d][T1]
+    const double *cs;            // polynomial source, blocks of [P^d][T1] per interval (null: none);
+                                 // added to v in the contraction
+    const int64_t *cs_off;       // per group: offset of its interval's source block
     const int64_t *coef_off;     // per group: offset of its (inst, iv) coefficient block
     const int64_t *slab_off;     // per group: offset of its q = 0 slab in the table (row layout)
     const int64_t *slab_off_mma; // the same in the matrix-core layout (null when not available)

@@ -320,6 +320,7 @@ __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
     const int64_t base = mma ? a.slab_off_mma[g] : a.slab_off[g];
     T *table = (T *)a.slab_table;
     const double *cu = a.cu + a.coef_off[g], *cv = a.cv + a.coef_off[g];
+    const double *cs = a.cs ? a.cs + a.cs_off[g] : nullptr;   // polynomial source, folded into v
     const double span = a.span[g], delta = a.delta[g], h2 = a.h2[g];
     for (int q0 = blockIdx.x * kSlabQ; q0 < nq; q0 += gridDim.x * kSlabQ) {
         const int qn = min(kSlabQ, nq - q0);
@@ -355,6 +356,12 @@ __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
                 const double *cp = (uv ? cv : cu) + (row * a.P + kl) * T1;
 #pragma unroll
                 for (int k = 0; k <= kMaxDeg; ++k) c[k] = k < T1 ? cp[k] : 0.0;
+                if (uv && cs) {
+                    const double *sp = cs + (row * a.P + kl) * T1;
+#pragma unroll
+                    for (int k = 0; k <= kMaxDeg; ++k)
+                        if (k < T1) c[k] += sp[k];
+                }
             }
             const double sc = mma && live ? c_rec.mu[kl] * c_rec.mu[row] : 1.0;   // coefficients of Q_{k0} Q_{k1}
             for (int j = 0; j < qn; ++j) {

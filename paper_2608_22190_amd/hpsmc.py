@@ -21,13 +21,14 @@ LIB_PATH = os.path.join(_HERE, "libhpsmc.so")
 
 F_KINDS = {"affine": 0, "u_minus_u3": 1, "sin": 2, "u2_over_1pu2": 3, "neg_u3": 4, "u_sin_u": 5}
 SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4, "frac_longtime": 5,
-             "frac_singular": 6, "frac_poly": 7}
+             "frac_singular": 6, "frac_poly": 7, "poly": 8}
 IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
 SCHEDULES = {"sequential": 0, "sweeps": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1}
 ESTIMATORS = {"residual": 0, "picard": 1}
 ACCELS = {"none": 0, "aitken": 1}
 QUADS = {"centre": 0, "ball": 1}
+NSTAR_MODES = {"array": 0, "dt": 1, "spectral": 2}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOTSUP", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED", -6: "ENOTCONVERGED"}
 ENOTCONVERGED = -6
 
@@ -48,6 +49,8 @@ class hpsmc_problem(C.Structure):
         ("M", C.c_int64), ("iters", C.c_int32), ("fresh_per_iter", C.c_int32), ("seed", C.c_uint64),
         ("precision", C.c_int32), ("estimator", C.c_int32), ("tol", C.c_double),
         ("accel", C.c_int32), ("quad", C.c_int32), ("omega", C.c_double * 3), ("alpha", C.c_double),
+        ("nstar_mode", C.c_int32), ("nstar_min", C.c_int32), ("nstar_c", C.c_double), ("dt_max", C.c_double),
+        ("src_coeffs", C.POINTER(C.c_double)), ("src_len", C.c_int64),
     ]
 
 
@@ -73,6 +76,8 @@ _SIGS = {
     "hpsmc_create": (C.c_int, [C.POINTER(hpsmc_problem), C.POINTER(C.c_void_p)]),
     "hpsmc_destroy": (None, [C.c_void_p]),
     "hpsmc_grid": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "hpsmc_resolve_nstar": (C.c_int, [C.POINTER(hpsmc_problem), C.c_void_p, C.c_void_p]),
+    "hpsmc_get_nstar": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "hpsmc_solve": (C.c_int, [C.c_void_p, C.c_void_p]),
     "hpsmc_start_interval": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "hpsmc_iterate": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
@@ -162,13 +167,22 @@ def make_problem(wl):
     """hpsmc_problem from a workload description; returns (struct, keep-alive list)."""
     tb = np.ascontiguousarray(wl.t_breaks, dtype=np.float64)
     deg = np.ascontiguousarray(wl.degree, dtype=np.int32)
-    ns = np.ascontiguousarray(wl.nstar, dtype=np.int32)
+    mode = NSTAR_MODES[getattr(wl, "nstar_mode", "array")]
+    ns = np.ascontiguousarray(wl.nstar, dtype=np.int32) if mode == NSTAR_MODES["array"] else None
+    sc = getattr(wl, "src_coeffs", None)
+    sc = None if sc is None else np.ascontiguousarray(sc, dtype=np.float64).reshape(-1)
     ic = None if wl.ic_data is None else np.ascontiguousarray(wl.ic_data, dtype=np.float64).reshape(-1)
     p = hpsmc_problem()
     p.dim, p.n, p.n_intervals, p.n_instances = wl.dim, wl.n, len(wl.degree), wl.n_instances
     p.t_breaks = tb.ctypes.data_as(C.POINTER(C.c_double))
     p.degree = deg.ctypes.data_as(C.POINTER(C.c_int32))
-    p.nstar = ns.ctypes.data_as(C.POINTER(C.c_int32))
+    p.nstar = ns.ctypes.data_as(C.POINTER(C.c_int32)) if ns is not None else C.POINTER(C.c_int32)()
+    p.nstar_mode = mode
+    p.nstar_min = int(getattr(wl, "nstar_min", 0))
+    p.nstar_c = float(getattr(wl, "nstar_c", 0.0))
+    p.dt_max = float(getattr(wl, "dt_max", 0.0))
+    p.src_coeffs = sc.ctypes.data_as(C.POINTER(C.c_double)) if sc is not None else C.POINTER(C.c_double)()
+    p.src_len = 0 if sc is None else sc.size
     p.f_kind, p.src_kind, p.ic_kind = F_KINDS[wl.f], SRC_KINDS[wl.src], IC_KINDS[wl.ic]
     p.schedule = SCHEDULES[wl.schedule]
     for i, v in enumerate(wl.f_param):
@@ -187,7 +201,17 @@ def make_problem(wl):
     p.alpha = float(getattr(wl, "alpha", 2.0))
     for i, v in enumerate(getattr(wl, "omega", [0.0, 0.0, 0.0])):
         p.omega[i] = v
-    return p, [tb, deg, ns, ic]
+    return p, [tb, deg, ns, ic, sc]
+
+
+def resolve_nstar(wl):
+    """(N* per node time, Delta_max per interval) of a workload by the library's
+    rule, without a plan or a device (hpsmc_resolve_nstar)."""
+    p, keep = make_problem(wl)
+    out = np.zeros(sum(wl.degree), dtype=np.int32)
+    dt = np.zeros(len(wl.degree))
+    _check(lib().hpsmc_resolve_nstar(C.byref(p), _ptr(out), _ptr(dt)), "hpsmc_resolve_nstar")
+    return out, dt
 
 
 # ------------------------------------------------------------ C-ABI mirrors
@@ -262,6 +286,12 @@ class Plan:
         t = np.zeros(self.wl.degree[iv] + 1)
         _check(lib().hpsmc_grid(self.h, iv, _ptr(x), _ptr(t)), "hpsmc_grid")
         return x, t
+
+    def hpsmc_get_nstar(self):
+        out = np.zeros(sum(self.wl.degree), dtype=np.int32)
+        dt = np.zeros(len(self.wl.degree))
+        _check(lib().hpsmc_get_nstar(self.h, _ptr(out), _ptr(dt)), "hpsmc_get_nstar")
+        return out, dt
 
     def hpsmc_solve(self, stream=None):
         """Returns the status: OK, or ENOTCONVERGED (informational) in tolerance mode."""

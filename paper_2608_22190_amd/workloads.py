@@ -29,7 +29,7 @@ class Workload:
     n: int                      # Jacobi-Gauss (1,1) points per dimension
     t_breaks: List[float]       # time mesh t_0 < ... < t_Nh
     degree: List[int]           # temporal degree M_n per interval
-    nstar: List[int]            # N* per (interval, ell = 1..M_n), concatenated
+    nstar: Optional[List[int]] = None   # explicit N* per (interval, ell = 1..M_n), concatenated
     f: str = "u_minus_u3"
     f_param: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0, 0.0])
     src: str = "none"
@@ -51,6 +51,15 @@ class Workload:
     quad: str = "centre"        # path quadrature: "centre" (eq. interIQ) or "ball" (Green's-function ball point)
     alpha: float = 2.0          # order of the operator: 2 the Laplacian, (0, 2) the fractional Laplacian (d = 1)
     omega: List[float] = field(default_factory=lambda: [0.0, 0.0, 0.0])  # Aitken w0, w_min, w_max (0: default)
+    # path lengths (eq. time division): "array" takes `nstar`; the rules give
+    # N* = max(nstar_min, ceil((t_{n,l} - t_{n-1}) / Delta_max)) with Delta_max =
+    # nstar_c / rho(A_h) per interval ("spectral", rho the spectral radius of the
+    # interval's discrete operator, computed by the library at set-up) or dt_max ("dt")
+    nstar_mode: str = "spectral"
+    nstar_c: float = 0.25
+    nstar_min: int = 4
+    dt_max: float = 0.0
+    src_coeffs: Optional[np.ndarray] = None   # "poly" source: per interval [k_0..k_{d-1}][q], concatenated
 
     @property
     def n_intervals(self):
@@ -68,44 +77,14 @@ class Workload:
         return replace(self, **kw)
 
 
-# --------------------------------------------------------------------------
-# Path length rule.  The residual estimator evaluates the residual at the node
-# itself with weight Delta, so a nodal error mode with eigenvalue lambda of the
-# discrete operator d_t - Lap_h is multiplied by roughly (1 - Delta*lambda) in
-# each iteration; Delta is therefore kept below c / rho with rho a closed-form
-# upper estimate of the spectral radius of that operator on one interval:
-#   rho ~ d * 0.025 (n+2)^4  +  (2/h) * 0.1 (M+1)^2,
-# whose constants bound the measured radii for n <= 24, M <= 26.  The node
-# position uses the Chebyshev-Lobatto approximation (1 - cos(pi l/M))/2 of the
-# Lobatto point; only the integer N* matters and both implementations receive
-# the same integers.
-# --------------------------------------------------------------------------
-# With the fractional operator of order alpha < 2 (d = 1) the spatial part of
-# rho is 0.03 * 2^{2.7 (2 - alpha)} (n+2)^{2 alpha}, which bounds the measured
-# radii of the collocation operator for alpha in [0.4, 1.9], n <= 24.
-def rho_estimate(dim: int, n: int, M: int, h: float, alpha: float = 2.0) -> float:
-    space = dim * 0.025 * (n + 2) ** 4 if alpha >= 2.0 else 0.03 * 2 ** (2.7 * (2 - alpha)) * (n + 2) ** (2 * alpha)
-    return space + (2.0 / h) * 0.1 * (M + 1) ** 2
-
-
-def nstar_rule(dim, n, t_breaks, degree, c=0.25, nmin=4, nmax=(1 << 24) - 1, alpha=2.0):
-    out = []
-    for iv, M in enumerate(degree):
-        h = t_breaks[iv + 1] - t_breaks[iv]
-        dt_max = c / rho_estimate(dim, n, M, h, alpha)
-        for ell in range(1, M + 1):
-            frac = 0.5 * (1.0 - math.cos(math.pi * ell / M))
-            out.append(int(min(nmax, max(nmin, math.ceil(frac * h / dt_max)))))
-    return out
-
-
 def fixed_nstar(degree, value):
     return [int(value)] * sum(degree)
 
 
 def _mk(name, dim, n, t_breaks, degree, c=0.25, nmin=4, **kw):
+    """A workload whose path lengths follow the spectral rule with Delta_max = c / rho."""
     return Workload(name=name, dim=dim, n=n, t_breaks=list(t_breaks), degree=list(degree),
-                    nstar=nstar_rule(dim, n, t_breaks, degree, c=c, nmin=nmin, alpha=kw.get("alpha", 2.0)), **kw)
+                    nstar_mode="spectral", nstar_c=c, nstar_min=nmin, **kw)
 
 
 # --------------------------------------------------------------------------
@@ -210,5 +189,5 @@ def small(dim=1, n=6, M_deg=4, M=64, iters=2, f="u_minus_u3", src="sin_decay", i
     wl = _mk(f"small_d{dim}_n{n}", dim, n, tb, deg, c=c, nmin=nmin, f=f, src=src, ic=ic,
              M=M, iters=iters, **kw)
     if nstar is not None:
-        wl = wl.with_(nstar=fixed_nstar(deg, nstar))
+        wl = wl.with_(nstar=fixed_nstar(deg, nstar), nstar_mode="array")
     return wl

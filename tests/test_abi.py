@@ -31,7 +31,8 @@ def test_library_exports_every_declared_symbol():
     (dict(dim=0), -1), (dict(dim=6), -1), (dict(n=0), -1), (dict(n=33), -1), (dict(M=0), -1),
     (dict(iters=0), -1), (dict(iters=256), -1), (dict(t_breaks=[0.0, 0.0]), -1),
     (dict(t_breaks=[0.0, float("nan")]), -1), (dict(degree=[0]), -1), (dict(degree=[32]), -1),
-    (dict(f="affine", seed=1, nstar=[0, 3, 3, 3]), -1), (dict(nstar=[1 << 24] * 4), -1),
+    (dict(f="affine", seed=1, nstar=[0, 3, 3, 3], nstar_mode="array"), -1),
+    (dict(nstar=[1 << 24] * 4, nstar_mode="array"), -1), (dict(nstar_c=1e-9), -1), (dict(nstar_mode="dt"), -1),
     (dict(src="none", ic="exact"), -1), (dict(n_instances=0), -1), (dict(n_instances=65536), -1),
     (dict(dim=5, n=11), -2), (dict(dim=4, n=19), -2)])
 def test_invalid_problems_are_rejected_before_device_work(change, status):
@@ -105,3 +106,27 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[name]) == C.sizeof(cls), name
         for f in cls._fields_:
             assert int(got[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, (name, f[0])
+
+
+@pytest.mark.parametrize("change,status", [
+    (dict(src_coeffs=None), -1), (dict(src_len_delta=1), -1), (dict(estimator="picard"), -2),
+    (dict(ic="exact"), -1), (dict(alpha=0.5), -2), (dict(src_nan=True), -1)])
+def test_invalid_polynomial_sources_are_rejected(change, status):
+    import numpy as np
+    n, M = 3, 2
+    coeffs = np.zeros((n + 2) ** 2 * (M + 1))
+    wl = W.small(dim=2, n=n, M_deg=M, src="poly", ic="nodal", ic_data=np.zeros((1, n * n))).with_(src_coeffs=coeffs)
+    if "src_len_delta" in change:
+        wl = wl.with_(src_coeffs=np.zeros(coeffs.size + 1))
+    elif "src_nan" in change:
+        bad = coeffs.copy()
+        bad[3] = float("nan")
+        wl = wl.with_(src_coeffs=bad)
+    elif "alpha" in change:
+        wl = W.small(dim=1, n=n, M_deg=M, src="poly", ic="nodal", ic_data=np.zeros((1, n)), alpha=0.5).with_(
+            src_coeffs=np.zeros((n + 2) * (M + 1)))
+    else:
+        wl = wl.with_(**change)
+    with pytest.raises(H.HpsmcError) as ei:
+        H.resolve_nstar(wl)
+    assert ei.value.status == status

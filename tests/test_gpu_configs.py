@@ -129,7 +129,7 @@ def test_five_dim_fp32_r24_against_fp64():
     solution than e64 + 3 sigma, and within the noise of the FP64 result."""
     H = _hp()
     wl = W.small(dim=5, n=6, M_deg=3, M=64, iters=3, T=1.0, f="neg_u3", src="cos_decay")
-    _say("d5 r24", max(wl.nstar))
+    _say("d5 r24")
     res = {}
     for prec in ("fp64", "fp32"):
         with H.Plan(wl.with_(precision=prec)) as plan:
@@ -206,7 +206,7 @@ def test_initial_singularity_kh11_against_oracle_fp64_walks():
     sample count: matrix-core against vector-unit kernel per sample, and both
     against the oracle's FP64 walks."""
     wl = W.c3_initial_singularity(M=70, sweeps=1)
-    wl = wl.with_(t_breaks=wl.t_breaks[:5], degree=wl.degree[:4], nstar=wl.nstar[:sum(wl.degree[:4])])
+    wl = wl.with_(t_breaks=wl.t_breaks[:5], degree=wl.degree[:4])
     pb = O.Problem(wl)
     _say("kh11 sweep", wl.degree)
     rm = _sweep_run(wl, 1, 70, launch=(1, 4, 2, 64))

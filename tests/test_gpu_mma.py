@@ -31,7 +31,7 @@ def _say(*a):
 def test_mma_kernel_walks_the_vector_kernel_paths(n, deg, M):
     H = _hp()
     wl = W.small(dim=2, n=n, M_deg=deg, M=M, T=0.5, f="sin", src="longtime", precision="fp32")
-    _say("mma vs valu", n, deg, M, max(wl.nstar))
+    _say("mma vs valu", n, deg, M)
     U = np.random.default_rng(n).standard_normal((1, wl.nsp, deg + 1)) * 0.5
     mp = min(M, 8)
     res = {}

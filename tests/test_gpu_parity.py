@@ -36,7 +36,7 @@ def _random_nodes(wl, seed=0, scale=0.5):
 def test_one_iteration_increment_fp64(dim, n, deg, M, ns):
     H = _hp()
     wl = W.small(dim=dim, n=n, M_deg=deg, M=M, T=0.5, f="sin", src="longtime", c=0.25)
-    _say("increment", dim, n, deg, M, ns, max(wl.nstar))
+    _say("increment", dim, n, deg, M, ns)
     U = _random_nodes(wl, seed=dim)
     with H.Plan(wl) as plan:
         plan.hpsmc_set_launch(ns, 2, 4)
@@ -105,7 +105,7 @@ def test_sweeps_uneven_degrees_fp64():
     wl = W.small(dim=2, n=3, M_deg=[2, 3, 4], M=40, iters=4, n_intervals=3, f="u2_over_1pu2", src="none",
                  ic="singular", ic_param=[0.5, 0, 0, 0], schedule="sweeps")
     tb = [0.0, 0.04, 0.2, 1.0]
-    wl = wl.with_(t_breaks=tb, nstar=W.nstar_rule(2, 3, tb, [2, 3, 4]))
+    wl = wl.with_(t_breaks=tb)
     _say("sweeps")
     Uo, mxo = O.Problem(wl).solve()
     with H.Plan(wl) as plan:

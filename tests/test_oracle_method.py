@@ -213,7 +213,7 @@ def test_residual_form_removes_the_bias_the_picard_form_keeps():
         x, t = pb.grid(0)
         ex = np.array([[pb.exact([xj], tl) for tl in t] for xj in x])
         res[est] = np.max(np.abs(U[0].reshape(wl.nsp, -1) - ex))
-    J = math.sqrt(2 * 0.5 / max(wl.nstar))
+    J = math.sqrt(2 * 0.5 / max(O.nstar_rule(wl)))
     assert res["residual"] < 1e-3, res
     assert res["picard"] > 20 * res["residual"] and res["picard"] < 5 * J, (res, J)
 
