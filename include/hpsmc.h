@@ -260,6 +260,10 @@ hpsmc_status hpsmc_set_allocator(hpsmc_alloc_fn alloc, hpsmc_free_fn free_, void
 /* Validate the problem, compute the grid and transform matrices on the host,
  * allocate device memory, and write the initial iterate (the initial column
  * replicated in time, for interval 0 or for all intervals under SWEEPS).
+ * The set-up of Sec. 2.1 and 2.3: the Jacobi-Gauss nodes, the shifted Lobatto
+ * nodes of every interval, the nodal-to-modal matrices of eqs. spacelag and
+ * timeLag, the path lengths of eq. time division (resolved here when a rule
+ * is selected), and Algorithm 1's initial guess.
  * EINVAL on any out-of-range field; ENOTSUP for unsupported combinations. */
 hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out);
 void hpsmc_destroy(hpsmc_plan *plan);
@@ -298,11 +302,18 @@ hpsmc_status hpsmc_sweep(hpsmc_plan *plan, int32_t tag, void *stream);
 hpsmc_status hpsmc_get_nodes(const hpsmc_plan *plan, int32_t iv, double *out, int32_t on_device, void *stream);
 hpsmc_status hpsmc_set_nodes(hpsmc_plan *plan, int32_t iv, const double *in, int32_t on_device, void *stream);
 
-/* Last increment of interval iv: eps and sum of S^2 per node, [instance][node id]. */
+/* Last increment of interval iv: eps and sum of S^2 per node, [instance][node id]
+ * (host).  eps is the Monte Carlo average of eq. varepsilon_1 over the M sample
+ * paths of each node (the per-path values S_i of eq. interIQ); sum S_i^2 gives
+ * the node's standard error sqrt((sumsq/M - eps^2)/M).  Synchronizes the stream. */
 hpsmc_status hpsmc_get_increment(const hpsmc_plan *plan, int32_t iv, double *eps, double *sumsq, void *stream);
 
 /* Evaluate the current reconstruction of interval iv at npts points
- * pts[k] = (x_0..x_{d-1}, t) (host): out[k] = (u, Lap u - d_t u) (host). */
+ * pts[k] = (x_0..x_{d-1}, t) (host): out[k] = (u, Lap u - d_t u) (host) --
+ * the approximation u* of eq. u_N built from the nodal values the last
+ * iteration started from, and the operator part of the residual of eq. ufg_ep1
+ * (no nonlinearity, no source).  ENOTSUP for the fractional operator.
+ * Allocates two staging buffers per call (hpsmc_eval_noalloc does not). */
 hpsmc_status hpsmc_eval(hpsmc_plan *plan, int32_t iv, int32_t inst, const double *pts, int64_t npts,
                         double *out, void *stream);
 
@@ -333,7 +344,11 @@ hpsmc_status hpsmc_get_launch(const hpsmc_plan *plan, hpsmc_launch *l);
  * the JSON file `cache_path` if not NULL). */
 hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char *cache_path, void *stream);
 
-/* Counters accumulated since creation or the last reset (synchronizes). */
+/* Counters accumulated since creation or the last reset (synchronizes): the
+ * residual evaluations (the sum of the exit indices L of eq. indexL over all
+ * paths), the walk steps executed, and max|eps| per iteration -- the quantity
+ * of Algorithm 1's loop condition.  A solve overwrites the records it writes
+ * (record iv * iters + k of a sequential solve, k of a sweep solve). */
 hpsmc_status hpsmc_stats(const hpsmc_plan *plan, hpsmc_stats_t *out, void *stream);
 hpsmc_status hpsmc_reset_stats(hpsmc_plan *plan, void *stream);
 
@@ -348,7 +363,9 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
 
 /* Replace the initial data by nodal values u0 [instance][n^d] at the spatial
  * nodes (host or device per on_device); the next start of interval 0 (or of
- * every interval under SWEEPS) uses them.  EINVAL for IC_PHI plans (use
+ * every interval under SWEEPS) uses them: u(x, 0) = u_0 of eq. mainproblem,
+ * entering as column 0 of the first interval (Algorithm 1, Step 4 hands the
+ * last column on from there).  EINVAL for IC_PHI plans (use
  * hpsmc_set_initial_coeffs there).  Synchronizes the stream. */
 hpsmc_status hpsmc_set_initial_nodes(hpsmc_plan *plan, const double *u0, int32_t on_device, void *stream);
 
