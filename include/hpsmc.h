@@ -151,9 +151,19 @@ enum { HPSMC_NSTAR_ARRAY = 0,     /* the `nstar` array, one entry per node time 
                                      set-up                                       */
 
 enum { HPSMC_FP64 = 0,            /* everything in FP64                            */
-       HPSMC_FP32_SAMPLING = 1 }; /* paths and basis evaluation in FP32 with
+       HPSMC_FP32_SAMPLING = 1,   /* paths and basis evaluation in FP32 with
                                      compensated accumulation; reconstruction,
                                      increments, norms and stop test in FP64      */
+       HPSMC_FP32_THEN_FP64 = 2 };/* hpsmc_solve samples an interval (a sweep) in
+                                     FP32 until max|eps| < switch_tol, then goes on
+                                     in FP64 with the same counter tags (iteration
+                                     k draws the Philox words a plain FP64 solve
+                                     draws at k): FP32's throughput for the early
+                                     iterations, FP64's accuracy floor at the end.
+                                     The host reads max|eps| after every
+                                     iteration.  hpsmc_iterate / hpsmc_sweep run
+                                     in FP32; residual form, no Aitken relaxation,
+                                     no gradient                                  */
 
 typedef struct {
     int32_t dim;               /* 1..5, Omega = (-1,1)^dim                      */
@@ -208,6 +218,8 @@ typedef struct {
                                   prod_i L_{k_i}(x_i) L_q(xi), xi = 2(t -
                                   t_{n-1})/h_n - 1; shared by all instances      */
     int64_t src_len;           /* HPSMC_SRC_POLY: sum_n P^d (M_n+1)             */
+    double switch_tol;         /* HPSMC_FP32_THEN_FP64: max|eps| below which the
+                                  solve continues in FP64, > 0                  */
 } hpsmc_problem;
 
 typedef struct hpsmc_plan hpsmc_plan;

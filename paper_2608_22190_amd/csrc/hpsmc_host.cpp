@@ -340,6 +340,7 @@ struct hpsmc_plan {
     std::vector<double> x;      // spatial nodes
     std::vector<std::vector<double>> xi, tnodes;   // per interval: reference LGL nodes, t_{n,l}
     bool fp32 = false, poisoned = false;
+    hpsmc_plan *twin = nullptr;   // HPSMC_FP32_THEN_FP64: the FP64 plan the solve switches to
     int cus = 0;
     hpsmc_launch launch{2, 4, 8, 256};
     int32_t round_steps = 256;           // walk steps per round
@@ -521,7 +522,13 @@ static hpsmc_status validate(const hpsmc_problem *pb)
     }
     if (pb->ic_kind < 0 || pb->ic_kind > 3) return fail(HPSMC_EINVAL, "unknown ic_kind");
     if (pb->schedule < 0 || pb->schedule > 1) return fail(HPSMC_EINVAL, "unknown schedule");
-    if (pb->precision < 0 || pb->precision > 1) return fail(HPSMC_EINVAL, "unknown precision");
+    if (pb->precision < 0 || pb->precision > HPSMC_FP32_THEN_FP64) return fail(HPSMC_EINVAL, "unknown precision");
+    if (pb->precision == HPSMC_FP32_THEN_FP64) {
+        if (!(std::isfinite(pb->switch_tol) && pb->switch_tol > 0.0))
+            return fail(HPSMC_EINVAL, "switch_tol must be finite and > 0");
+        if (pb->estimator != HPSMC_EST_RESIDUAL || pb->accel != HPSMC_ACCEL_NONE)
+            return fail(HPSMC_ENOTSUP, "the precision switch covers the plain residual iteration");
+    }
     if (!std::isfinite(pb->tol) || pb->tol < 0.0) return fail(HPSMC_EINVAL, "tol must be finite and >= 0");
     if (pb->tol > 0.0 && pb->schedule == HPSMC_SEQUENTIAL && (int64_t)pb->n_intervals * pb->iters > 4096)
         return fail(HPSMC_EINVAL, "tolerance mode keeps one max|eps| record per (interval, iteration): "
@@ -1258,6 +1265,7 @@ const char *hpsmc_last_error(void) { return g_err.c_str(); }
 void hpsmc_destroy(hpsmc_plan *plan)
 {
     if (!plan) return;
+    if (plan->twin) hpsmc_destroy(plan->twin);
     if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->own_stream) (void)hipStreamDestroy(plan->own_stream);
@@ -1278,6 +1286,19 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
     *out = nullptr;
     hpsmc_status st = validate(pb);
     if (st) return st;
+    if (pb->precision == HPSMC_FP32_THEN_FP64) {
+        // an FP32 plan and its FP64 twin over the same problem
+        hpsmc_problem p32 = *pb, p64 = *pb;
+        p32.precision = HPSMC_FP32_SAMPLING;
+        p64.precision = HPSMC_FP64;
+        hpsmc_plan *main = nullptr, *twin = nullptr;
+        if ((st = hpsmc_create(&p32, &main))) return st;
+        if ((st = hpsmc_create(&p64, &twin))) { hpsmc_destroy(main); return st; }
+        main->twin = twin;
+        main->pb.precision = HPSMC_FP32_THEN_FP64;
+        *out = main;
+        return HPSMC_OK;
+    }
     std::unique_ptr<hpsmc_plan, void (*)(hpsmc_plan *)> plan(new hpsmc_plan, hpsmc_destroy);
     {
         std::lock_guard<std::mutex> lk(g_alloc_mutex);
@@ -1639,10 +1660,107 @@ static hpsmc_status solve_body(hpsmc_plan *plan, hipStream_t s)
     return HPSMC_OK;
 }
 
+// nodal values of interval iv from one plan into another of the same layout
+// (a plan and its twin)
+static hpsmc_status copy_interval(hpsmc_plan *dst, hpsmc_plan *src, int iv, hipStream_t s)
+{
+    const size_t bytes = (size_t)src->n_inst * src->nsp * (src->degree[iv] + 1) * 8;
+    if (hipMemcpyAsync(dst->U + dst->u_off[iv], src->U + src->u_off[iv], bytes, hipMemcpyDeviceToDevice, s) !=
+        hipSuccess) {
+        dst->poisoned = true;
+        return fail(HPSMC_EDEVICE, "copy between the FP32 plan and its FP64 twin failed");
+    }
+    return HPSMC_OK;
+}
+
+// HPSMC_FP32_THEN_FP64: Algorithm 1 (or the sweeps) as in solve_body, each
+// interval (the sweep sequence) sampled by the FP32 plan until max|eps| <
+// switch_tol and by the FP64 twin afterwards, with the counter tags running
+// on; the twin's max|eps| records are copied into the plan's, and the final
+// nodal values back into the plan.  Always eager: the switch needs the host.
+static hpsmc_status mixed_solve_body(hpsmc_plan *plan, hipStream_t s)
+{
+    hpsmc_status st;
+    hpsmc_plan *tw = plan->twin;
+    const int K = plan->pb.iters;
+    const double tol = plan->pb.tol, sw = plan->pb.switch_tol;
+    const bool seq = plan->pb.schedule == HPSMC_SEQUENTIAL;
+    const int64_t n_rec = std::min<int64_t>(4096, seq ? (int64_t)plan->n_iv * K : (int64_t)K);
+    HIP_TRY(launch_fill_u64(plan->maxbits, n_rec, 0ull, s));
+    HIP_TRY(launch_fill_u64(tw->maxbits, n_rec, 0ull, s));
+    auto step = [&](hpsmc_plan *p, int iv, int k, int rec, double *e) -> hpsmc_status {
+        const int tag = plan->pb.fresh_per_iter ? k : 0;
+        hpsmc_status r = seq ? iterate_impl(p, iv, tag, rec, s) : sweep_impl(p, tag, rec, s);
+        if (r || (r = read_record(p, rec, e, s))) return r;
+        if (p == tw) {
+            unsigned long long bits;
+            memcpy(&bits, e, 8);
+            if (hipMemcpyAsync(plan->maxbits + std::min(rec, 4095), &bits, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                plan->poisoned = true;
+                return fail(HPSMC_EDEVICE, "record copy failed");
+            }
+            plan->n_records = std::max(plan->n_records, std::min(rec, 4095) + 1);
+        }
+        return HPSMC_OK;
+    };
+    bool unconverged = false;
+    if (seq) {
+        for (int iv = 0; iv < plan->n_iv; ++iv) {
+            if ((st = start_interval(plan, iv, 1, s))) return st;
+            std::vector<double> hist;
+            bool in64 = false;
+            int k = 0;
+            for (; k < K; ++k) {
+                double e;
+                if ((st = step(in64 ? tw : plan, iv, k, iv * K + k, &e))) return st;
+                hist.push_back(e);
+                if (diverged(hist))
+                    return fail(HPSMC_EDIVERGED, "max|eps| diverged in interval " + std::to_string(iv) +
+                                                     ", iteration " + std::to_string(k));
+                if (tol > 0.0 && e < tol) break;
+                if (!in64 && e < sw) {
+                    if ((st = copy_interval(tw, plan, iv, s))) return st;
+                    in64 = true;
+                }
+            }
+            if (in64 && (st = copy_interval(plan, tw, iv, s))) return st;
+            if (tol > 0.0 && k == K) unconverged = true;
+        }
+    } else {
+        for (int iv = 0; iv < plan->n_iv; ++iv)
+            HIP_TRY(launch_start_columns(plan->U + plan->u_off[iv], plan->ic, 1, 0, plan->degree[iv] + 1,
+                                         plan->degree[iv] + 1, (int64_t)plan->n_inst * plan->nsp, 1, s));
+        std::vector<double> hist;
+        bool in64 = false;
+        int k = 0;
+        for (; k < K; ++k) {
+            double e;
+            if ((st = step(in64 ? tw : plan, 0, k, k, &e))) return st;
+            hist.push_back(e);
+            if (diverged(hist)) return fail(HPSMC_EDIVERGED, "max|eps| diverged at sweep " + std::to_string(k));
+            if (tol > 0.0 && e < tol) break;
+            if (!in64 && e < sw) {
+                for (int iv = 0; iv < plan->n_iv; ++iv)
+                    if ((st = copy_interval(tw, plan, iv, s))) return st;
+                in64 = true;
+            }
+        }
+        if (in64)
+            for (int iv = 0; iv < plan->n_iv; ++iv)
+                if ((st = copy_interval(plan, tw, iv, s))) return st;
+        if (tol > 0.0 && k == K) unconverged = true;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    if (unconverged) return fail(HPSMC_ENOTCONVERGED, "max|eps| stayed above tol after iters iterations");
+    return HPSMC_OK;
+}
+
 hpsmc_status hpsmc_solve(hpsmc_plan *plan, void *stream)
 {
     CHECK_PLAN(plan);
     hipStream_t s = (hipStream_t)stream;
+    if (plan->twin) return mixed_solve_body(plan, s);
     if (!plan->use_graph || plan->pb.tol > 0.0) return solve_body(plan, s);   // the stop test needs the host
     if (!plan->graph_exec) {
         // capture on a stream of the plan (the legacy default stream cannot be captured)
@@ -1896,6 +2014,20 @@ hpsmc_status hpsmc_stats(const hpsmc_plan *plan, hpsmc_stats_t *out, void *strea
     out->path_steps = c[1];
     out->lane_steps = c[2];
     out->node_samples = (uint64_t)plan->node_samples;
+    if (plan->twin) {   // the FP64 twin's share of the work
+        hpsmc_stats_t t;
+        if (hpsmc_status st = hpsmc_stats(plan->twin, &t, stream)) return st;
+        out->path_steps += t.path_steps;
+        out->lane_steps += t.lane_steps;
+        out->node_samples += t.node_samples;
+        out->sample_launches += t.sample_launches;
+        out->recon_launches += t.recon_launches;
+        out->sample_ms += t.sample_ms;
+        out->sampling_span_ms += t.sampling_span_ms;
+        out->recon_ms += t.recon_ms;
+        out->slab_ms += t.slab_ms;
+        out->advance_launches += t.advance_launches;
+    }
     out->n_records = plan->n_records;
     const int K = std::max(1, plan->pb.iters);
     for (int r = 0; r < plan->n_records; ++r) {
@@ -1914,6 +2046,8 @@ hpsmc_status hpsmc_stats(const hpsmc_plan *plan, hpsmc_stats_t *out, void *strea
 hpsmc_status hpsmc_reset_stats(hpsmc_plan *plan, void *stream)
 {
     CHECK_PLAN(plan);
+    if (plan->twin)
+        if (hpsmc_status st = hpsmc_reset_stats(plan->twin, stream)) return st;
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_fill_u64(plan->counters, 4, 0ull, s));
     HIP_TRY(launch_fill_u64(plan->maxbits, 4096, 0ull, s));
@@ -2001,6 +2135,8 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     if (iv < 0 || iv >= plan->n_iv) return fail(HPSMC_EINVAL, "interval out of range");
     if (m_tune < 0) return fail(HPSMC_EINVAL, "m_tune must be >= 0");
     if (plan->pb.schedule != HPSMC_SEQUENTIAL && iv != 0) return fail(HPSMC_EINVAL, "sweep plans tune interval 0");
+    if (plan->twin)   // the FP64 twin tunes its own launch shape (its own cache key)
+        if (hpsmc_status st = hpsmc_tune(plan->twin, iv, m_tune, cache_path, stream)) return st;
     const int64_t M_full = plan->pb.M;
     const int64_t mt = m_tune == 0 ? std::min<int64_t>(M_full, 256) : std::min<int64_t>(M_full, m_tune);
     const std::string key = tune_key(plan, iv, M_full);
@@ -2307,6 +2443,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
 {
     CHECK_PLAN(plan);
     if (!target || !loss || !grad) return fail(HPSMC_EINVAL, "NULL argument");
+    if (plan->twin) return fail(HPSMC_ENOTSUP, "no gradient under the precision switch");
     if (plan->n_iv != 1 || plan->pb.ic_kind != HPSMC_IC_PHI || plan->pb.schedule != HPSMC_SEQUENTIAL)
         return fail(HPSMC_EINVAL, "the gradient needs one interval, phi-coefficient initial data, sequential schedule");
     if (plan->d > 2 || plan->P > 32 || !plan->sets[0].rounds)

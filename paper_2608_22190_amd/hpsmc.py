@@ -24,7 +24,7 @@ SRC_KINDS = {"none": 0, "sin_decay": 1, "cos_decay": 2, "longtime": 3, "quad": 4
              "frac_singular": 6, "frac_poly": 7, "poly": 8}
 IC_KINDS = {"exact": 0, "singular": 1, "phi": 2, "nodal": 3}
 SCHEDULES = {"sequential": 0, "sweeps": 1}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "fp32_then_fp64": 2}
 ESTIMATORS = {"residual": 0, "picard": 1}
 ACCELS = {"none": 0, "aitken": 1}
 QUADS = {"centre": 0, "ball": 1}
@@ -50,7 +50,7 @@ class hpsmc_problem(C.Structure):
         ("precision", C.c_int32), ("estimator", C.c_int32), ("tol", C.c_double),
         ("accel", C.c_int32), ("quad", C.c_int32), ("omega", C.c_double * 3), ("alpha", C.c_double),
         ("nstar_mode", C.c_int32), ("nstar_min", C.c_int32), ("nstar_c", C.c_double), ("dt_max", C.c_double),
-        ("src_coeffs", C.POINTER(C.c_double)), ("src_len", C.c_int64),
+        ("src_coeffs", C.POINTER(C.c_double)), ("src_len", C.c_int64), ("switch_tol", C.c_double),
     ]
 
 
@@ -183,6 +183,7 @@ def make_problem(wl):
     p.dt_max = float(getattr(wl, "dt_max", 0.0))
     p.src_coeffs = sc.ctypes.data_as(C.POINTER(C.c_double)) if sc is not None else C.POINTER(C.c_double)()
     p.src_len = 0 if sc is None else sc.size
+    p.switch_tol = float(getattr(wl, "switch_tol", 0.0))
     p.f_kind, p.src_kind, p.ic_kind = F_KINDS[wl.f], SRC_KINDS[wl.src], IC_KINDS[wl.ic]
     p.schedule = SCHEDULES[wl.schedule]
     for i, v in enumerate(wl.f_param):

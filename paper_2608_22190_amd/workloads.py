@@ -43,7 +43,9 @@ class Workload:
     schedule: str = "sequential"
     n_instances: int = 1
     fresh_per_iter: bool = True
-    precision: str = "fp64"     # "fp64" or "fp32" (path sampling precision)
+    precision: str = "fp64"     # "fp64", "fp32" (path sampling precision), or "fp32_then_fp64" (FP32
+                                # until max|eps| < switch_tol, then FP64)
+    switch_tol: float = 0.0
     exact_known: bool = True
     tol: float = 0.0            # > 0: stop an interval once max|eps| < tol (Algorithm 1's loop condition)
     estimator: str = "residual" # "residual" (eq. varepsilon_1) or "picard" (eq. uast, classical MC form)
