@@ -34,7 +34,8 @@ METRIC = "node-samples/sec at fixed error vs exact; FP32-batched vs FP64 speedup
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "advance_mma_kernel_c2_fp32_m1024_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2608_22190_amd", "csrc", "hpsmc_kernels.hip")
+# the matrix-core round kernel's sources (its unit and the device helpers it includes)
+KERNEL_SRC = [os.path.join(ROOT, "paper_2608_22190_amd", "csrc", f) for f in ("hpsmc_kern_mma.hip", "hpsmc_device.h")]
 
 
 def measured_traffic(launch):
@@ -44,7 +45,10 @@ def measured_traffic(launch):
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for f in KERNEL_SRC:
+            h.update(open(f, "rb").read())
+        sha = h.hexdigest()
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256") != sha or list(rec.get("launch", [])) != list(launch):
@@ -62,10 +66,15 @@ def flops_per_eval(dim, P, picard=False):
     return (2 if picard else 4) * cont + 3 * dim * (P - 2)
 
 
-def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256):
+def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256, exact_fn=None):
+    """Warm up, then time `steps` residual iterations of interval 1 from the
+    replicated initial data.  With `exact_fn` (grid -> nodal values of the exact
+    solution), every timed iteration also records (seconds so far, max error against it,
+    max node standard error, max|eps|), read after its own timing stops."""
     from paper_2608_22190_amd import hpsmc
     stream = torch.cuda.Stream()
     with hpsmc.Plan(wl) as plan:
+        exact = exact_fn(plan.hpsmc_grid(0)) if exact_fn else None
         if launch:
             plan.hpsmc_set_launch(*launch)
         elif tune_cache:
@@ -82,15 +91,24 @@ def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256):
         plan.hpsmc_reset_stats(stream=stream)
         plan.hpsmc_start_interval(0, stream=stream)
         torch.cuda.synchronize()
+        traj, busy = [], 0.0
         t0 = time.perf_counter()
         for k in range(steps):
+            ts = time.perf_counter()
             plan.hpsmc_iterate(0, k, stream=stream)
-            if steps > 1:
+            if steps > 1 or exact is not None:
                 stream.synchronize()
-                print(f"[bench] {wl.precision} step {k + 1}/{steps} {time.perf_counter() - t0:.2f}s",
-                      file=sys.stderr, flush=True)
+                busy += time.perf_counter() - ts
+                print(f"[bench] {wl.precision} step {k + 1}/{steps} {busy:.2f}s", file=sys.stderr, flush=True)
+            if exact is not None:
+                Uk = plan.hpsmc_get_nodes(0, stream=stream)[0]
+                ek, sk = plan.hpsmc_get_increment(0, stream=stream)
+                sig_k = float(np.sqrt(np.maximum(sk / wl.M - ek ** 2, 0.0) / wl.M).max())
+                traj.append([busy, float(np.max(np.abs(Uk - exact))), sig_k, float(np.max(np.abs(ek)))])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        if exact is not None:
+            t1 = t0 + busy                 # the reads of the trajectory are not timed
         st = plan.hpsmc_stats(stream=stream)
         U = plan.hpsmc_get_nodes(0, stream=stream)
         grid = plan.hpsmc_grid(0)
@@ -98,7 +116,43 @@ def run_gpu(wl, steps, warmup, launch, torch, tune_cache=None, m_tune=256):
         lau = plan.hpsmc_get_launch()
         mma = plan.hpsmc_get_option("sample_mfma_active")
     sig = float(np.sqrt(np.maximum(ssq / wl.M - eps ** 2, 0.0) / wl.M).max())
-    return {"seconds": t1 - t0, "stats": st, "U": U, "sigma": sig, "launch": lau, "mma": mma, "grid": grid}
+    return {"seconds": t1 - t0, "stats": st, "U": U, "sigma": sig, "launch": lau, "mma": mma, "grid": grid,
+            "trajectory": traj}
+
+
+def run_switched_solve(wl, tol, switch_tol, torch, tune_cache=None):
+    """Algorithm 1 on interval 1 with the loop condition max|eps| < tol, FP32
+    sampling until max|eps| < switch_tol and FP64 after (one timed solve)."""
+    from paper_2608_22190_amd import hpsmc
+    stream = torch.cuda.Stream()
+    wl = wl.with_(precision="fp32_then_fp64", switch_tol=switch_tol, tol=tol)
+    with hpsmc.Plan(wl) as plan:
+        if tune_cache:
+            plan.hpsmc_tune(0, 256, tune_cache, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status = plan.hpsmc_solve(stream=stream)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        rec = plan.hpsmc_stats(stream=stream)["max_eps"]
+        U = plan.hpsmc_get_nodes(0, stream=stream)[0]
+        eps, ssq = plan.hpsmc_get_increment(0, stream=stream)
+        grid = plan.hpsmc_grid(0)
+    used = int(np.count_nonzero(rec))
+    switch = next((k + 1 for k, e in enumerate(rec[:used]) if e < switch_tol), None)
+    print(f"[bench] switched solve: {used} iterations ({switch} in FP32), {sec:.1f}s", file=sys.stderr, flush=True)
+    return {"seconds": sec, "status": int(status), "iterations": used, "fp32_iterations": switch, "U": U,
+            "grid": grid, "sigma": float(np.sqrt(np.maximum(ssq / wl.M - eps ** 2, 0.0) / wl.M).max()),
+            "max_eps": [float(e) for e in rec[:used]]}
+
+
+def time_to_error(traj, target, col=1):
+    """seconds until the first iteration whose column `col` (1: error against the
+    exact solution, 3: max|eps|) is below `target`, or None"""
+    for t, *vals in traj:
+        if vals[col - 1] < target:
+            return t
+    return None
 
 
 def long_time_exact(wl, grid):
@@ -584,6 +638,7 @@ def main():
     ap.add_argument("--m-slice", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-switch", action="store_true", help="skip the solve with the FP32 -> FP64 switch")
     ap.add_argument("--workload", type=str, default="c2", choices=["c1", "c2", "c2p", "c2b", "c3", "c4", "c5", "compare", "aitken",
                                                               "ballcmp", "frac", "fraccmp", "fracexp", "ex1"])
     ap.add_argument("--copy-calibration", action="store_true",
@@ -619,7 +674,9 @@ def main():
     base = W.c2_long_time(M=args.m_slice, iters=args.steps, n_intervals=1)
     P = base.n + 2
     nodes = base.nsp * base.degree[0]
-    r32 = run_gpu(base.with_(precision="fp32"), args.steps, args.warmup, launch, torch, args.tune_cache)
+    exact_fn = (lambda grid: long_time_exact(base, grid))
+    r32 = run_gpu(base.with_(precision="fp32"), args.steps, args.warmup, launch, torch, args.tune_cache,
+                  exact_fn=exact_fn)
     ns_step = nodes * base.M
     value = ns_step * args.steps / r32["seconds"]
     st = r32["stats"]
@@ -652,21 +709,58 @@ def main():
         "advance_launches_per_step": st["advance_launches"] / args.steps,
     }
     if not args.no_fp64:
-        r64 = run_gpu(base.with_(precision="fp64"), args.steps, args.warmup, launch, torch, args.tune_cache)
+        r64 = run_gpu(base.with_(precision="fp64"), args.steps, args.warmup, launch, torch, args.tune_cache,
+                      exact_fn=exact_fn)
         v64 = ns_step * args.steps / r64["seconds"]
         s64 = r64["stats"]
         k64 = s64["sample_ms"] / max(1, s64["sample_launches"])
         a64 = fpe * s64["path_steps"] / max(1, s64["advance_launches"]) / (k64 * 1e-3) / 1e12
         out["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["seconds"] / args.steps,
                        "roofline_achieved_tflops": a64, "roofline_frac": a64 / FP64_PEAK_TFLOPS}
-        out["fp32_over_fp64_speedup"] = value / v64
+        out["fp32_over_fp64_rate_ratio"] = value / v64
         ex = long_time_exact(base, r64["grid"])
-        out["accuracy"] = {"max_abs_u32_minus_u64": float(np.max(np.abs(r32["U"] - r64["U"]))),
-                           "max_node_std_error_fp64": r64["sigma"],
-                           "e32_vs_exact": float(np.max(np.abs(r32["U"][0] - ex))),
-                           "e64_vs_exact": float(np.max(np.abs(r64["U"][0] - ex))),
-                           "note": "same Philox words in both precisions; errors are the max over all nodes "
-                                   "after the timed iterations from the replicated initial data"}
+        t32, t64 = r32["trajectory"], r64["trajectory"]
+        # time to a given error against the exact solution, each precision from the replicated
+        # initial data on the same Philox words; the speedup at equal accuracy is quoted at the
+        # tightest decade both precisions reach
+        tte = {}
+        for j in range(1, 13):
+            target = 10.0 ** -j
+            a, b = time_to_error(t32, target), time_to_error(t64, target)
+            tte[f"1e-{j}"] = {"fp32_s": a, "fp64_s": b, "speedup": (b / a) if a and b else None}
+        common = [k for k, v in tte.items() if v["speedup"] is not None]
+        e32, e64, sig = t32[-1][1], t64[-1][1], t64[-1][2]
+        out["fp32_over_fp64_speedup"] = tte[common[-1]]["speedup"] if common else None
+        out["accuracy"] = {
+            "equal_accuracy_target": common[-1] if common else None,
+            "time_to_error": tte,
+            "e32_vs_exact": e32, "e64_vs_exact": e64, "max_node_std_error_fp64": sig,
+            "max_abs_u32_minus_u64": float(np.max(np.abs(r32["U"] - r64["U"]))),
+            "r24_pass": bool(e32 <= e64 + 3 * sig),
+            "trajectory_fp32": [[round(t, 4), e, s_, m] for t, e, s_, m in t32],
+            "trajectory_fp64": [[round(t, 4), e, s_, m] for t, e, s_, m in t64],
+            "note": "rows: [seconds so far, max error against the exact solution, max node standard error, "
+                    "max|eps|] after each timed iteration from the replicated initial data; same Philox words in "
+                    "both precisions.  FP32 sampling levels off at its rounding floor, so the speedup at equal "
+                    "accuracy is quoted at the tightest error both reach; r24_pass is reading R24 after the last "
+                    "iteration (e32 <= e64 + 3 sigma)"}
+        if not args.no_switch:
+            # Algorithm 1's loop condition at the paper's long-time tolerance: FP64 alone (its
+            # trajectory), and FP32 sampling that hands over to FP64 once max|eps| < switch_tol
+            tol, sw = 1e-10, 1e-6
+            rs = run_switched_solve(base.with_(iters=max(args.steps, 30)), tol, sw, torch, args.tune_cache)
+            es = float(np.max(np.abs(rs["U"] - long_time_exact(base, rs["grid"]))))
+            t64_tol = time_to_error(t64, tol, col=3)
+            out["accuracy"]["to_tolerance"] = {
+                "tol": tol, "switch_tol": sw,
+                "fp64": {"seconds": t64_tol, "iterations": next((k + 1 for k, r in enumerate(t64) if r[3] < tol), None),
+                         "error_vs_exact": next((r[1] for r in t64 if r[3] < tol), None)},
+                "fp32": {"reached": time_to_error(t32, tol, col=3) is not None, "min_max_eps": min(r[3] for r in t32)},
+                "fp32_then_fp64": {"seconds": rs["seconds"], "iterations": rs["iterations"],
+                                   "fp32_iterations": rs["fp32_iterations"], "status": rs["status"],
+                                   "error_vs_exact": es, "max_node_std_error": rs["sigma"],
+                                   "r24_pass_vs_fp64": bool(es <= e64 + 3 * sig)},
+                "speedup_vs_fp64": (t64_tol / rs["seconds"]) if t64_tol else None}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(base.with_(precision="fp64"))
     print(json.dumps(out), flush=True)

@@ -341,6 +341,7 @@ struct hpsmc_plan {
     std::vector<std::vector<double>> xi, tnodes;   // per interval: reference LGL nodes, t_{n,l}
     bool fp32 = false, poisoned = false;
     hpsmc_plan *twin = nullptr;   // HPSMC_FP32_THEN_FP64: the FP64 plan the solve switches to
+    std::vector<char> twin_last;  // per interval: its last iteration ran on the twin
     int cus = 0;
     hpsmc_launch launch{2, 4, 8, 256};
     int32_t round_steps = 256;           // walk steps per round
@@ -1238,6 +1239,7 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
 
 static hpsmc_status start_interval(hpsmc_plan *plan, int iv, int replicate, hipStream_t s)
 {
+    if (iv < (int)plan->twin_last.size()) plan->twin_last[iv] = 0;
     if (hpsmc_status st = aitken_reset(plan, iv, s)) return st;
     const int T1 = plan->degree[iv] + 1;
     const int64_t rows = (int64_t)plan->n_inst * plan->nsp;
@@ -1547,6 +1549,7 @@ hpsmc_status hpsmc_start_interval(hpsmc_plan *plan, int32_t iv, void *stream)
 static hpsmc_status iterate_impl(hpsmc_plan *plan, int iv, int tag, int record, hipStream_t s)
 {
     hpsmc_status st;
+    if (iv < (int)plan->twin_last.size()) plan->twin_last[iv] = 0;
     if ((st = reconstruct(plan, iv, s))) return st;
     return sample_set(plan, plan->sets[iv], tag, record, s);
 }
@@ -1563,6 +1566,7 @@ hpsmc_status hpsmc_iterate(hpsmc_plan *plan, int32_t iv, int32_t tag, void *stre
 static hpsmc_status sweep_impl(hpsmc_plan *plan, int tag, int record, hipStream_t s)
 {
     hpsmc_status st;
+    std::fill(plan->twin_last.begin(), plan->twin_last.end(), 0);
     // every interval takes column 0 from the previous interval's last column
     // (the values of the previous sweep: the copies run before any update)
     for (int iv = 1; iv < plan->n_iv; ++iv) {
@@ -1705,6 +1709,7 @@ static hpsmc_status mixed_solve_body(hpsmc_plan *plan, hipStream_t s)
         return HPSMC_OK;
     };
     bool unconverged = false;
+    plan->twin_last.assign(plan->n_iv, 0);
     if (seq) {
         for (int iv = 0; iv < plan->n_iv; ++iv) {
             if ((st = start_interval(plan, iv, 1, s))) return st;
@@ -1725,6 +1730,7 @@ static hpsmc_status mixed_solve_body(hpsmc_plan *plan, hipStream_t s)
                 }
             }
             if (in64 && (st = copy_interval(plan, tw, iv, s))) return st;
+            plan->twin_last[iv] = in64 ? 1 : 0;
             if (tol > 0.0 && k == K) unconverged = true;
         }
     } else {
@@ -1747,8 +1753,10 @@ static hpsmc_status mixed_solve_body(hpsmc_plan *plan, hipStream_t s)
             }
         }
         if (in64)
-            for (int iv = 0; iv < plan->n_iv; ++iv)
+            for (int iv = 0; iv < plan->n_iv; ++iv) {
                 if ((st = copy_interval(plan, tw, iv, s))) return st;
+                plan->twin_last[iv] = 1;
+            }
         if (tol > 0.0 && k == K) unconverged = true;
     }
     HIP_TRY(hipStreamSynchronize(s));
@@ -1829,6 +1837,8 @@ static const NodeSet *set_of(const hpsmc_plan *plan, int iv, int64_t *off)
 hpsmc_status hpsmc_get_increment(const hpsmc_plan *plan, int32_t iv, double *eps, double *sumsq, void *stream)
 {
     CHECK_PLAN(plan);
+    if (plan->twin && iv >= 0 && iv < (int)plan->twin_last.size() && plan->twin_last[iv])
+        return hpsmc_get_increment(plan->twin, iv, eps, sumsq, stream);   // the last iteration ran in FP64
     if (iv < 0 || iv >= plan->n_iv) return fail(HPSMC_EINVAL, "interval out of range");
     int64_t off;
     const NodeSet *set = set_of(plan, iv, &off);
@@ -1931,6 +1941,8 @@ hpsmc_status hpsmc_eval_noalloc(hpsmc_plan *plan, int32_t iv, int32_t inst, cons
 hpsmc_status hpsmc_set_probe(hpsmc_plan *plan, int64_t m_probe)
 {
     CHECK_PLAN(plan);
+    if (plan->twin)
+        if (hpsmc_status st = hpsmc_set_probe(plan->twin, m_probe)) return st;
     if (m_probe < 0 || m_probe > plan->pb.M) return fail(HPSMC_EINVAL, "m_probe must be 0..M");
     if (plan->graph_exec) {   // the captured graph holds the old probe buffers
         (void)hipGraphExecDestroy(plan->graph_exec);
@@ -1953,6 +1965,8 @@ hpsmc_status hpsmc_set_probe(hpsmc_plan *plan, int64_t m_probe)
 hpsmc_status hpsmc_get_probe(const hpsmc_plan *plan, int32_t iv, double *out, void *stream)
 {
     CHECK_PLAN(plan);
+    if (plan->twin && iv >= 0 && iv < (int)plan->twin_last.size() && plan->twin_last[iv])
+        return hpsmc_get_probe(plan->twin, iv, out, stream);
     if (iv < 0 || iv >= plan->n_iv || !out || plan->m_probe == 0) return fail(HPSMC_EINVAL, "no probe");
     int64_t off;
     const NodeSet *set = set_of(plan, iv, &off);

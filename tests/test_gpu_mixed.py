@@ -55,12 +55,16 @@ def test_switch_is_fp32_then_fp64_with_the_same_tags():
     wl = _wl(iters=12)
     _say("switch structure")
     with H.Plan(wl.with_(precision="fp32_then_fp64", switch_tol=sw)) as plan:
+        plan.hpsmc_set_probe(4)
         plan.hpsmc_solve()
         U_mix = plan.hpsmc_get_nodes(0)
         rec_mix = plan.hpsmc_stats()["max_eps"][:wl.iters]
         ns_mix = plan.hpsmc_stats()["node_samples"]
+        inc_mix = plan.hpsmc_get_increment(0)
+        probe_mix = plan.hpsmc_get_probe(0)
     # emulation: FP32 iterations until the record drops below sw, then FP64
     with H.Plan(wl.with_(precision="fp32")) as p32, H.Plan(wl.with_(precision="fp64")) as p64:
+        p64.hpsmc_set_probe(4)
         p32.hpsmc_start_interval(0)
         k = 0
         recs = []
@@ -77,10 +81,15 @@ def test_switch_is_fp32_then_fp64_with_the_same_tags():
             recs.append(p64.hpsmc_stats()["max_eps"][-1])
             k += 1
         U_emu = p64.hpsmc_get_nodes(0) if k_switch < wl.iters else p32.hpsmc_get_nodes(0)
+        inc_emu = p64.hpsmc_get_increment(0)
+        probe_emu = p64.hpsmc_get_probe(0)
     print("switch after iteration", k_switch, "records", rec_mix)
     assert 2 <= k_switch < wl.iters - 2
     assert np.array_equal(U_mix, U_emu)
     assert np.array_equal(rec_mix, np.array(recs))
+    # the last increment and per-sample values are those of the FP64 phase
+    assert np.array_equal(inc_mix[0], inc_emu[0]) and np.array_equal(inc_mix[1], inc_emu[1])
+    assert np.array_equal(probe_mix, probe_emu)
     assert ns_mix == wl.iters * wl.nsp * wl.degree[0] * wl.M
 
 
