@@ -165,6 +165,24 @@ def long_time_exact(wl, grid):
     return sp[:, None] * tf[None, :]
 
 
+def exact_nodes(name, wl, grid):
+    """Nodal values of the manufactured exact solution of a workload (None when
+    it has none): C1 e^{-t} sin(pi x); C4 e^{-t} prod cos(pi x_i / 2); the 2-D
+    long-time solution for the Picard and ball-point lines."""
+    x, t = grid
+    if name == "c1":
+        return np.sin(np.pi * x)[:, None] * np.exp(-t)[None, :]
+    if name == "c4":
+        c = np.cos(0.5 * np.pi * x)
+        sp = c
+        for _ in range(wl.dim - 1):
+            sp = np.multiply.outer(sp, c)
+        return sp.reshape(-1)[:, None] * np.exp(-t)[None, :]
+    if name in ("c2p", "c2b"):
+        return long_time_exact(wl, grid)
+    return None
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -245,6 +263,36 @@ def run_other(name, args, torch):
         st = plan.hpsmc_stats(stream=stream)
         plan_launch = plan.hpsmc_get_launch()
         mma = plan.hpsmc_get_option("sample_mfma_active")
+        # accuracy of the iterate after the run (outside the timed region)
+        acc = None
+        if name in ("c1", "c4", "c2p", "c2b"):
+            ex = exact_nodes(name, wl, plan.hpsmc_grid(0))
+            U = plan.hpsmc_get_nodes(0, stream=stream)[0]
+            eps, ssq = plan.hpsmc_get_increment(0, stream=stream)
+            acc = {"error_vs_exact": float(np.max(np.abs(U - ex))),
+                   "max_node_std_error": float(np.sqrt(np.maximum(ssq / wl.M - eps ** 2, 0.0) / wl.M).max()),
+                   "iterations": int(args.warmup + args.steps) if name != "c1" else int(wl.iters),
+                   "note": ("max over all nodes of the interval against the manufactured solution after the "
+                            "run's iterations from the replicated initial data, with the samples of the slice")}
+        elif name == "c3":
+            U32 = [plan.hpsmc_get_nodes(iv, stream=stream)[0] for iv in range(wl.n_intervals)]
+    if name == "c3":
+        # the FP64 sweeps on the same Philox words, for the FP32 result's error against them
+        with hpsmc.Plan(wl.with_(precision="fp64")) as p64:
+            if args.tune_cache:
+                p64.hpsmc_tune(0, min(wl.M, 4), args.tune_cache, stream=stream)
+            for k in range(args.warmup + args.steps):
+                p64.hpsmc_sweep(k, stream=stream)
+            stream.synchronize()
+            U64 = [p64.hpsmc_get_nodes(iv, stream=stream)[0] for iv in range(wl.n_intervals)]
+            sig = 0.0
+            for iv in range(wl.n_intervals):
+                eps, ssq = p64.hpsmc_get_increment(iv, stream=stream)
+                sig = max(sig, float(np.sqrt(np.maximum(ssq / wl.M - eps ** 2, 0.0) / wl.M).max()))
+        acc = {"max_abs_u32_minus_u64": max(float(np.max(np.abs(a - b))) for a, b in zip(U32, U64)),
+               "max_node_std_error_fp64": sig, "sweeps": int(args.warmup + args.steps),
+               "note": "no exact solution: the FP32 sweeps against the FP64 sweeps on the same Philox words, "
+                       "all 12 intervals, after the run's sweeps"}
     per_step = nodes * wl.M * (wl.iters if name in ("c1", "c5") else 1)
     P = wl.n + 2
     fpe = flops_per_eval(wl.dim, P, picard=wl.estimator == "picard")
@@ -273,8 +321,27 @@ def run_other(name, args, torch):
                            "lane_utilization": st["path_steps"] / max(1, st["lane_steps"])}
         if out["roofline"]["achieved"] is not None:
             out["roofline"]["frac"] = out["roofline"]["achieved"] / out["roofline"]["peak"]
+    else:
+        # the dominant kernel is the adjoint: it replays every forward evaluation and forms, per
+        # evaluation, u* (2 (P + P^2) flops), the Legendre values at both coordinates (3 flops
+        # each) and the two weighted outer products L(x_0) (x) L(x_1) (2 P^2 multiply-adds each)
+        fadj = 2 * (P + P * P) + 3 * 2 * (P - 2) + 4 * P * P
+        adj_ms = st["adjoint_ms"]
+        fwd_ms = st["sample_ms"]
+        achieved = fadj * st["path_steps"] / max(1e-9, adj_ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                           "kernel": "adjoint_kernel<float,2,20,true> (outer products on v_mfma_f32_32x32x2f32)",
+                           "flops_per_eval": fadj,
+                           "evals_per_launch": st["path_steps"] / max(1, st["adjoint_launches"]),
+                           "avg_launch_ms": adj_ms / max(1, st["adjoint_launches"]),
+                           "adjoint_ms_per_step": adj_ms / args.steps,
+                           "forward_round_kernel_ms_per_step": fwd_ms / args.steps,
+                           "adjoint_over_forward": adj_ms / max(1e-9, fwd_ms)}
     out["path_steps_per_s"] = st["path_steps"] / sec
     out["mean_path_length"] = st["path_steps"] / max(1, st["node_samples"])
+    if acc is not None:
+        out["accuracy"] = acc
     print(json.dumps(out), flush=True)
 
 

@@ -248,6 +248,8 @@ typedef struct {
     double slab_ms;            /* summed time-contraction (slab) kernel time     */
     int64_t advance_launches;  /* path-advancing kernel launches, timed or not   */
     double max_eps[4096];      /* max|eps| per (interval, iteration) or sweep    */
+    int64_t adjoint_launches;  /* adjoint-kernel launches timed                 */
+    double adjoint_ms;         /* their summed duration (HIP events), ms         */
 } hpsmc_stats_t;
 
 /* Sampling-kernel launch shape (chosen by hpsmc_tune or set directly). */

@@ -391,8 +391,8 @@ struct hpsmc_plan {
     int64_t node_samples = 0;
     // HIP-event timing of the sampling, slab and reconstruction kernels
     struct EvPair { hipEvent_t a = nullptr, b = nullptr; };
-    std::vector<EvPair> ev_sample, ev_slab, ev_recon, ev_span;
-    size_t n_sample = 0, n_slab = 0, n_recon = 0, n_span = 0;
+    std::vector<EvPair> ev_sample, ev_slab, ev_recon, ev_span, ev_adj;
+    size_t n_sample = 0, n_slab = 0, n_recon = 0, n_span = 0, n_adj = 0;
     int64_t n_advance = 0;                   // advance-kernel launches (round mode)
     int32_t n_records = 0, sweep_count = 0;
 };
@@ -1272,7 +1272,7 @@ void hpsmc_destroy(hpsmc_plan *plan)
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     if (plan->own_stream) (void)hipStreamDestroy(plan->own_stream);
     for (auto &s : plan->sets) free_set(plan, s);
-    for (auto *pool : {&plan->ev_sample, &plan->ev_slab, &plan->ev_recon, &plan->ev_span})
+    for (auto *pool : {&plan->ev_sample, &plan->ev_slab, &plan->ev_recon, &plan->ev_span, &plan->ev_adj})
         for (auto &e : *pool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     void *ptrs[] = {plan->U, plan->cu, plan->cv, plan->tmp0, plan->tmp1, plan->ic, plan->mats,
                     plan->slab_table, plan->part, plan->counters, plan->maxbits, plan->hist_u, plan->hist_v,
@@ -2023,6 +2023,8 @@ hpsmc_status hpsmc_stats(const hpsmc_plan *plan, hpsmc_stats_t *out, void *strea
     out->slab_ms = pool_ms(plan->ev_slab, plan->n_slab);
     out->recon_ms = pool_ms(plan->ev_recon, plan->n_recon);
     out->sample_launches = (int32_t)plan->n_sample;
+    out->adjoint_ms = pool_ms(plan->ev_adj, plan->n_adj);
+    out->adjoint_launches = (int64_t)plan->n_adj;
     out->advance_launches = plan->n_advance;
     out->recon_launches = (int32_t)plan->n_recon;
     out->path_steps = c[1];
@@ -2067,7 +2069,7 @@ hpsmc_status hpsmc_reset_stats(hpsmc_plan *plan, void *stream)
     HIP_TRY(launch_fill_u64(plan->maxbits, 4096, 0ull, s));
     plan->node_samples = 0;
     plan->n_records = 0;
-    plan->n_sample = plan->n_slab = plan->n_recon = plan->n_span = 0;
+    plan->n_sample = plan->n_slab = plan->n_recon = plan->n_span = plan->n_adj = 0;
     plan->n_advance = 0;
     return HPSMC_OK;
 }
@@ -2446,7 +2448,10 @@ static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hi
             a.live_in = set.live + (r & 1) * G;
             a.live_out = set.live + ((r + 1) & 1) * G;
             HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, a.live_in, a.live_out, set.prefix, plan->counters, s));
+            hpsmc_plan::EvPair *ea = next_pair(plan->ev_adj, plan->n_adj);
+            if (ea) HIP_TRY(hipEventRecord(ea->a, s));
             HIP_TRY(launch_adjoint(aa, plan->fp32, waves, blocks, lds, s));
+            if (ea) HIP_TRY(hipEventRecord(ea->b, s));
         }
     }
     return HPSMC_OK;

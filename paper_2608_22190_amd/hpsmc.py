@@ -59,7 +59,8 @@ class hpsmc_stats_t(C.Structure):
                 ("n_records", C.c_int32), ("status_flags", C.c_int32), ("sample_launches", C.c_int32),
                 ("recon_launches", C.c_int32), ("sample_ms", C.c_double), ("sampling_span_ms", C.c_double),
                 ("recon_ms", C.c_double),
-                ("slab_ms", C.c_double), ("advance_launches", C.c_int64), ("max_eps", C.c_double * 4096)]
+                ("slab_ms", C.c_double), ("advance_launches", C.c_int64), ("max_eps", C.c_double * 4096),
+                ("adjoint_launches", C.c_int64), ("adjoint_ms", C.c_double)]
 
 
 class hpsmc_launch(C.Structure):
@@ -401,7 +402,8 @@ class Plan:
                 "sample_launches": s.sample_launches, "recon_launches": s.recon_launches,
                 "sample_ms": s.sample_ms, "sampling_span_ms": s.sampling_span_ms, "recon_ms": s.recon_ms,
                 "slab_ms": s.slab_ms,
-                "advance_launches": s.advance_launches}
+                "advance_launches": s.advance_launches,
+                "adjoint_launches": s.adjoint_launches, "adjoint_ms": s.adjoint_ms}
 
     def hpsmc_reset_stats(self, stream=None):
         _check(lib().hpsmc_reset_stats(self.h, _stream(stream)), "hpsmc_reset_stats")
