@@ -17,8 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhpsmc.so")
-SOURCES = ["hpsmc_kern_valu_f32.hip", "hpsmc_kern_valu_f64.hip", "hpsmc_kern_mma.hip", "hpsmc_kern_adjoint.hip",
-           "hpsmc_kern_frac.hip", "hpsmc_kernels.hip", "hpsmc_host.cpp"]
+SOURCES = ["hpsmc_kern_valu_f32.hip", "hpsmc_kern_valu_f64.hip", "hpsmc_kern_mma.hip", "hpsmc_kern_mma5.hip",
+           "hpsmc_kern_adjoint.hip", "hpsmc_kern_frac.hip", "hpsmc_kernels.hip", "hpsmc_host.cpp"]
 HEADERS = ["hpsmc_internal.h", "hpsmc_device.h", "hpsmc_round.h", "hpsmc_lobatto_eigs.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -152,6 +152,45 @@ __device__ __forceinline__ void ball_offset(uint32_t c0, uint32_t c1, int q, uin
 }
 
 // ---------------------------------------------------------------------------
+// Uniform direction on the unit sphere of R^D, D >= 3, for walk step q
+// (Lemma 2.1): Philox blocks q (D <= 4) or 2q and 2q + 1 (D = 5), Box-Muller
+// pairs of words (2k, 2k + 1), the first D normals normalised.
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ void sphere_dir(uint32_t c0, uint32_t c1, int q, uint32_t c3, uint32_t k0, uint32_t k1,
+                                           T (&dir)[D])
+{
+    static_assert(D >= 3 && D <= 5, "Gaussian directions for d = 3..5");
+    uint32_t ww[8];
+    if constexpr (D <= 4) {
+        uint32_t o[4];
+        philox(c0, c1, (uint32_t)q, c3, k0, k1, o);
+        ww[0] = o[0]; ww[1] = o[1]; ww[2] = o[2]; ww[3] = o[3];
+    } else {
+        uint32_t o[4], o2[4];
+        philox(c0, c1, (uint32_t)(2 * q), c3, k0, k1, o);
+        philox(c0, c1, (uint32_t)(2 * q + 1), c3, k0, k1, o2);
+        ww[0] = o[0]; ww[1] = o[1]; ww[2] = o[2]; ww[3] = o[3];
+        ww[4] = o2[0]; ww[5] = o2[1]; ww[6] = o2[2]; ww[7] = o2[3];
+    }
+    T gg[D + 1];
+#pragma unroll
+    for (int k = 0; k < (D + 1) / 2; ++k) {
+        const T r = m_sqrt((T)-2 * m_log(u01(ww[2 * k], (T)0)));
+        T c, sn;
+        angle_dir(u01(ww[2 * k + 1], (T)0), c, sn);
+        gg[2 * k] = r * c;
+        gg[2 * k + 1] = r * sn;
+    }
+    T nrm = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) nrm += gg[i] * gg[i];
+    nrm = m_sqrt(nrm);
+#pragma unroll
+    for (int i = 0; i < D; ++i) dir[i] = gg[i] / nrm;
+}
+
+// ---------------------------------------------------------------------------
 // Problem terms.
 // ---------------------------------------------------------------------------
 // sin(u) for the nonlinearity: FP32 arguments with |u| <= 2 take the sine's
@@ -581,12 +620,14 @@ __device__ __forceinline__ void mma_epilogue(const f32x16 &du0, const f32x16 &dv
 hipError_t launch_adv_valu_f32(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 hipError_t launch_adv_valu_f64(const RoundArgs &a, int ns, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 hipError_t launch_adv_mma(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s);
+hipError_t launch_adv_mma5(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 hipError_t launch_adv_frac(const RoundArgs &a, int fp32, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 // each unit's copy of the recurrence tables
 hipError_t set_rec_tables_main();
 hipError_t set_rec_tables_valu_f32();
 hipError_t set_rec_tables_valu_f64();
 hipError_t set_rec_tables_mma();
+hipError_t set_rec_tables_mma5();
 hipError_t set_rec_tables_frac();
 hipError_t set_rec_tables_adjoint();
 

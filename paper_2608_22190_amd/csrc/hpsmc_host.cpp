@@ -599,6 +599,15 @@ static double walk_radius(const hpsmc_plan *plan, double delta)
     return std::sqrt(2.0 * plan->d * delta);
 }
 
+// whether some launch shape runs this plan's rounds on a matrix-core kernel
+static bool mma_capable(const hpsmc_plan *plan)
+{
+    if (plan->d == 5)
+        return advance_mma5_eligible(plan->fp32, 5, plan->P, plan->pb.estimator == HPSMC_EST_PICARD,
+                                     plan->pb.quad == HPSMC_QUAD_BALL, 1, 4);
+    return advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
+}
+
 static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<int32_t> &ivs)
 {
     const int d = plan->d;
@@ -609,10 +618,10 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     std::vector<int32_t> nst, deg;
     const int64_t rows = ipow(plan->P, d - 1);
     const int64_t stride = rows * 2 * plan->PP;
-    // plans the matrix-core round kernel can serve also get offsets in its slab layout
-    const bool mma_ok = advance_mma_eligible(plan->fp32, d, plan->P, 0, 1, 4);
+    // plans a matrix-core round kernel can serve also get offsets in its slab layout
+    const bool mma_ok = mma_capable(plan);
     const int extra = plan->pb.estimator == HPSMC_EST_PICARD ? 1 : 0;   // the slab of q = N* (t = t_{n-1})
-    const int64_t mstride = mma_slab_elems(plan->PP);
+    const int64_t mstride = d == 5 ? mma5_geom(plan->P).step : mma_slab_elems(plan->PP);
     int64_t slab_pos = 0, slab_pos_mma = 0, out = 0;
     // canonical output order: [iv][inst][node id]
     for (int32_t iv : ivs) {
@@ -1068,11 +1077,17 @@ static bool one_sample_per_lane(const hpsmc_plan *plan)
     return plan->frac || plan->pb.estimator == HPSMC_EST_PICARD || plan->pb.quad == HPSMC_QUAD_BALL;
 }
 
-// Whether the rounds of this set run the matrix-core kernel with the current
-// launch shape (its slabs are then written in the matrix-core layout).
+// Whether the rounds of this set run a matrix-core kernel with the current
+// launch shape (its slabs are then written in that kernel's layout): 1 the
+// 2-D kernel, 2 the 5-D kernel, 0 neither.
 static int set_uses_mma(const hpsmc_plan *plan, const NodeSet &set)
 {
     if (!set.rounds || !plan->sample_mma || !set.slab.slab_off_mma) return 0;
+    if (plan->d == 5)
+        return advance_mma5_eligible(plan->fp32, plan->d, plan->P, plan->pb.estimator == HPSMC_EST_PICARD,
+                                     plan->pb.quad == HPSMC_QUAD_BALL,
+                                     one_sample_per_lane(plan) ? 1 : plan->launch.samples_per_lane,
+                                     plan->launch.waves_per_block) ? 2 : 0;
     int cf, nc;
     int64_t ce;
     if (!pick_chunking(plan, 64 * plan->launch.waves_per_block, &cf, &ce, &nc)) return 0;
@@ -1115,13 +1130,14 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     // the fractional kernel, the Picard form and the ball-point rule run one sample per lane
     const int ns = one_sample_per_lane(plan) ? 1 : plan->launch.samples_per_lane, waves = plan->launch.waves_per_block;
     const int nthr = 64 * waves;
-    int cf, n_chunks;
-    int64_t chunk_elems;
-    if (!pick_chunking(plan, nthr, &cf, &chunk_elems, &n_chunks))
+    const int mma = set_uses_mma(plan, set);
+    int cf = 0, n_chunks = 1;
+    int64_t chunk_elems = 0;
+    if (mma != 2 && !pick_chunking(plan, nthr, &cf, &chunk_elems, &n_chunks))
         return fail(HPSMC_EINVAL, "slab chunk too large for this block size; use more waves per block");
     const int64_t nvec = chunk_elems * (plan->fp32 ? 4 : 8) / 16;
-    const int mma = set_uses_mma(plan, set);
-    const size_t lds = mma ? advance_mma_lds_bytes(plan->PP)
+    const size_t lds = mma == 2 ? advance_mma5_lds_bytes(plan->P)
+                     : mma ? advance_mma_lds_bytes(plan->PP)
                      : plan->frac ? frac_lds_bytes(plan->fp32, plan->PP, plan->frac_kmax, plan->P, plan->frac_K,
                                                    plan->frac_nt)
                                   : (size_t)2 * ((nvec + 1) & ~1LL) * 16;
@@ -2090,7 +2106,7 @@ static std::string tune_key(const hpsmc_plan *plan, int iv, int64_t M)
     // plans that may run the matrix-core round kernel tune separately from those that may not
     const bool picard = plan->pb.estimator == HPSMC_EST_PICARD;
     const bool ball = plan->pb.quad == HPSMC_QUAD_BALL;
-    const bool mma = plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 4);
+    const bool mma = plan->sample_mma && mma_capable(plan);
     char buf[256];
     snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
              plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", picard ? "_picard" : "", ball ? "_ball" : "",
@@ -2175,6 +2191,13 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
     for (int a = 0; a < 3; ++a) {
         if (nsv[a] == 4 && plan->d > 2) continue;
         if (nsv[a] != 1 && one_sample_per_lane(plan)) continue;
+        if (nsv[a] == 1 && plan->sample_mma && plan->d == 5 && mma_capable(plan)) {
+            // the 5-D matrix-core kernel: two LDS buffers of 2 x 32-row tiles per block
+            const int fit = std::max(1, (int)((160 * 1024 - 4096) / advance_mma5_lds_bytes(plan->P)));
+            for (int w : {2, 4})
+                for (int b = 1; b <= std::min(fit, 4); ++b) cands.push_back(hpsmc_launch{1, w, b, plan->round_steps});
+            continue;
+        }
         for (int w : {2, 4}) {
             // two-wave blocks of the matrix-core kernel: 1, 1.5, 2, 3, 4 waves per SIMD
             if (w == 2 && nsv[a] == 1 && plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 2)) {

@@ -171,6 +171,60 @@ size_t advance_mma_lds_bytes(int PP);
 // kMmaRows rows k0 (zeros past P), stored as the kernel's LDS image
 constexpr int kMmaRows = 33;
 inline int64_t mma_slab_elems(int PP) { return (int64_t)2 * PP * kMmaRows; }
+
+// Five-dimensional matrix-core slab layout.  A step's image is a sequence of
+// NCH chunks, each a 32-row tile of the u coefficients followed by the same
+// tile of the v coefficients.  Tile rows run over (k0, k1, k2); the
+// contraction index over (k3, k4) in k-steps j = k3 HK + m, k4 = 2m + h, where
+// h is the half of the wave that feeds k4's parity to the 32x32x2 product.
+// Row i of a tile holds [h = 0: j < KH2][h = 1: j < KH2][4 floats pad]: RS is
+// an odd multiple of 4 floats, so eight rows read as 16-byte vectors hit
+// distinct bank quads.  The rows f = k1 P + k2 < 32 A of each k0 fill A main
+// tiles per k0, k0-major; the B = P^2 - 32 A remaining rows of every k0 are
+// gathered, k0-major, into R tiles at the end, so every P in 3..12 wastes at
+// most 3% of the rows.  Entries past P (k4 of odd P) and past the last row are zero.
+struct Mma5Geom {
+    int P, HK, KJ, KH2, RS, A, B, R, NCH;
+    int64_t chunk;   // floats per chunk (u tile, v tile)
+    int64_t step;    // floats per step
+};
+constexpr Mma5Geom mma5_geom(int P)
+{
+    const int HK = (P + 1) / 2, KJ = P * HK, KH2 = (KJ + 3) & ~3, RS = 2 * KH2 + 4;
+    const int A = P * P / 32, B = P * P - 32 * A, R = (B * P + 31) / 32;
+    return Mma5Geom{P, HK, KJ, KH2, RS, A, B, R, P * A + R, (int64_t)64 * RS, (int64_t)(P * A + R) * 64 * RS};
+}
+// Element e of a step's image: false for padding, else its table (0 u, 1 v),
+// the flat index row4 = ((k0 P + k1) P + k2) P + k3 of the first four modes, and k4.
+__host__ __device__ inline bool mma5_source(const Mma5Geom &g, int64_t e, int &uv, int64_t &row4, int &k4)
+{
+    const int c = (int)(e / g.chunk);
+    int r = (int)(e - (int64_t)c * g.chunk);
+    uv = r / (32 * g.RS);
+    r -= uv * 32 * g.RS;
+    const int i = r / g.RS, col = r - i * g.RS;
+    const int h = col / g.KH2, j = col - h * g.KH2;
+    if (h > 1 || j >= g.KJ) return false;
+    const int k3 = j / g.HK, m = j - k3 * g.HK;
+    k4 = 2 * m + h;
+    if (k4 >= g.P) return false;
+    int k0, f;
+    if (c < g.P * g.A) {
+        k0 = c / g.A;
+        f = 32 * (c - k0 * g.A) + i;
+    } else {
+        const int rr = 32 * (c - g.P * g.A) + i;
+        if (rr >= g.B * g.P) return false;
+        k0 = rr / g.B;
+        f = 32 * g.A + (rr - k0 * g.B);
+    }
+    row4 = ((int64_t)k0 * g.P * g.P + f) * g.P + k3;
+    return true;
+}
+// matrix-core form of the 5-D round kernel: FP32, 3 <= P <= 12, residual form
+// with the centre-point rule, one path per lane
+bool advance_mma5_eligible(int fp32, int dim, int P, int picard, int ball, int samples_per_lane, int waves_per_block);
+size_t advance_mma5_lds_bytes(int P);
 hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mcount, double *sums, int first,
                                hipStream_t s);
 size_t path_state_bytes(int fp32, int dim);

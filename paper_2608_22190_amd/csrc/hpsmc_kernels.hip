@@ -23,7 +23,8 @@ hipError_t set_rec_tables_main() { return upload_recurrence_tables(); }
 hipError_t set_recurrence_tables()
 {
     for (hipError_t (*f)() : {set_rec_tables_main, set_rec_tables_valu_f32, set_rec_tables_valu_f64,
-                              set_rec_tables_mma, set_rec_tables_frac, set_rec_tables_adjoint})
+                              set_rec_tables_mma, set_rec_tables_mma5, set_rec_tables_frac,
+                              set_rec_tables_adjoint})
         if (hipError_t e = f(); e != hipSuccess) return e;
     return hipSuccess;
 }
@@ -315,9 +316,10 @@ __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
     const int g = blockIdx.y;
     const int nq = a.nstar[g] + a.extra;
     const int T1 = a.deg[g] + 1;
-    const bool mma = a.layout == 1;
-    const int64_t stride = mma ? a.mma_stride : a.slab_stride;
-    const int64_t base = mma ? a.slab_off_mma[g] : a.slab_off[g];
+    const bool mma = a.layout == 1, mma5 = a.layout == 2;
+    const Mma5Geom g5 = mma5_geom(a.P);
+    const int64_t stride = a.layout ? a.mma_stride : a.slab_stride;
+    const int64_t base = a.layout ? a.slab_off_mma[g] : a.slab_off[g];
     T *table = (T *)a.slab_table;
     const double *cu = a.cu + a.coef_off[g], *cv = a.cv + a.coef_off[g];
     const double *cs = a.cs ? a.cs + a.cs_off[g] : nullptr;   // polynomial source, folded into v
@@ -337,20 +339,25 @@ __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
         }
         __syncthreads();
         for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) {
-            int64_t row;
-            int uv, kl;
-            if (mma) {   // column c = uv * PP + k1 of kMmaRows rows k0
-                const int c = (int)(e / kMmaRows);
-                row = e - (int64_t)c * kMmaRows;
-                uv = c / a.PP;
-                kl = c - uv * a.PP;
+            int64_t row = 0;
+            int uv = 0, kl = 0;
+            bool live;
+            if (mma5) {  // 32-row tiles over (k0, k1, k2), columns (k3, k4)
+                live = mma5_source(g5, e, uv, row, kl);
             } else {
-                row = e / (2 * a.PP);
-                const int rem = (int)(e - row * 2 * a.PP);
-                uv = rem / a.PP;
-                kl = rem - uv * a.PP;
+                if (mma) {   // column c = uv * PP + k1 of kMmaRows rows k0
+                    const int c = (int)(e / kMmaRows);
+                    row = e - (int64_t)c * kMmaRows;
+                    uv = c / a.PP;
+                    kl = c - uv * a.PP;
+                } else {
+                    row = e / (2 * a.PP);
+                    const int rem = (int)(e - row * 2 * a.PP);
+                    uv = rem / a.PP;
+                    kl = rem - uv * a.PP;
+                }
+                live = kl < a.P && row < a.rows;
             }
-            const bool live = kl < a.P && row < a.rows;
             double c[kMaxDeg + 1];
             if (live) {
                 const double *cp = (uv ? cv : cu) + (row * a.P + kl) * T1;
@@ -664,6 +671,11 @@ hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, in
 {
     dim3 block(64 * waves_per_block), grid(blocks);
     if (a.phys.frac) return launch_adv_frac(a, fp32, grid, block, lds_bytes, s);
+    if (mma == 2) {
+        if (!advance_mma5_eligible(fp32, a.phys.dim, a.P, a.phys.picard, a.phys.ball, samples_per_lane, waves_per_block))
+            return hipErrorInvalidValue;
+        return launch_adv_mma5(a, grid, block, lds_bytes, s);
+    }
     if (mma) {
         if (!advance_mma_eligible(fp32, a.phys.dim, a.P, a.cf, samples_per_lane, waves_per_block))
             return hipErrorInvalidValue;

@@ -138,35 +138,7 @@ __device__ __forceinline__ void advance_body(const RoundArgs &a)
                 }
             } else {
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    uint32_t ww[8];
-                    if constexpr (D <= 4) {
-                        uint32_t o[4];
-                        philox(c0[s], sample[s], (uint32_t)q, c3, a.key0, a.key1, o);
-                        ww[0] = o[0]; ww[1] = o[1]; ww[2] = o[2]; ww[3] = o[3];
-                    } else {
-                        uint32_t o[4], o2[4];
-                        philox(c0[s], sample[s], (uint32_t)(2 * q), c3, a.key0, a.key1, o);
-                        philox(c0[s], sample[s], (uint32_t)(2 * q + 1), c3, a.key0, a.key1, o2);
-                        ww[0] = o[0]; ww[1] = o[1]; ww[2] = o[2]; ww[3] = o[3];
-                        ww[4] = o2[0]; ww[5] = o2[1]; ww[6] = o2[2]; ww[7] = o2[3];
-                    }
-                    T gg[D + 1];
-#pragma unroll
-                    for (int k = 0; k < (D + 1) / 2; ++k) {
-                        const T r = m_sqrt((T)-2 * m_log(u01(ww[2 * k], (T)0)));
-                        T c, sn;
-                        angle_dir(u01(ww[2 * k + 1], (T)0), c, sn);
-                        gg[2 * k] = r * c;
-                        gg[2 * k + 1] = r * sn;
-                    }
-                    T nrm = 0;
-#pragma unroll
-                    for (int i = 0; i < D; ++i) nrm += gg[i] * gg[i];
-                    nrm = m_sqrt(nrm);
-#pragma unroll
-                    for (int i = 0; i < D; ++i) dir[s][i] = gg[i] / nrm;
-                }
+                for (int s = 0; s < NS; ++s) sphere_dir<T, D>(c0[s], sample[s], q, c3, a.key0, a.key1, dir[s]);
             }
             // ---- jump and exit test (eq. indexL)
             bool any_live = false;
