@@ -404,10 +404,19 @@ hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_
  *                       (v_mfma_f32_32x32x2f32) -- the residual and Picard
  *                       forms, the centre-point and ball-point rules (plans of
  *                       the Picard form or the ball rule count as one sample
- *                       per lane); 0: always on the vector units.  Same walks
- *                       and exit steps either way; the FP32 sums differ only
- *                       by rounding order.  Changing it discards a captured
- *                       graph.
+ *                       per lane); so do 5-D FP32 plans of the residual form
+ *                       with the centre-point rule, P <= 12 and one sample per
+ *                       lane (the innermost two modes of the contraction as
+ *                       matrix-core products); 0: always on the vector units.
+ *                       Same walks and exit steps either way; the FP32 sums
+ *                       differ only by rounding order.  Changing it discards a
+ *                       captured graph.
+ *   "sample_split"      1 (default): in a round of the 5-D matrix-core kernel
+ *                       whose live paths fit in one pass of the grid at 64
+ *                       paths per block, the block's two or four waves walk the
+ *                       same 64 paths and share each step's products (shorter
+ *                       rounds when few long paths remain); 0: never.  The
+ *                       FP32 sums differ only by rounding order.
  *   "graph"             1: hpsmc_solve captures the whole solve into a hipGraph
  *                       on its first call (on a stream of the plan) and replays
  *                       it on this and later calls; 0 (default): eager launches.
@@ -416,8 +425,9 @@ hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_
 hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value);
 
 /* Read a named option into *value: the names above, and the read-only
- * "sample_mfma_active" = 1 when the current launch shape runs the matrix-core
- * path-advancing kernel for some interval.  EINVAL for an unknown name. */
+ * "sample_mfma_active": 0 when the current launch shape runs no matrix-core
+ * path-advancing kernel, 1 the 2-D one, 2 the 5-D one.  EINVAL for an
+ * unknown name. */
 hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t *value);
 
 const char *hpsmc_last_error(void);

@@ -365,7 +365,8 @@ struct hpsmc_plan {
     int32_t adj_use_mfma = 1;
     // hipGraph of a whole solve (captured on the first graph solve, replayed after)
     int32_t use_graph = 0;
-    int32_t sample_mma = 1;     // 2-D FP32 round kernel on the matrix cores where eligible
+    int32_t sample_mma = 1;     // FP32 round kernels on the matrix cores where eligible (2-D, 5-D)
+    int32_t sample_split = 1;   // sparse rounds of the 5-D matrix-core kernel on all waves of a block
     // fractional operator (d = 1): tables of the round kernel (see Physics)
     bool frac = false;
     double *frac_tab = nullptr;
@@ -767,7 +768,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
         if ((st = dalloc(plan, &set.state[0], sb * set.n * ms))) return st;
         if ((st = dalloc(plan, &set.state[1], sb * set.n * ms))) return st;
         if ((st = dalloc(plan, (void **)&set.live, sizeof(uint32_t) * 2 * G))) return st;
-        if ((st = dalloc(plan, (void **)&set.prefix, sizeof(int64_t) * (G + 1)))) return st;
+        if ((st = dalloc(plan, (void **)&set.prefix, sizeof(int64_t) * (G + 2)))) return st;
         if ((st = dalloc(plan, (void **)&set.result, sizeof(double) * set.n * ms))) return st;
         if (hipMemcpy(set.gdev, set.ghost.data(), sizeof(GroupDesc) * G, hipMemcpyHostToDevice) != hipSuccess)
             return fail(HPSMC_EDEVICE, "upload of group descriptors failed");
@@ -1166,6 +1167,10 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     a.stats = plan->counters + 1;
     a.phys = physics_of(plan);
     const int blocks = std::max(1, plan->cus * plan->launch.blocks_per_cu);
+    // rounds of the 5-D matrix-core kernel whose paths fit in one pass of the
+    // grid at 64 paths per block run each item on all the block's waves (two or
+    // four), each taking a share of every tile's products
+    const int split_batch = mma == 2 && plan->sample_split && (waves == 2 || waves == 4) ? 64 : 0;
     hpsmc_plan::EvPair *ek = next_pair(plan->ev_span, plan->n_span);
     if (ek) HIP_TRY(hipEventRecord(ek->a, s));
     int first = 1;
@@ -1179,7 +1184,8 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
             a.state_out = set.state[(r + 1) & 1];
             a.live_in = set.live + (r & 1) * G;
             a.live_out = set.live + ((r + 1) & 1) * G;
-            HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, a.live_in, a.live_out, set.prefix, plan->counters, s));
+            HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, split_batch, blocks, a.live_in, a.live_out,
+                                      set.prefix, plan->counters, s));
             hpsmc_plan::EvPair *ea = next_pair(plan->ev_sample, plan->n_sample);
             if (ea) HIP_TRY(hipEventRecord(ea->a, s));
             HIP_TRY(launch_advance(a, plan->fp32, ns, waves, blocks, lds, mma, s));
@@ -2394,6 +2400,17 @@ hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value)
         plan->sample_mma = (int32_t)value;
         return HPSMC_OK;
     }
+    if (strcmp(name, "sample_split") == 0) {
+        if (value != 0 && value != 1) return fail(HPSMC_EINVAL, "sample_split must be 0 or 1");
+        if (plan->sample_split != (int32_t)value && plan->graph_exec) {   // captured with the other batching
+            (void)hipGraphExecDestroy(plan->graph_exec);
+            (void)hipGraphDestroy(plan->graph);
+            plan->graph_exec = nullptr;
+            plan->graph = nullptr;
+        }
+        plan->sample_split = (int32_t)value;
+        return HPSMC_OK;
+    }
     return fail(HPSMC_EINVAL, std::string("unknown option ") + name);
 }
 
@@ -2410,6 +2427,7 @@ hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t 
     if (strcmp(name, "graph") == 0) { *value = plan->use_graph; return HPSMC_OK; }
     if (strcmp(name, "adjoint_mfma") == 0) { *value = plan->adj_use_mfma; return HPSMC_OK; }
     if (strcmp(name, "sample_mfma") == 0) { *value = plan->sample_mma; return HPSMC_OK; }
+    if (strcmp(name, "sample_split") == 0) { *value = plan->sample_split; return HPSMC_OK; }
     if (strcmp(name, "sample_mfma_active") == 0) {
         *value = 0;
         for (int iv = 0; iv < (plan->pb.schedule == HPSMC_SEQUENTIAL ? plan->n_iv : 1); ++iv)
@@ -2470,7 +2488,8 @@ static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hi
             a.state_out = set.state[(r + 1) & 1];
             a.live_in = set.live + (r & 1) * G;
             a.live_out = set.live + ((r + 1) & 1) * G;
-            HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, a.live_in, a.live_out, set.prefix, plan->counters, s));
+            HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, 0, 0, a.live_in, a.live_out, set.prefix,
+                                      plan->counters, s));
             hpsmc_plan::EvPair *ea = next_pair(plan->ev_adj, plan->n_adj);
             if (ea) HIP_TRY(hipEventRecord(ea->a, s));
             HIP_TRY(launch_adjoint(aa, plan->fp32, waves, blocks, lds, s));

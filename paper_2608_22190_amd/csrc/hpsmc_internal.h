@@ -90,7 +90,7 @@ struct RoundArgs {
     void *state_out;
     const uint32_t *live_in;     // per group, paths in state_in (round > 0)
     uint32_t *live_out;          // per group, survivors appended to state_out
-    const int64_t *batch_prefix; // [n_groups + 1] work items per group, prefix
+    const int64_t *batch_prefix; // [n_groups + 2] work items per group, prefix; [n_groups + 1] paths per item
     double *result;              // [node out][mcount] path value S of each sample
     int32_t n_chunks;            // LDS chunks per slab: P^cf, the first cf dimensions fixed per chunk
     int32_t cf;
@@ -158,9 +158,13 @@ hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long 
 size_t frac_lds_bytes(int fp32, int PP, int kmax, int P, int K, int nt);
 hipError_t launch_eval(const double *cu, const double *cv, int dim, int P, int T1, double t_prev, double h,
                        const double *pts, int64_t npts, double *out, hipStream_t s);
+// batch_prefix: [n_groups + 2]; batch_split > 0 lets a round that fits in at
+// most split_max items of batch_split paths use that batch (the 5-D
+// matrix-core kernel then splits each item's products over the block's waves)
 hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t round, int32_t steps,
-                             int64_t mcount, int32_t batch, const uint32_t *live_in, uint32_t *live_out,
-                             int64_t *batch_prefix, unsigned long long *work, hipStream_t s);
+                             int64_t mcount, int32_t batch, int32_t batch_split, int64_t split_max,
+                             const uint32_t *live_in, uint32_t *live_out, int64_t *batch_prefix,
+                             unsigned long long *work, hipStream_t s);
 hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
                           size_t lds_bytes, int mma, hipStream_t s);
 // matrix-core form of the round kernel: FP32, d = 2, P <= 32, whole slab per

@@ -64,13 +64,16 @@ __device__ __forceinline__ void mma5_operands(float x3, float x4, float (&a3)[P]
     }
 }
 
-// the four products of one tile (S: the chunk's u tile, its v tile 32 RS floats on)
-template <int P>
+// the four products of one tile over k-steps [J0, J1) (S: the chunk's u tile,
+// its v tile 32 RS floats on)
+template <int P, int J0, int J1>
 __device__ __forceinline__ void mma5_tile(const float *S, int lane, const float (&a3)[P], const float (&b3)[P],
                                           const float (&a4)[(P + 1) / 2], const float (&b4)[(P + 1) / 2],
                                           f32x16 &uA, f32x16 &vA, f32x16 &uB, f32x16 &vB)
 {
     constexpr Mma5Geom g = mma5_geom(P);
+    static_assert(0 <= J0 && J0 < J1 && J1 <= g.KJ, "k-step range");
+    constexpr int JB = J0 & ~3;   // first 16-byte group
     const float *Au = S + (lane & 31) * g.RS + (lane >> 5) * g.KH2;
     const float *Av = Au + 32 * g.RS;
     uA = f32x16{}; vA = f32x16{}; uB = f32x16{}; vB = f32x16{};
@@ -92,18 +95,18 @@ __device__ __forceinline__ void mma5_tile(const float *S, int lane, const float 
     // A operands four k-steps at a time, one group ahead of the products; the
     // scheduling fence keeps later groups from being hoisted (their registers
     // would push the kernel past two waves per SIMD)
-    f32x4 xu = *(const f32x4 *)Au, xv = *(const f32x4 *)Av;
+    f32x4 xu = *(const f32x4 *)(Au + JB), xv = *(const f32x4 *)(Av + JB);
 #pragma unroll
-    for (int jj = 0; jj < g.KJ; jj += 4) {
+    for (int jj = JB; jj < J1; jj += 4) {
         f32x4 nu = xu, nv = xv;
-        if (jj + 4 < g.KJ) {
+        if (jj + 4 < J1) {
             nu = *(const f32x4 *)(Au + jj + 4);
             nv = *(const f32x4 *)(Av + jj + 4);
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int j = jj + s;
-            if (j < g.KJ) {
+            if (j >= J0 && j < J1) {
                 const int k3 = j / g.HK, m = j - k3 * g.HK;
                 const float bA = f3[k3] * f4[m], bB = g3[k3] * g4[m];
                 uA = __builtin_amdgcn_mfma_f32_32x32x2f32(xu[s], bA, uA, 0, 0, 0);
@@ -115,6 +118,30 @@ __device__ __forceinline__ void mma5_tile(const float *S, int lane, const float 
         __builtin_amdgcn_sched_barrier(0);
         xu = nu;
         xv = nv;
+    }
+}
+
+// the products of part `part` of `nparts` (1, 2 or 4: the waves that share
+// one item in a sparse round) -- k-steps [KJ part / nparts, KJ (part + 1) / nparts)
+template <int P>
+__device__ __forceinline__ void mma5_tile_part(int part, int nparts, const float *S, int lane, const float (&a3)[P],
+                                               const float (&b3)[P], const float (&a4)[(P + 1) / 2],
+                                               const float (&b4)[(P + 1) / 2], f32x16 &uA, f32x16 &vA, f32x16 &uB,
+                                               f32x16 &vB)
+{
+    constexpr int KJ = mma5_geom(P).KJ;
+    if (nparts == 1) {
+        mma5_tile<P, 0, KJ>(S, lane, a3, b3, a4, b4, uA, vA, uB, vB);
+    } else if (nparts == 2) {
+        if (part == 0) mma5_tile<P, 0, KJ / 2>(S, lane, a3, b3, a4, b4, uA, vA, uB, vB);
+        else mma5_tile<P, KJ / 2, KJ>(S, lane, a3, b3, a4, b4, uA, vA, uB, vB);
+    } else {
+        switch (part) {
+        case 0: mma5_tile<P, 0, KJ / 4>(S, lane, a3, b3, a4, b4, uA, vA, uB, vB); break;
+        case 1: mma5_tile<P, KJ / 4, KJ / 2>(S, lane, a3, b3, a4, b4, uA, vA, uB, vB); break;
+        case 2: mma5_tile<P, KJ / 2, 3 * KJ / 4>(S, lane, a3, b3, a4, b4, uA, vA, uB, vB); break;
+        default: mma5_tile<P, 3 * KJ / 4, KJ>(S, lane, a3, b3, a4, b4, uA, vA, uB, vB); break;
+        }
     }
 }
 
@@ -187,12 +214,21 @@ __device__ __forceinline__ void advance_mma5_body(const RoundArgs &a)
     constexpr int HK = g5.HK, A = g5.A, R = g5.R, NCH = g5.NCH;
     constexpr int CF = (int)g5.chunk, CV = CF / 4;   // floats, 16-byte vectors per chunk
     extern __shared__ u32x4 lds[];
-    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63;
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
     __shared__ long long s_item;
     __shared__ SrcTime<float> s_tf[256];   // source time factors of a window of blockDim.x steps
+    __shared__ float s_red[2][4][64];      // sparse rounds: each wave's share of u and v
     cptr<GroupDesc> groups = as_const(a.groups);
     cptr<NodeDesc> nodes = as_const(a.nodes);
     const int64_t total = a.batch_prefix[a.n_groups];
+    // Sparse rounds (few live paths, set by the round's prep kernel): an item is
+    // 64 paths that every wave of the block walks alike; wave w runs its share
+    // of each tile's k-steps, the shares are summed in wave order, and wave 0
+    // alone writes results, state and counts.
+    const int bsz = (int)a.batch_prefix[a.n_groups + 1];
+    const bool split = bsz < nthr;
+    const int nparts = split ? nthr >> 6 : 1, part = split ? wave : 0;
+    const bool writer = !split || wave == 0;
     unsigned long long evals = 0, slots = 0;
     using State = PathState<float, 5>;
     const State *sin = (const State *)a.state_in;
@@ -222,7 +258,7 @@ __device__ __forceinline__ void advance_mma5_body(const RoundArgs &a)
         const float *gtab = (const float *)a.slab_table + G->slab_mma;
 
         // ---- this lane's path
-        const int64_t p = b * a.batch + tid;
+        const int64_t p = b * bsz + (split ? lane : tid);
         bool alive = p < live;
         uint32_t node = 0, sample = 0, c0 = 0;
         float X[5] = {0.f, 0.f, 0.f, 0.f, 0.f}, acc = 0.f, comp = 0.f;
@@ -274,10 +310,11 @@ __device__ __forceinline__ void advance_mma5_body(const RoundArgs &a)
                 }
                 if (!inside) {   // path ended: L = q
                     alive = false;
-                    a.result[(int64_t)nodes[node].out * a.mcount + (sample - a.m0)] = (double)acc - (double)comp;
+                    if (writer)
+                        a.result[(int64_t)nodes[node].out * a.mcount + (sample - a.m0)] = (double)acc - (double)comp;
                 }
             }
-            ++slots;
+            if (writer) ++slots;
             // ---- u and v at X_q: the step's chunks, the next one always in flight
             const bool wave_live = __ballot(alive) != 0ull;
             float a3[P], b3[P], a4[HK], b4[HK], L1[P], L2[P];
@@ -302,7 +339,8 @@ __device__ __forceinline__ void advance_mma5_body(const RoundArgs &a)
                         stage_next(k0 * A + t);
                         if (wave_live) {
                             f32x16 uA, vA, uB, vB;
-                            mma5_tile<P>((const float *)(lds + buf * CV), lane, a3, b3, a4, b4, uA, vA, uB, vB);
+                            mma5_tile_part<P>(part, nparts, (const float *)(lds + buf * CV), lane, a3, b3, a4, b4,
+                                              uA, vA, uB, vB);
                             mma5_fold_main<P>(t, uA, vA, uB, vB, L2, au, av);
                         }
                         mma_stage_wait();
@@ -330,12 +368,24 @@ __device__ __forceinline__ void advance_mma5_body(const RoundArgs &a)
                     stage_next(P * A + t);
                     if (wave_live) {
                         f32x16 uA, vA, uB, vB;
-                        mma5_tile<P>((const float *)(lds + buf * CV), lane, a3, b3, a4, b4, uA, vA, uB, vB);
+                        mma5_tile_part<P>(part, nparts, (const float *)(lds + buf * CV), lane, a3, b3, a4, b4, uA, vA,
+                                          uB, vB);
                         mma5_fold_rem<P>(t, uA, vA, uB, vB, L0, L1, L2, u, v);
                     }
                     mma_stage_wait();
                     __syncthreads();
                     buf ^= 1;
+                }
+            }
+            if (split) {   // the waves' shares of u and v, summed in wave order
+                s_red[0][wave][lane] = u;
+                s_red[1][wave][lane] = v;
+                __syncthreads();
+                u = 0.f;
+                v = 0.f;
+                for (int k = 0; k < nparts; ++k) {
+                    u += s_red[0][k][lane];
+                    v += s_red[1][k][lane];
                 }
             }
             if (alive) {   // residual at X_q, time tau_q = t_{n,l} - q Delta
@@ -347,14 +397,14 @@ __device__ __forceinline__ void advance_mma5_body(const RoundArgs &a)
                 acc = tt;
 #pragma unroll
                 for (int i = 0; i < 5; ++i) X[i] = Y[i];
-                ++evals;
+                if (writer) ++evals;
             }
             if (__syncthreads_or(alive ? 1 : 0) == 0) { ++q; break; }
         }
 
         // ---- paths alive after the round: finished at N*, or carried to the next round
-        const bool carry = alive && q1 < nstar;
-        if (alive && !carry)
+        const bool carry = writer && alive && q1 < nstar;
+        if (writer && alive && !carry)
             a.result[(int64_t)nodes[node].out * a.mcount + (sample - a.m0)] = (double)acc - (double)comp;
         const unsigned long long mask = __ballot(carry);
         if (mask != 0ull) {

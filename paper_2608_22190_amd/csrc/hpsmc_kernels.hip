@@ -621,48 +621,64 @@ size_t path_state_bytes(int fp32, int dim)
 }
 
 __global__ void round_prep_kernel(const GroupDesc *__restrict__ groups, int32_t n_groups, int32_t round,
-                                  int32_t steps, int64_t mcount, int32_t batch, const uint32_t *__restrict__ live_in,
+                                  int32_t steps, int64_t mcount, int32_t batch, int32_t batch_split,
+                                  int64_t split_max, const uint32_t *__restrict__ live_in,
                                   uint32_t *__restrict__ live_out, int64_t *__restrict__ batch_prefix,
                                   unsigned long long *work)
 {
     // one block of 256 threads: clear the output counters, then an exclusive
     // prefix over groups of their work items (each thread a contiguous chunk,
-    // a scan of the 256 chunk sums in LDS, then the chunks again)
-    __shared__ int64_t part[256];
+    // a scan of the 256 chunk sums in LDS, then the chunks again).  With
+    // batch_split > 0 a round whose paths fit in at most split_max items of
+    // batch_split paths takes that batch instead; batch_prefix[n_groups + 1]
+    // holds the paths per item the round kernel is to use.
+    __shared__ int64_t part[256], part_s[256];
+    __shared__ int32_t s_batch;
     const int t = threadIdx.x, nt = blockDim.x;
     for (int g = t; g < n_groups; g += nt) live_out[g] = 0u;
     const int64_t q0 = (int64_t)round * steps;
-    auto items = [&](int g) -> int64_t {
+    auto items = [&](int g, int32_t bsz) -> int64_t {
         int64_t live = round == 0 ? (int64_t)groups[g].node_count * mcount : (int64_t)live_in[g];
         if (q0 >= groups[g].nstar) live = 0;
-        return (live + batch - 1) / batch;
+        return (live + bsz - 1) / bsz;
     };
     const int chunk = (n_groups + nt - 1) / nt;
     const int g0 = min(n_groups, t * chunk), g1 = min(n_groups, g0 + chunk);
-    int64_t sum = 0;
-    for (int g = g0; g < g1; ++g) sum += items(g);
+    int64_t sum = 0, sum_s = 0;
+    for (int g = g0; g < g1; ++g) {
+        sum += items(g, batch);
+        if (batch_split > 0) sum_s += items(g, batch_split);
+    }
     part[t] = sum;
+    part_s[t] = sum_s;
     __syncthreads();
     if (t == 0) {
+        int64_t tot_s = 0;
+        for (int i = 0; i < nt; ++i) tot_s += part_s[i];
+        const bool split = batch_split > 0 && tot_s <= split_max;
+        int64_t *pp = split ? part_s : part;
         int64_t acc = 0;
-        for (int i = 0; i < nt; ++i) { const int64_t v = part[i]; part[i] = acc; acc += v; }
+        for (int i = 0; i < nt; ++i) { const int64_t v = pp[i]; pp[i] = acc; acc += v; }
         batch_prefix[n_groups] = acc;
+        batch_prefix[n_groups + 1] = split ? batch_split : batch;
+        s_batch = split ? batch_split : batch;
         *work = 0ull;
     }
     __syncthreads();
-    int64_t acc = part[t];
+    const int32_t bsz = s_batch;
+    int64_t acc = bsz == batch ? part[t] : part_s[t];
     for (int g = g0; g < g1; ++g) {
         batch_prefix[g] = acc;
-        acc += items(g);
+        acc += items(g, bsz);
     }
 }
 
 hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t round, int32_t steps, int64_t mcount,
-                             int32_t batch, const uint32_t *live_in, uint32_t *live_out, int64_t *batch_prefix,
-                             unsigned long long *work, hipStream_t s)
+                             int32_t batch, int32_t batch_split, int64_t split_max, const uint32_t *live_in,
+                             uint32_t *live_out, int64_t *batch_prefix, unsigned long long *work, hipStream_t s)
 {
     hipLaunchKernelGGL(round_prep_kernel, dim3(1), dim3(256), 0, s, groups, n_groups, round, steps, mcount, batch,
-                       live_in, live_out, batch_prefix, work);
+                       batch_split, split_max, live_in, live_out, batch_prefix, work);
     return hipGetLastError();
 }
 

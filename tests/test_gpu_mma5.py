@@ -8,7 +8,10 @@ innermost two modes as a 32x32x2 matrix-core product over 32-row tiles of
 tiling case of the slab image: all rows in remainder tiles (P = 3, 4, 5), one
 or several main tiles per k0 with a remainder (P = 6, 7, 9, 10), none (P = 8)
 and the largest supported P = 12; sample counts leave ragged waves; short
-rounds carry the path state over; blocks of one, two and four waves.
+rounds carry the path state over; blocks of one, two and four waves.  Rounds
+with few live paths (sparse rounds) run each 64-path item on all the waves of
+a block, each wave taking a share of every tile's k-steps; every case runs
+with that split on and off.
 """
 import numpy as np
 import pytest
@@ -28,10 +31,12 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-def _run(wl, mma, launch, U, m_probe, tag=1):
+def _run(wl, mma, launch, U, m_probe, tag=1, split=1):
     H = _hp()
     with H.Plan(wl) as plan:
         plan.hpsmc_set_option("sample_mfma", mma)
+        plan.hpsmc_set_option("sample_split", split)
+        assert plan.hpsmc_get_option("sample_split") == split
         plan.hpsmc_set_launch(*launch)
         assert plan.hpsmc_get_option("sample_mfma_active") == (2 if mma else 0)
         plan.hpsmc_set_probe(m_probe)
@@ -50,15 +55,23 @@ def test_mma5_kernel_walks_the_vector_kernel_paths(n, deg, M, launch):
     _say("mma5 vs valu", n, deg, M, launch)
     U = np.random.default_rng(n).standard_normal((1, wl.nsp, deg + 1)) * 0.5
     mp = min(M, 4)
-    pm, em, sm = _run(wl, 1, launch, U, mp)
     pv, ev, sv = _run(wl, 0, launch, U, mp)
-    assert sm["path_steps"] == sv["path_steps"]
-    assert sm["node_samples"] == sv["node_samples"] == wl.nsp * deg * M
     scale = 1.0 + np.max(np.abs(pv))
-    dmv = np.max(np.abs(pm - pv))
-    print(f"max|S_mma - S_valu| = {dmv:.3e} (scale {scale:.3e}), path steps {sm['path_steps']}")
-    assert dmv <= 1e-4 * scale
-    assert np.max(np.abs(em - ev)) <= 1e-4 * scale
+    runs = {}
+    for split in (1, 0):   # sparse rounds on all the block's waves, or never
+        pm, em, sm = runs[split] = _run(wl, 1, launch, U, mp, split=split)
+        assert sm["path_steps"] == sv["path_steps"]
+        assert sm["node_samples"] == sv["node_samples"] == wl.nsp * deg * M
+        dmv = np.max(np.abs(pm - pv))
+        print(f"split={split}: max|S_mma - S_valu| = {dmv:.3e} (scale {scale:.3e}), path steps {sm['path_steps']}")
+        assert dmv <= 1e-4 * scale
+        assert np.max(np.abs(em - ev)) <= 1e-4 * scale
+    if launch[1] in (2, 4):
+        # these small sets leave sparse rounds: the split rounds sum u and v in another order
+        assert not np.array_equal(runs[1][0], runs[0][0])
+    else:
+        assert np.array_equal(runs[1][0], runs[0][0])
+    pm = runs[1][0]
     # sampled paths against the FP64 oracle: no less accurate than the vector-unit kernel
     pb = O.Problem(wl)
     Ut = O.reconstruct(5, n, deg, U[0].reshape(-1))
