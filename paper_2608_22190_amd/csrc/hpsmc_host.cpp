@@ -2437,6 +2437,14 @@ hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t 
     return fail(HPSMC_EINVAL, std::string("unknown option ") + name);
 }
 
+// Form of the adjoint kernel: 0 vector units; 1 outer products on the matrix
+// cores; 2 (d = 2, slabs in the matrix-core layout) u* on the matrix cores too.
+static int adjoint_mfma_mode(const hpsmc_plan *plan, const NodeSet &set)
+{
+    if (!plan->fp32 || !plan->adj_use_mfma) return 0;
+    return plan->d == 2 && plan->P <= 2 * kAdjMma2MaxKH && set.slab.slab_off_mma ? 2 : 1;
+}
+
 static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hipStream_t s)
 {
     const int G = (int)set.ghost.size();
@@ -2444,12 +2452,13 @@ static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hi
     // tables over half of the block's samples, and the halves meet in LDS
     // before the atomics into the slab-adjoint table; the vector form sums one
     // wave's
-    const int mfma = plan->fp32 && plan->adj_use_mfma;
+    const int mfma = adjoint_mfma_mode(plan, set);
     const int waves = mfma ? 4 : 1;
     const int nthr = 64 * waves;
-    const size_t lds = adjoint_lds_bytes(plan->fp32, mfma, plan->d, plan->P, nthr, set.slab.slab_stride);
+    const size_t lds = mfma == 2 ? adjoint_mma2_lds_bytes(plan->P, nthr)
+                                 : adjoint_lds_bytes(plan->fp32, mfma, plan->d, plan->P, nthr, set.slab.slab_stride);
     const int64_t nvec = set.slab.slab_stride * (plan->fp32 ? 4 : 8) / 16;
-    if (nvec > 4LL * nthr || lds > 65536) return fail(HPSMC_ENOTSUP, "slab too large for the adjoint kernel");
+    if ((mfma != 2 && nvec > 4LL * nthr) || lds > 65536) return fail(HPSMC_ENOTSUP, "slab too large for the adjoint kernel");
     const int C = plan->round_steps;
     const int R = (set.max_nstar + C - 1) / C;
     AdjointArgs aa{};
@@ -2466,10 +2475,11 @@ static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hi
     a.key0 = (uint32_t)plan->pb.seed;
     a.key1 = (uint32_t)(plan->pb.seed >> 32);
     a.slab_table = plan->slab_table;
-    a.slab_stride = set.slab.slab_stride;
+    a.slab_stride = mfma == 2 ? set.slab.mma_stride : set.slab.slab_stride;
     a.work = plan->counters;
     a.stats = plan->counters + 1;
     a.phys = physics_of(plan);
+    aa.bar_stride = set.slab.slab_stride;
     aa.lambda = plan->lam;
     aa.slab_bar = plan->slab_bar;
     aa.inv_M = 1.0 / (double)plan->pb.M;
@@ -2551,6 +2561,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
         HIP_TRY(hipMemcpyAsync(plan->cv, plan->hist_v + (size_t)k * csz, csz * 8, hipMemcpyDeviceToDevice, s));
         SlabArgs sa = set.slab;
         sa.slab_table = plan->slab_table;
+        sa.layout = adjoint_mfma_mode(plan, set) == 2 ? 1 : 0;   // the slabs in the layout the adjoint reads
         HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
         HIP_TRY(launch_fill_u64((unsigned long long *)plan->slab_bar, (int64_t)(plan->slab_bytes / 8), 0ull, s));
         if ((st = adjoint_sampling(plan, set, plan->pb.fresh_per_iter ? k : 0, s))) return st;

@@ -112,7 +112,9 @@ struct AdjointArgs {
     const double *lambda;        // nodal adjoint, U layout
     void *slab_bar;              // slab-adjoint table, slab layout, type T
     double inv_M;                // 1/M
-    int32_t use_mfma;            // FP32 only: outer products on the matrix cores
+    int32_t use_mfma;            // FP32 only: 1 outer products on the matrix cores; 2 (d = 2) u* too, from
+                                 // the slabs in the matrix-core layout (r.slab_stride, GroupDesc::slab_mma)
+    int64_t bar_stride;          // elements per step of the slab-adjoint table (row layout, GroupDesc::slab)
 };
 
 // Time contraction of the modal coefficients into per-step spatial slabs.
@@ -235,6 +237,10 @@ size_t path_state_bytes(int fp32, int dim);
 hipError_t launch_adjoint(const AdjointArgs &a, int fp32, int waves_per_block, int blocks, size_t lds_bytes,
                           hipStream_t s);
 size_t adjoint_lds_bytes(int fp32, int mfma, int dim, int P, int nthr, int64_t slab_stride);
+size_t adjoint_mma2_lds_bytes(int P, int nthr);
+// the 2-D adjoint with u* on the matrix cores covers KH = ceil(P/2) <= 10 (past
+// that its registers spill; larger P keep u* on the vector units)
+constexpr int kAdjMma2MaxKH = 10;
 hipError_t launch_slab_adjoint(const SlabArgs &a, int32_t groups_per_inst, int32_t n_inst, int fp32, double *cbar_u,
                                double *cbar_v, int64_t coef_inst_stride, hipStream_t s);
 hipError_t launch_loss_lambda(const double *U, const double *target, int n_inst, int64_t nsp, int T1, double *lambda,

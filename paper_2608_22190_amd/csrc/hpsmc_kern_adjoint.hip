@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFMA ?
             }
             __syncthreads();
             // ---- block sum of the outer products into the slab adjoint of step q
-            T *dstq = gbar + (int64_t)q * a.slab_stride;
+            T *dstq = gbar + (int64_t)q * aa.bar_stride;
             if constexpr (MFMA) {
                 // wave w forms tile w & 1 (0: the f'(u)-weighted table, 1: the
                 // plain one) over half w >> 1 of the block's samples, two samples
@@ -317,6 +317,236 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFMA ?
     }
 }
 
+// ===========================================================================
+// Two-dimensional FP32 form with u* on the matrix cores as well: the lanes
+// read the u-table operands of the forward kernel's contraction (32 rows k0
+// per column k1, monic basis) straight from the slab image in the matrix-core
+// layout (coalesced 128-byte rows, L2-resident: every block of a group reads
+// the same image), and run its products and epilogue in the same order
+// -- so u*(X_q), and with it f'(u*), is bit for bit the forward kernel's.  No
+// slab passes through LDS; the weighted outer products are the form above.
+// Templated on KH = ceil(P/2): every per-sample loop has a fixed trip count.
+// ===========================================================================
+size_t adjoint_mma2_lds_bytes(int P, int nthr)
+{
+    const int K2 = 2 * ((P + 1) / 2);
+    return ((size_t)2 * K2 * (nthr + 4) + 2 * nthr) * 4 + 2 * 16 * 64 * 4;
+}
+
+template <int KH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) adjoint_mma2_kernel(AdjointArgs aa)
+{
+    constexpr int K2 = 2 * KH;
+    const RoundArgs &a = aa.r;
+    extern __shared__ u32x4 lds[];
+    const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
+    const int P = a.P, PP = a.PP;
+    // [i][sample] tables of the basis values L_i(x_0) (Am) and L_j(x_1) (Bm),
+    // rows NST = nthr + 4 floats apart, the two weights Wm [2][sample], and
+    // the upper half's tiles gsum [2][16][64]
+    const int NST = nthr + 4;
+    float *Am = (float *)lds;
+    float *Bm = Am + K2 * NST;
+    float *Wm = Bm + K2 * NST;
+    float *gsum = Wm + 2 * nthr;
+    __shared__ long long s_item;
+    cptr<GroupDesc> groups = as_const(a.groups);
+    cptr<NodeDesc> nodes = as_const(a.nodes);
+    const int64_t total = a.batch_prefix[a.n_groups];
+    using State = PathState<float, 2>;
+    const State *sin = (const State *)a.state_in;
+    State *sout = (State *)a.state_out;
+    float *sbar = (float *)aa.slab_bar;
+    // this lane's u-table operands in a step's image: column (lane / 32) KH + kk, row lane % 32
+    const int aoff = (lane >> 5) * KH * kMmaRS + (lane & 31);
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (long long)atomicAdd(a.work, 1ull);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;
+        int lo = 0, hi = a.n_groups - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.batch_prefix[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const int g = lo;
+        const int64_t b = item - a.batch_prefix[g];
+        cptr<GroupDesc> G = groups + g;
+        const int nstar = G->nstar;
+        const int q0 = a.round * a.steps;
+        const int q1 = min(q0 + a.steps, nstar);
+        const float J = (float)G->jump;
+        const double ddelta = G->delta;
+        const uint32_t c3 = G->c3 | (uint32_t)a.tag;
+        const int64_t live = a.round == 0 ? (int64_t)G->node_count * a.mcount : (int64_t)a.live_in[g];
+        const float *gtab = (const float *)a.slab_table + G->slab_mma;
+        float *gbar = sbar + G->slab;
+
+        float x0 = 0.f, x1 = 0.f, lam = 0.f;
+        uint32_t node = 0, sample = 0, c0 = 0;
+        const int64_t p = b * a.batch + tid;
+        bool alive = p < live;
+        if (alive) {
+            if (a.round == 0) {
+                node = (uint32_t)(G->node_begin + p / a.mcount);
+                sample = (uint32_t)(a.m0 + p % a.mcount);
+                x0 = (float)nodes[node].x0[0];
+                x1 = (float)nodes[node].x0[1];
+            } else {
+                const State st = sin[G->path_off + p];
+                x0 = st.x[0];
+                x1 = st.x[1];
+                node = st.node;
+                sample = st.sample;
+            }
+            c0 = nodes[node].c0;
+            lam = (float)(aa.lambda[nodes[node].u_index] * ddelta * aa.inv_M);
+        }
+        uint32_t w[4];
+        for (int q = q0; q < q1; ++q) {
+            // this step's operands, in flight under the walk step
+            const float *gq = gtab + (int64_t)q * a.slab_stride;   // uniform: lanes add a 32-bit offset
+            float au[KH];
+#pragma unroll
+            for (int kk = 0; kk < KH; ++kk) au[kk] = gq[aoff + kk * kMmaRS];
+            if ((q & 3) == 0 || q == q0) philox(c0, sample, (uint32_t)(q >> 2), c3, a.key0, a.key1, w);
+            const int wi = q & 3;
+            const uint32_t word = wi == 0 ? w[0] : wi == 1 ? w[1] : wi == 2 ? w[2] : w[3];
+            float d0, d1, y0 = x0, y1 = x1;
+            angle_dir(u01(word, 0.f), d0, d1);
+            if (alive) {
+                y0 = fmaf(J, d0, x0);
+                y1 = fmaf(J, d1, x1);
+                alive = fabsf(y0) < 1.f && fabsf(y1) < 1.f;
+            }
+            // ---- weights of this evaluation: lambda Delta/M f'(u*(X_q)) and lambda Delta/M
+            float wu = 0.f, wv = 0.f;
+            if (__ballot(alive) != 0ull) {
+                float b0[KH], b1[KH];
+                mma_operands<KH>(x1, P, b0, b1);
+                f32x16 du0 = {}, du1 = {}, dv = {};
+#pragma unroll
+                for (int kk = 0; kk < KH; ++kk) {
+                    du0 = __builtin_amdgcn_mfma_f32_32x32x2f32(au[kk], b0[kk], du0, 0, 0, 0);
+                    du1 = __builtin_amdgcn_mfma_f32_32x32x2f32(au[kk], b1[kk], du1, 0, 0, 0);
+                }
+                float u = 0.f, v = 0.f;
+                mma_epilogue<KH, true>(du0, dv, du1, dv, x0, u, v);
+                if (alive) {
+                    wv = lam;
+                    wu = lam * fprime_of<float>(a.phys, u);
+                }
+            }
+            // ---- outer-product factors of this sample: rows L(X_0) weighted, columns L(X_1)
+            Wm[tid] = wu;
+            Wm[nthr + tid] = wv;
+            {
+                float lp = 0.f, lc = 1.f, mp = 0.f, mc = 1.f;
+#pragma unroll
+                for (int i = 0; i < K2; ++i) {
+                    Am[i * NST + tid] = lc;
+                    Bm[i * NST + tid] = mc;
+                    const float ai = (float)((2.0 * i + 1.0) / (i + 1.0)), bi = (float)(i / (i + 1.0));
+                    const float nx = ai * x0 * lc - bi * lp, ny = ai * x1 * mc - bi * mp;
+                    lp = lc;
+                    lc = nx;
+                    mp = mc;
+                    mc = ny;
+                }
+            }
+            if (alive) {
+                x0 = y0;
+                x1 = y1;
+            }
+            __syncthreads();
+            // ---- block sum of the outer products into the slab adjoint of step q
+            // (the matrix-core form of the kernel above: wave w forms tile w & 1 over
+            // half w >> 1 of the samples; rows and columns >= P are not written out)
+            float *dstq = gbar + (int64_t)q * aa.bar_stride;
+            const int tile = wave & 1, half = wave >> 1, i = lane & 31;
+            constexpr int hs = 128;
+            const int ri = i < K2 ? i : K2 - 1;
+            const int base = half * hs + (lane >> 5) * (hs / 2);
+            const float4 *ap = (const float4 *)(Am + ri * NST + base);
+            const float4 *bp = (const float4 *)(Bm + ri * NST + base);
+            const float4 *wp = (const float4 *)(Wm + tile * nthr + base);
+            f32x16 c = {};
+            // operands one group ahead of the products; the fence keeps the
+            // scheduler from hoisting every group's reads (register spills)
+            float4 a4 = ap[0], b4 = bp[0], w4 = wp[0];
+#pragma unroll
+            for (int m = 0; m < hs / 8; ++m) {
+                float4 a4n = a4, b4n = b4, w4n = w4;
+                if (m + 1 < hs / 8) {
+                    a4n = ap[m + 1];
+                    b4n = bp[m + 1];
+                    w4n = wp[m + 1];
+                }
+                c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.x * a4.x, b4.x, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.y * a4.y, b4.y, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.z * a4.z, b4.z, c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.w * a4.w, b4.w, c, 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                a4 = a4n;
+                b4 = b4n;
+                w4 = w4n;
+            }
+            float *cm = gsum + tile * 16 * 64 + lane;
+            if (half == 1) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) cm[r * 64] = c[r];
+            }
+            const int any_alive = __syncthreads_or(alive ? 1 : 0);
+            if (half == 0) {
+                // row ii = 8 (r / 4) + 4 (lane / 32) + r % 4 of tile `tile`, column i:
+                // a lane offset plus a uniform row offset from the step's uniform base
+                const int ii0 = 4 * (lane >> 5), loff = ii0 * 2 * PP + tile * PP + i;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int rr = 8 * (r >> 2) + (r & 3);
+                    const float val = c[r] + cm[r * 64];
+                    if (ii0 + rr < P && i < P && val != 0.f) atomicAdd(dstq + (loff + rr * 2 * PP), val);
+                }
+            }
+            if (any_alive == 0) break;
+        }
+        // survivors to the next round
+        const bool carry = alive && q1 < nstar;
+        const unsigned long long mask = __ballot(carry);
+        if (mask != 0ull) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(a.live_out + g, (uint32_t)__popcll(mask));
+            base = __shfl(base, 0, 64);
+            if (carry) {
+                const uint32_t off = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                State st;
+                st.x[0] = x0;
+                st.x[1] = x1;
+                st.acc = 0.f;
+                st.comp = 0.f;
+                st.node = node;
+                st.sample = sample;
+                sout[G->path_off + off] = st;
+            }
+        }
+    }
+}
+
+template <int KH>
+static hipError_t adj_mma2(const AdjointArgs &a, int kh, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    if constexpr (KH > kAdjMma2MaxKH) {
+        return hipErrorInvalidValue;
+    } else {
+        if (kh != KH) return adj_mma2<KH + 1>(a, kh, grid, block, lds, s);
+        if (block.x != 256 || lds < adjoint_mma2_lds_bytes(a.r.P, 256)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((adjoint_mma2_kernel<KH>), grid, block, lds, s, a);
+        return hipGetLastError();
+    }
+}
+
 template <typename T, int D, int PMAX>
 static hipError_t adj_mfma(const AdjointArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
 {
@@ -341,6 +571,10 @@ hipError_t launch_adjoint(const AdjointArgs &a, int fp32, int waves_per_block, i
                           hipStream_t s)
 {
     dim3 block(64 * waves_per_block), grid(blocks);
+    if (a.use_mfma == 2) {
+        if (!fp32 || a.r.phys.dim != 2 || a.r.P < 3 || a.r.P > 2 * kAdjMma2MaxKH) return hipErrorInvalidValue;
+        return adj_mma2<2>(a, (a.r.P + 1) / 2, grid, block, lds_bytes, s);
+    }
     if (a.r.phys.dim == 1) return fp32 ? adj_p<float, 1>(a, grid, block, lds_bytes, s) : adj_p<double, 1>(a, grid, block, lds_bytes, s);
     if (a.r.phys.dim == 2) return fp32 ? adj_p<float, 2>(a, grid, block, lds_bytes, s) : adj_p<double, 2>(a, grid, block, lds_bytes, s);
     return hipErrorInvalidValue;

@@ -86,6 +86,23 @@ def test_fp32_mfma_and_vector_outer_products_agree(dim, n):
     assert np.max(np.abs(g1 - g64)) <= 1e-3 * np.max(np.abs(g64))
 
 
+def test_fp32_adjoint_past_p20_keeps_the_outer_product_form():
+    """P = 21: past the range of the form that also takes u* on the matrix
+    cores, the adjoint keeps u* on the vector units and the outer products on
+    the matrix cores; it must agree with the all-vector form (FP32 both)."""
+    H = _hp()
+    wl, c0, target = _problem(dim=2, n=19, deg=2, M=64, precision="fp32", I=2, nstar=60)
+    _say("adjoint p21 mfma vs valu")
+    res = {}
+    for mf in (1, 0):
+        with H.Plan(wl) as plan:
+            plan.hpsmc_set_option("adjoint_mfma", mf)
+            res[mf] = plan.hpsmc_loss_grad_c0(target)
+    assert np.array_equal(res[0][0], res[1][0])
+    g1, g0 = res[1][1], res[0][1]
+    assert np.max(np.abs(g1 - g0)) <= 1e-5 * (1 + np.max(np.abs(g0)))
+
+
 def test_autograd_function_uses_the_adjoint():
     import torch
     H = _hp()
