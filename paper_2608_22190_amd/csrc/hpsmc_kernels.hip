@@ -723,59 +723,79 @@ hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mc
     return hipGetLastError();
 }
 
-// Transpose of the slab kernel: cbar[inst][k][q'] = sum over the instance's
-// node times l and steps q of Sbar_{g,q}[k] L_{q'}(xi_{l,q}).
+// Transpose of the slab kernel: cbar[inst][k][m] = sum over the instance's
+// node times l and steps q of Sbar_{g,q}[k] L_m(xi_{l,q}).  A block takes one
+// instance and 256 consecutive entries e of the row layout ([row][u: PP][v:
+// PP]) and streams their columns over every step of every group of the
+// instance: one coalesced 1 KiB row per step, eight steps' loads in flight per
+// thread, the Legendre values of kSlabQ steps at a time in LDS (computed once
+// per block).  Each entry's sums run over (l, q) in order, with the
+// recurrence of the slab kernel.
 template <typename T>
-__global__ void slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t n_inst, double *__restrict__ cbar_u,
-                                    double *__restrict__ cbar_v, int64_t coef_inst_stride)
+__global__ void __launch_bounds__(256) slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t n_inst,
+                                                           double *__restrict__ cbar_u, double *__restrict__ cbar_v,
+                                                           int64_t coef_inst_stride)
 {
-    const int64_t psp = (int64_t)a.rows * a.P;
-    const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)n_inst * 2 * psp) return;
-    const int inst = (int)(idx / (2 * psp));
-    const int64_t rem = idx - (int64_t)inst * 2 * psp;
-    const int uv = (int)(rem / psp);
-    const int64_t k = rem - uv * psp;
-    const int64_t row = k / a.P;
-    const int kl = (int)(k - row * a.P);
+    __shared__ double Lq[kSlabQ][kMaxDeg + 2];
+    constexpr int QB = 8;   // loads in flight per thread
+    const int inst = blockIdx.y;
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t row = e / (2 * a.PP);
+    const int rem = (int)(e - row * 2 * a.PP), uv = rem / a.PP, kl = rem - uv * a.PP;
+    const bool live = e < a.slab_stride && kl < a.P;
     const T *tab = (const T *)a.slab_table;
-    double accq[kMaxDeg + 1];
     const int T1 = a.deg[inst * groups_per_inst] + 1;
+    double acc[kMaxDeg + 1];
 #pragma unroll
-    for (int m = 0; m <= kMaxDeg; ++m) accq[m] = 0.0;
+    for (int m = 0; m <= kMaxDeg; ++m) acc[m] = 0.0;
     for (int gl = 0; gl < groups_per_inst; ++gl) {
         const int g = inst * groups_per_inst + gl;
         const int nstar = a.nstar[g];
         const double span = a.span[g], delta = a.delta[g], h2 = a.h2[g];
-        const T *src = tab + a.slab_off[g] + row * 2 * a.PP + uv * a.PP + kl;
-        for (int q = 0; q < nstar; ++q) {
-            const double val = (double)src[(int64_t)q * a.slab_stride];
-            if (val == 0.0) continue;
-            const double xi = h2 * (span - (double)q * delta) - 1.0;
-            double lp = 0.0, lc = 1.0;
-            // fully unrolled with a guard so that accq stays in registers
-#pragma unroll
-            for (int m = 0; m <= kMaxDeg; ++m) {
-                if (m < T1) {
-                    accq[m] = fma(val, lc, accq[m]);
+        const T *src = tab + a.slab_off[g] + (live ? e : 0);
+        for (int q0 = 0; q0 < nstar; q0 += kSlabQ) {
+            const int qn = min(kSlabQ, nstar - q0);
+            __syncthreads();   // the previous chunk's reads of Lq are over
+            if ((int)threadIdx.x < qn) {
+                const double xi = h2 * (span - (double)(q0 + (int)threadIdx.x) * delta) - 1.0;
+                double lp = 0.0, lc = 1.0;
+                for (int m = 0; m < T1; ++m) {
+                    Lq[threadIdx.x][m] = lc;
                     const double nx = c_rec.ad[m] * xi * lc - c_rec.bd[m] * lp;
                     lp = lc;
                     lc = nx;
                 }
             }
+            __syncthreads();
+            if (!live) continue;
+            for (int j0 = 0; j0 < qn; j0 += QB) {
+                double v[QB];
+#pragma unroll
+                for (int j = 0; j < QB; ++j)
+                    v[j] = j0 + j < qn ? (double)src[(int64_t)(q0 + j0 + j) * a.slab_stride] : 0.0;
+#pragma unroll
+                for (int j = 0; j < QB; ++j) {
+                    if (v[j] == 0.0) continue;
+                    // fully unrolled with a guard so that acc stays in registers
+#pragma unroll
+                    for (int m = 0; m <= kMaxDeg; ++m)
+                        if (m < T1) acc[m] = fma(v[j], Lq[j0 + j][m], acc[m]);
+                }
+            }
         }
     }
-    double *out = (uv ? cbar_v : cbar_u) + (int64_t)inst * coef_inst_stride + k * T1;
+    if (!live) return;
+    double *out = (uv ? cbar_v : cbar_u) + (int64_t)inst * coef_inst_stride + (row * a.P + kl) * T1;
 #pragma unroll
     for (int m = 0; m <= kMaxDeg; ++m)
-        if (m < T1) out[m] = accq[m];
+        if (m < T1) out[m] = acc[m];
 }
 
 hipError_t launch_slab_adjoint(const SlabArgs &a, int32_t groups_per_inst, int32_t n_inst, int fp32, double *cbar_u,
                                double *cbar_v, int64_t coef_inst_stride, hipStream_t s)
 {
-    const int64_t n = (int64_t)n_inst * 2 * a.rows * a.P;
-    dim3 grid((unsigned)((n + 127) / 128)), block(128);
+    if (n_inst <= 0) return hipSuccess;
+    dim3 grid((unsigned)((a.slab_stride + 255) / 256), (unsigned)n_inst), block(256);
     if (fp32)
         hipLaunchKernelGGL(slab_adjoint_kernel<float>, grid, block, 0, s, a, groups_per_inst, n_inst, cbar_u, cbar_v, coef_inst_stride);
     else
