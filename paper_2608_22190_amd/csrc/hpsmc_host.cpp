@@ -1169,8 +1169,11 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     const int blocks = std::max(1, plan->cus * plan->launch.blocks_per_cu);
     // rounds of the 5-D matrix-core kernel whose paths fit in one pass of the
     // grid at 64 paths per block run each item on all the block's waves (two or
-    // four), each taking a share of every tile's products
+    // four), each taking a share of every tile's products.  (The 2-D kernel does
+    // several vector instructions per product, which a split wave repeats: it
+    // measured no faster.)
     const int split_batch = mma == 2 && plan->sample_split && (waves == 2 || waves == 4) ? 64 : 0;
+    const int64_t split_max = blocks;
     hpsmc_plan::EvPair *ek = next_pair(plan->ev_span, plan->n_span);
     if (ek) HIP_TRY(hipEventRecord(ek->a, s));
     int first = 1;
@@ -1184,7 +1187,7 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
             a.state_out = set.state[(r + 1) & 1];
             a.live_in = set.live + (r & 1) * G;
             a.live_out = set.live + ((r + 1) & 1) * G;
-            HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, split_batch, blocks, a.live_in, a.live_out,
+            HIP_TRY(launch_round_prep(set.gdev, G, r, C, mc, a.batch, split_batch, split_max, a.live_in, a.live_out,
                                       set.prefix, plan->counters, s));
             hpsmc_plan::EvPair *ea = next_pair(plan->ev_sample, plan->n_sample);
             if (ea) HIP_TRY(hipEventRecord(ea->a, s));
