@@ -19,7 +19,6 @@ namespace hpsmc {
 struct RecTable {
     double ad[kMaxP + 2], bd[kMaxP + 2];
     float af[kMaxP + 2], bf[kMaxP + 2];
-    double mu[kMaxP + 2];   // leading coefficient of L_k: L_k = mu_k Q_k, Q_k monic
 };
 // every translation unit holds its own copy, uploaded by its own setter
 static __constant__ RecTable c_rec;
@@ -33,8 +32,6 @@ static hipError_t upload_recurrence_tables()
         t.af[k] = float(t.ad[k]);
         t.bf[k] = float(t.bd[k]);
     }
-    t.mu[0] = 1.0;
-    for (int k = 0; k + 1 < kMaxP + 2; ++k) t.mu[k + 1] = t.mu[k] * t.ad[k];
     return hipMemcpyToSymbol(HIP_SYMBOL(c_rec), &t, sizeof(t));
 }
 
@@ -531,24 +528,23 @@ __device__ __forceinline__ void mma_stage_wait() { asm volatile("s_waitcnt vmcnt
 // the path, so no lane duplicates another's work.
 // Sb: slab in LDS, transposed: Sb[c * kMmaRS + k0], c = k1 (u) or PP + k1 (v);
 // rows k0 in [P, 32) hold zeros, columns k1 in [P, PP) the slab's zero padding.
-// The image holds the coefficients of the monic basis Q_{k0} Q_{k1} (L_k =
-// mu_k Q_k), so each basis value costs one multiply and one fma.
+// The image holds coefficients in the Chebyshev basis T_{k0} T_{k1} (converted
+// from the Legendre tensors on the host side), whose recurrence T_{k+1} =
+// 2x T_k - T_{k-1} has constant coefficients: one fma per basis value.
 // ---------------------------------------------------------------------------
 
-// B operands: monic Legendre values Q_{k1}(x1) of the wave's 64 points
+// B operands: Chebyshev values T_{k1}(x1) of the wave's 64 points
 template <int KH>
 __device__ __forceinline__ void mma_operands(float x1, int P, float (&b0)[KH], float (&b1)[KH])
 {
     static_assert(KH >= 2 && KH <= 16, "one 32-row tile, at least 4 modes");
     constexpr int K2 = 2 * KH;
-    // monic Legendre polynomials Q_{k+1} = x Q_k - k^2/(4k^2-1) Q_{k-1} (the slab
-    // image holds the coefficients of Q_{k0} Q_{k1})
     float L[K2];
+    const float x2 = x1 + x1;
     L[0] = 1.f;
     L[1] = x1;
 #pragma unroll
-    for (int k = 1; k + 1 < K2; ++k)
-        L[k + 1] = fmaf(x1, L[k], -(float)((double)k * k / (4.0 * k * k - 1.0)) * L[k - 1]);
+    for (int k = 1; k + 1 < K2; ++k) L[k + 1] = fmaf(x2, L[k], -L[k - 1]);
     if (P < K2) L[K2 - 1] = 0.f;   // odd P: mode P does not exist
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
@@ -576,14 +572,15 @@ __device__ __forceinline__ void mma_issue(const float *Sb, int PP, int lane, con
     }
 }
 
-// rows back to the owning lane and the contraction with Q_{k0}(x0) (rows >= P
+// rows back to the owning lane and the contraction with T_{k0}(x0) (rows >= P
 // of T are zero).  Registers r = 4g..4g+3 hold rows 8g..8g+3 (before the swap)
-// and 8g+4..8g+7 (after it): the Legendre values in x0 advance eight at a time.
+// and 8g+4..8g+7 (after it): the Chebyshev values in x0 advance eight at a time.
 template <int KH, bool UO = false>
 __device__ __forceinline__ void mma_epilogue(const f32x16 &du0, const f32x16 &dv0, const f32x16 &du1,
                                              const f32x16 &dv1, float x0, float &u, float &v)
 {
     constexpr int K2 = 2 * KH;
+    const float x02 = x0 + x0;
     float su = 0.f, sv = 0.f, lp = 0.f, lc = 1.f;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -593,7 +590,7 @@ __device__ __forceinline__ void mma_epilogue(const f32x16 &du0, const f32x16 &dv
         for (int j = 0; j < 8; ++j) {
             const int k = 8 * g + j;
             Lb[j] = lc;
-            const float nx = fmaf(x0, lc, -(float)((double)k * k / (4.0 * k * k - 1.0)) * lp);   // monic
+            const float nx = k == 0 ? x0 : fmaf(x02, lc, -lp);   // T_1 = x, T_{k+1} = 2x T_k - T_{k-1}
             lp = lc;
             lc = nx;
         }

@@ -250,6 +250,29 @@ static std::vector<double> legendre_d1(int N)
         for (int m = q + 1; m < N; m += 2) D[(size_t)q * N + m] = 2.0 * q + 1.0;
     return D;
 }
+// A[j][k] (N x N): the Chebyshev coefficients of L_k, L_k = sum_j A[j][k] T_j,
+// from the Legendre recurrence and x T_j = (T_{j+1} + T_{|j-1|}) / 2
+static std::vector<double> legendre_to_chebyshev(int N)
+{
+    std::vector<std::vector<double>> c(N, std::vector<double>(N + 1, 0.0));
+    c[0][0] = 1.0;
+    if (N > 1) c[1][1] = 1.0;
+    for (int k = 1; k + 1 < N; ++k) {
+        std::vector<double> xc(N + 1, 0.0);   // x L_k
+        for (int j = 0; j <= k; ++j) {
+            if (j == 0) { xc[1] += c[k][0]; continue; }
+            xc[j + 1] += 0.5 * c[k][j];
+            xc[j - 1] += 0.5 * c[k][j];
+        }
+        const double a = (2.0 * k + 1.0) / (k + 1.0), b = double(k) / (k + 1.0);
+        for (int j = 0; j <= k + 1; ++j) c[k + 1][j] = a * xc[j] - b * c[k - 1][j];
+    }
+    std::vector<double> A((size_t)N * N);
+    for (int j = 0; j < N; ++j)
+        for (int k = 0; k < N; ++k) A[(size_t)j * N + k] = c[k][j];
+    return A;
+}
+
 static std::vector<double> legendre_d2(int N)
 {
     std::vector<double> D((size_t)N * N, 0.0);
@@ -352,6 +375,10 @@ struct hpsmc_plan {
     std::vector<int64_t> u_off;          // per interval
     double *cu = nullptr, *cv = nullptr; // [iv block][inst][P^d][T1]
     std::vector<int64_t> c_off;          // per interval
+    // 2-D plans the matrix-core kernel can serve: c^u, c^v (and a polynomial
+    // source) in the Chebyshev basis of both spatial dimensions, the slab image's basis
+    double *cu_ch = nullptr, *cv_ch = nullptr, *cs_ch = nullptr;
+    int64_t cheb_off = -1;               // in mats: Legendre -> Chebyshev, A[j][k] = coefficient of T_j in L_k
     double *tmp0 = nullptr, *tmp1 = nullptr;
     double *ic = nullptr;                // [inst][nsp]
     double *mats = nullptr;              // G0 (P x n), D2 (P x P), then per interval Bt, D1
@@ -1211,12 +1238,40 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     return HPSMC_OK;
 }
 
+// Slab arguments for `layout`: the 2-D matrix-core image (layout 1) holds
+// Chebyshev coefficients in both spatial dimensions, so c^u and c^v of the
+// set's intervals are converted first (two mode products per table and
+// interval) and the slab kernel reads the converted tensors.
+static hpsmc_status slab_args_for(hpsmc_plan *plan, const NodeSet &set, int layout, SlabArgs &sa, hipStream_t s)
+{
+    sa = set.slab;
+    sa.slab_table = plan->slab_table;
+    sa.layout = layout;
+    if (layout != 1) return HPSMC_OK;
+    if (!plan->cu_ch) return fail(HPSMC_EINVAL, "no Chebyshev coefficient buffers for the matrix-core layout");
+    const int P = plan->P;
+    const double *A = plan->mats + plan->cheb_off;
+    const int64_t I = plan->n_inst;
+    for (int32_t iv : set.ivs) {
+        const int T1 = plan->degree[iv] + 1;
+        for (int t = 0; t < 2; ++t) {
+            const double *in = (t ? plan->cv : plan->cu) + plan->c_off[iv];
+            double *out = (t ? plan->cv_ch : plan->cu_ch) + plan->c_off[iv];
+            HIP_TRY(launch_mode_product(in, plan->tmp0, I, P, P, (int64_t)P * T1, A, 1.0, 0, s));
+            HIP_TRY(launch_mode_product(plan->tmp0, out, I * P, P, P, T1, A, 1.0, 0, s));
+        }
+    }
+    sa.cu = plan->cu_ch;
+    sa.cv = plan->cv_ch;
+    if (sa.cs) sa.cs = plan->cs_ch;
+    return HPSMC_OK;
+}
+
 static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int record, hipStream_t s)
 {
     const int ns = plan->launch.samples_per_lane;
-    SlabArgs sa = set.slab;
-    sa.slab_table = plan->slab_table;
-    sa.layout = set_uses_mma(plan, set);
+    SlabArgs sa;
+    if (hpsmc_status st = slab_args_for(plan, set, set_uses_mma(plan, set), sa, s)) return st;
     hpsmc_plan::EvPair *es = next_pair(plan->ev_slab, plan->n_slab);
     if (es) HIP_TRY(hipEventRecord(es->a, s));
     HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
@@ -1302,7 +1357,7 @@ void hpsmc_destroy(hpsmc_plan *plan)
     void *ptrs[] = {plan->U, plan->cu, plan->cv, plan->tmp0, plan->tmp1, plan->ic, plan->mats,
                     plan->slab_table, plan->part, plan->counters, plan->maxbits, plan->hist_u, plan->hist_v,
                     plan->lam, plan->cbar_u, plan->cbar_v, plan->dtarget, plan->dloss, plan->dgrad, plan->slab_bar,
-                    plan->frac_tab, plan->src_poly};
+                    plan->frac_tab, plan->src_poly, plan->cu_ch, plan->cv_ch, plan->cs_ch};
     for (void *p : ptrs) dfree(plan, p);
     delete plan;
 }
@@ -1485,6 +1540,14 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
         plan->ainv_off = (int64_t)mats.size();
         mats.insert(mats.end(), Ainv.begin(), Ainv.end());
     }
+    const bool cheb = plan->d == 2 && !plan->frac && mma_capable(pl);   // the 2-D matrix-core image's basis
+    if (cheb) {
+        auto Ach = legendre_to_chebyshev(plan->P);
+        plan->cheb_off = (int64_t)mats.size();
+        mats.insert(mats.end(), Ach.begin(), Ach.end());
+        if ((st = dalloc(pl, (void **)&pl->cu_ch, csz * 8))) return st;
+        if ((st = dalloc(pl, (void **)&pl->cv_ch, csz * 8))) return st;
+    }
     if ((st = dalloc(pl, (void **)&pl->mats, mats.size() * 8))) return st;
     std::vector<double> u0;
     initial_nodes(pl, u0);
@@ -1493,6 +1556,21 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
         hipMemset(pl->counters, 0, 32) != hipSuccess || hipMemset(pl->maxbits, 0, 4096 * 8) != hipSuccess ||
         hipMemset(pl->U, 0, usz * 8) != hipSuccess)
         return fail(HPSMC_EDEVICE, "initial upload failed");
+    if (cheb && pl->src_poly) {   // the polynomial source in the image's basis, once
+        int64_t off = 0;
+        for (int iv = 0; iv < plan->n_iv; ++iv) off += plan->psp * (plan->degree[iv] + 1);
+        if ((st = dalloc(pl, (void **)&pl->cs_ch, off * 8))) return st;
+        const double *A = pl->mats + pl->cheb_off;
+        const int P = plan->P;
+        for (int iv = 0; iv < plan->n_iv; ++iv) {
+            const int T1 = plan->degree[iv] + 1;
+            if (launch_mode_product(pl->src_poly + pl->src_off[iv], pl->tmp0, 1, P, P, (int64_t)P * T1, A, 1.0, 0,
+                                    nullptr) != hipSuccess ||
+                launch_mode_product(pl->tmp0, pl->cs_ch + pl->src_off[iv], P, P, P, T1, A, 1.0, 0, nullptr) !=
+                    hipSuccess)
+                return fail(HPSMC_EDEVICE, "source conversion failed");
+        }
+    }
 
     // node sets and the slab table
     if (pb->schedule == HPSMC_SEQUENTIAL) {
@@ -2562,9 +2640,8 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
     for (int k = K - 1; k >= 0; --k) {
         HIP_TRY(hipMemcpyAsync(plan->cu, plan->hist_u + (size_t)k * csz, csz * 8, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(plan->cv, plan->hist_v + (size_t)k * csz, csz * 8, hipMemcpyDeviceToDevice, s));
-        SlabArgs sa = set.slab;
-        sa.slab_table = plan->slab_table;
-        sa.layout = adjoint_mfma_mode(plan, set) == 2 ? 1 : 0;   // the slabs in the layout the adjoint reads
+        SlabArgs sa;   // the slabs in the layout the adjoint reads
+        if ((st = slab_args_for(plan, set, adjoint_mfma_mode(plan, set) == 2 ? 1 : 0, sa, s))) return st;
         HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
         HIP_TRY(launch_fill_u64((unsigned long long *)plan->slab_bar, (int64_t)(plan->slab_bytes / 8), 0ull, s));
         if ((st = adjoint_sampling(plan, set, plan->pb.fresh_per_iter ? k : 0, s))) return st;

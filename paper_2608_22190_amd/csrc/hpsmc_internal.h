@@ -174,7 +174,8 @@ hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, in
 bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane, int waves_per_block);
 size_t advance_mma_lds_bytes(int PP);
 // matrix-core slab layout: 2 PP columns (u modes k1, then v modes k1) of
-// kMmaRows rows k0 (zeros past P), stored as the kernel's LDS image
+// kMmaRows rows k0 (zeros past P), stored as the kernel's LDS image; the
+// coefficients are those of the Chebyshev basis T_{k0} T_{k1}
 constexpr int kMmaRows = 33;
 inline int64_t mma_slab_elems(int PP) { return (int64_t)2 * PP * kMmaRows; }
 

@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFMA ?
 // ===========================================================================
 // Two-dimensional FP32 form with u* on the matrix cores as well: the lanes
 // read the u-table operands of the forward kernel's contraction (32 rows k0
-// per column k1, monic basis) straight from the slab image in the matrix-core
+// per column k1, Chebyshev basis) straight from the slab image in the matrix-core
 // layout (coalesced 128-byte rows, L2-resident: every block of a group reads
 // the same image), and run its products and epilogue in the same order
 // -- so u*(X_q), and with it f'(u*), is bit for bit the forward kernel's.  No

@@ -370,7 +370,6 @@ __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
                         if (k < T1) c[k] += sp[k];
                 }
             }
-            const double sc = mma && live ? c_rec.mu[kl] * c_rec.mu[row] : 1.0;   // coefficients of Q_{k0} Q_{k1}
             for (int j = 0; j < qn; ++j) {
                 double val = 0.0;
                 if (live) {
@@ -378,7 +377,6 @@ __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
                     for (int k = 0; k <= kMaxDeg; ++k)
                         if (k < T1) val = fma(c[k], Lq[j][k], val);
                 }
-                if (mma) val *= sc;
                 table[base + (int64_t)(q0 + j) * stride + e] = (T)val;
             }
         }
