@@ -232,7 +232,9 @@ def run_other(name, args, torch):
             plan.hpsmc_set_launch(*(int(v) for v in args.launch.split(",")))
         elif args.tune_cache and name in ("c2p", "c2b", "c3", "c4", "c5"):
             t0 = time.perf_counter()
-            plan.hpsmc_tune(0, 256 if name in ("c2p", "c2b") else min(wl.M, 4), args.tune_cache, stream=stream)
+            # tuned on the slice it times (c4: its 16 samples per node), else a short trial
+            plan.hpsmc_tune(0, 256 if name in ("c2p", "c2b") else wl.M if name == "c4" else min(wl.M, 4),
+                            args.tune_cache, stream=stream)
             print(f"[bench] {name} launch {plan.hpsmc_get_launch()} ({time.perf_counter() - t0:.1f}s)",
                   file=sys.stderr, flush=True)
         def step(k):

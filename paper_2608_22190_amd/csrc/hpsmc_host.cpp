@@ -2340,11 +2340,14 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
         if (ms < best_ms) { best_ms = ms; best = c; }
     }
     if (!st) {
-        const int rs_d1[5] = {128, 256, 512, 1024, 128}, rs[5] = {32, 64, 128, 256, 512};
+        // walk steps per round: long rounds for 1-D (cheap steps), short ones from
+        // 3-D on (expensive steps: compaction pays sooner)
+        const int rs_d1[5] = {128, 256, 512, 1024, 128}, rs[5] = {32, 64, 128, 256, 512},
+                  rs_d3[5] = {16, 32, 64, 128, 256};
         const hpsmc_launch base = best;
         for (int k = 0; k < 5; ++k) {
             hpsmc_launch c = base;
-            c.round_steps = plan->d == 1 ? rs_d1[k] : rs[k];
+            c.round_steps = plan->d == 1 ? rs_d1[k] : plan->d == 2 ? rs[k] : rs_d3[k];
             if (c.round_steps == base.round_steps) continue;
             float ms;
             if ((st = trial(c, ms))) break;
