@@ -796,7 +796,15 @@ def main():
         "sampling_span_ms_per_step": st["sampling_span_ms"] / args.steps,
         "advance_launches_per_step": st["advance_launches"] / args.steps,
     }
-    if not args.no_fp64:
+    if args.no_fp64:
+        # FP32 alone: its error against the exact solution after every timed iteration
+        t32 = r32["trajectory"]
+        out["accuracy"] = {
+            "e32_vs_exact": t32[-1][1], "max_node_std_error_fp32": t32[-1][2],
+            "trajectory_fp32": [[round(t, 4), e, s_, m] for t, e, s_, m in t32],
+            "note": "rows: [seconds so far, max error against the exact solution, max node standard error, "
+                    "max|eps|] after each timed iteration from the replicated initial data"}
+    else:
         r64 = run_gpu(base.with_(precision="fp64"), args.steps, args.warmup, launch, torch, args.tune_cache,
                       exact_fn=exact_fn)
         v64 = ns_step * args.steps / r64["seconds"]
