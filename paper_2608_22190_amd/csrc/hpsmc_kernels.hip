@@ -631,7 +631,7 @@ __global__ void round_prep_kernel(const GroupDesc *__restrict__ groups, int32_t 
     // batch_split paths takes that batch instead; batch_prefix[n_groups + 1]
     // holds the paths per item the round kernel is to use.
     __shared__ int64_t part[256], part_s[256];
-    __shared__ int32_t s_batch;
+    __shared__ int32_t s_split;
     const int t = threadIdx.x, nt = blockDim.x;
     for (int g = t; g < n_groups; g += nt) live_out[g] = 0u;
     const int64_t q0 = (int64_t)round * steps;
@@ -659,12 +659,13 @@ __global__ void round_prep_kernel(const GroupDesc *__restrict__ groups, int32_t 
         for (int i = 0; i < nt; ++i) { const int64_t v = pp[i]; pp[i] = acc; acc += v; }
         batch_prefix[n_groups] = acc;
         batch_prefix[n_groups + 1] = split ? batch_split : batch;
-        s_batch = split ? batch_split : batch;
+        s_split = split ? 1 : 0;
         *work = 0ull;
     }
     __syncthreads();
-    const int32_t bsz = s_batch;
-    int64_t acc = bsz == batch ? part[t] : part_s[t];
+    const bool split = s_split != 0;
+    const int32_t bsz = split ? batch_split : batch;
+    int64_t acc = split ? part_s[t] : part[t];
     for (int g = g0; g < g1; ++g) {
         batch_prefix[g] = acc;
         acc += items(g, bsz);
