@@ -237,10 +237,10 @@ def run_other(name, args, torch):
     with hpsmc.Plan(wl) as plan:
         if args.launch:
             plan.hpsmc_set_launch(*(int(v) for v in args.launch.split(",")))
-        elif args.tune_cache and name in ("c2p", "c2b", "c3", "c4", "c5"):
+        elif args.tune_cache and name in ("c1", "c2p", "c2b", "c3", "c4", "c5"):
             t0 = time.perf_counter()
-            # tuned on the slice it times (c4: its 16 samples per node), else a short trial
-            plan.hpsmc_tune(0, 256 if name in ("c2p", "c2b") else wl.M if name == "c4" else min(wl.M, 4),
+            # tuned on the slice it times (c1: all its samples, c4: its 16 per node), else a short trial
+            plan.hpsmc_tune(0, 256 if name in ("c2p", "c2b") else wl.M if name in ("c1", "c4") else min(wl.M, 4),
                             args.tune_cache, stream=stream)
             print(f"[bench] {name} launch {plan.hpsmc_get_launch()} ({time.perf_counter() - t0:.1f}s)",
                   file=sys.stderr, flush=True)

@@ -417,7 +417,14 @@ hpsmc_status hpsmc_set_initial_coeffs(hpsmc_plan *plan, const double *c0, int32_
  *                       same 64 paths and share each step's products (shorter
  *                       rounds when few long paths remain); 0: never.  The
  *                       FP32 sums differ only by rounding order.
- *   "graph"             1: hpsmc_solve captures the whole solve into a hipGraph
+ *   "sample_1d"         1 (default): d = 1 rounds of the residual form with
+ *                       the centre-point rule run the windowed 1-D kernel (the
+ *                       slabs of 32 walk steps staged in LDS per barrier, the
+ *                       same walk and arithmetic as the general kernel); 0: the
+ *                       general vector-unit kernel.
+ *   "sample_1d_active"  read-only: 1 when the rounds run the windowed 1-D
+ *                       kernel with the current launch shape.
+ *   "graph"            1: hpsmc_solve captures the whole solve into a hipGraph
  *                       on its first call (on a stream of the plan) and replays
  *                       it on this and later calls; 0 (default): eager launches.
  *                       A new launch shape discards the captured graph.

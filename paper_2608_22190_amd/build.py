@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhpsmc.so")
 SOURCES = ["hpsmc_kern_valu_f32.hip", "hpsmc_kern_valu_f64.hip", "hpsmc_kern_mma.hip", "hpsmc_kern_mma5.hip",
-           "hpsmc_kern_adjoint.hip", "hpsmc_kern_frac.hip", "hpsmc_kernels.hip", "hpsmc_host.cpp"]
+           "hpsmc_kern_adjoint.hip", "hpsmc_kern_frac.hip", "hpsmc_kern_1d.hip", "hpsmc_kernels.hip",
+           "hpsmc_host.cpp"]
 HEADERS = ["hpsmc_internal.h", "hpsmc_device.h", "hpsmc_round.h", "hpsmc_lobatto_eigs.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

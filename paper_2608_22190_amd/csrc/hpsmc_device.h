@@ -67,14 +67,66 @@ __device__ __forceinline__ float m_fma(float a, float b, float c) { return fmaf(
 __device__ __forceinline__ double u01(uint32_t w, double) { return ((double)w + 0.5) * 0x1p-32; }
 __device__ __forceinline__ float u01(uint32_t w, float) { return ((float)(w >> 8) + 0.5f) * 0x1p-24f; }
 
-// direction angle 2*pi*u
-__device__ __forceinline__ void angle_dir(double u, double &c, double &s)
+// ---------------------------------------------------------------------------
+// sin(pi y) and cos(pi y), branch-free, for |y| < 2^30: y = n/2 + f with
+// n = rint(2y), so |f| <= 1/4 and f = y - n/2 is exact; the Maclaurin series of
+// sin(pi f) and cos(pi f) (|pi f| <= pi/4), truncated where the next term is
+// below 1e-17 (FP64: through f^17 and f^16) or 2e-9 (FP32: through f^9 and
+// f^10); then n quarter turns.  Coefficients (-1)^k pi^(2k+1)/(2k+1)! and
+// (-1)^k pi^(2k)/(2k)!, rounded from 60-digit values.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sincospi_series(double y, double &s, double &c)
 {
-    const double th = 2.0 * 3.14159265358979323846 * u;
-    c = cos(th);
-    s = sin(th);
+    const double n = rint(y + y);
+    const double f = fma(n, -0.5, y);
+    const double z = f * f;
+    double ps = 0x1.aaec32af93359p-21;
+    ps = fma(ps, z, -0x1.6fadb9f155744p-16);
+    ps = fma(ps, z, 0x1.e8f434d018d63p-12);
+    ps = fma(ps, z, -0x1.e3074fde8871fp-8);
+    ps = fma(ps, z, 0x1.50783487ee782p-4);
+    ps = fma(ps, z, -0x1.32d2cce62bd86p-1);
+    ps = fma(ps, z, 0x1.466bc6775aae2p+1);
+    ps = fma(ps, z, -0x1.4abbce625be53p+2);
+    ps = fma(ps, z, 0x1.921fb54442d18p+1);
+    double pc = 0x1.20c62c2f2d7f5p-18;
+    pc = fma(pc, z, -0x1.b6e24f44b128fp-14);
+    pc = fma(pc, z, 0x1.f9d38a3763cc3p-10);
+    pc = fma(pc, z, -0x1.a6d1f2a204a8cp-6);
+    pc = fma(pc, z, 0x1.e1f506891babbp-3);
+    pc = fma(pc, z, -0x1.55d3c7e3cbffap+0);
+    pc = fma(pc, z, 0x1.03c1f081b5ac4p+2);
+    pc = fma(pc, z, -0x1.3bd3cc9be45dep+2);
+    const double sn = ps * f, cs = fma(pc, z, 1.0);
+    const int q = (int)n;
+    const double a = (q & 1) ? cs : sn, b = (q & 1) ? sn : cs;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
 }
-__device__ __forceinline__ void angle_dir(float u, float &c, float &s) { sincospif(2.0f * u, &s, &c); }
+__device__ __forceinline__ void sincospi_series(float y, float &s, float &c)
+{
+    const float n = rintf(y + y);
+    const float f = fmaf(n, -0.5f, y);
+    const float z = f * f;
+    float ps = (float)0x1.50783487ee782p-4;
+    ps = fmaf(ps, z, (float)-0x1.32d2cce62bd86p-1);
+    ps = fmaf(ps, z, (float)0x1.466bc6775aae2p+1);
+    ps = fmaf(ps, z, (float)-0x1.4abbce625be53p+2);
+    ps = fmaf(ps, z, (float)0x1.921fb54442d18p+1);
+    float pc = (float)-0x1.a6d1f2a204a8cp-6;
+    pc = fmaf(pc, z, (float)0x1.e1f506891babbp-3);
+    pc = fmaf(pc, z, (float)-0x1.55d3c7e3cbffap+0);
+    pc = fmaf(pc, z, (float)0x1.03c1f081b5ac4p+2);
+    pc = fmaf(pc, z, (float)-0x1.3bd3cc9be45dep+2);
+    const float sn = ps * f, cs = fmaf(pc, z, 1.0f);
+    const int q = (int)n;
+    const float a = (q & 1) ? cs : sn, b = (q & 1) ? sn : cs;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+}
+
+// direction (cos, sin) of the angle 2*pi*u, u in (0, 1)
+template <typename T> __device__ __forceinline__ void angle_dir(T u, T &c, T &s) { sincospi_series(u + u, s, c); }
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 S-box with
@@ -307,14 +359,22 @@ __device__ __forceinline__ T source_space(const Physics &ph, const T (&X)[D], Sr
     case 1: {
         T p = tf.a;
 #pragma unroll
-        for (int i = 0; i < D; ++i) p *= m_sin(pi * X[i]);
+        for (int i = 0; i < D; ++i) {   // sin(pi x)
+            T sn, cs;
+            sincospi_series(X[i], sn, cs);
+            p *= sn;
+        }
         u = p; ut = -p; lap = -(T)D * pi * pi * p;
         break;
     }
     case 2: {
         T p = tf.a;
 #pragma unroll
-        for (int i = 0; i < D; ++i) p *= m_cos((T)0.5 * pi * X[i]);
+        for (int i = 0; i < D; ++i) {   // cos(pi x / 2)
+            T sn, cs;
+            sincospi_series((T)0.5 * X[i], sn, cs);
+            p *= cs;
+        }
         u = p; ut = -p; lap = (T)(-0.25 * D) * pi * pi * p;
         break;
     }
@@ -334,8 +394,8 @@ __device__ __forceinline__ T source_space(const Physics &ph, const T (&X)[D], Sr
         T S, C;
         if constexpr (BOUNDED && D == 2 && std::is_same<T, float>::value)
             sincos_small(sig, S, C);
-        else
-            m_sincos(sig, S, C);
+        else   // |sig| <= d: sin and cos of pi (sig / pi)
+            sincospi_series(sig * (T)0.31830988618379067154, S, C);
         u = a * S * tf.a;
         ut = a * S * tf.b;
         lap = tf.a * (S * lapa + (T)2 * C * grada - (T)D * a * S);
@@ -619,6 +679,7 @@ hipError_t launch_adv_valu_f64(const RoundArgs &a, int ns, dim3 grid, dim3 block
 hipError_t launch_adv_mma(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 hipError_t launch_adv_mma5(const RoundArgs &a, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 hipError_t launch_adv_frac(const RoundArgs &a, int fp32, dim3 grid, dim3 block, size_t lds, hipStream_t s);
+hipError_t launch_adv_1d(const RoundArgs &a, int fp32, int ns, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 // each unit's copy of the recurrence tables
 hipError_t set_rec_tables_main();
 hipError_t set_rec_tables_valu_f32();

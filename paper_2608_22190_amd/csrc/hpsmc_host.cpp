@@ -394,6 +394,7 @@ struct hpsmc_plan {
     int32_t use_graph = 0;
     int32_t sample_mma = 1;     // FP32 round kernels on the matrix cores where eligible (2-D, 5-D)
     int32_t sample_split = 1;   // sparse rounds of the 5-D matrix-core kernel on all waves of a block
+    int32_t sample_1d = 1;      // d = 1 rounds on the windowed 1-D kernel where eligible
     // fractional operator (d = 1): tables of the round kernel (see Physics)
     bool frac = false;
     double *frac_tab = nullptr;
@@ -1105,6 +1106,13 @@ static bool one_sample_per_lane(const hpsmc_plan *plan)
     return plan->frac || plan->pb.estimator == HPSMC_EST_PICARD || plan->pb.quad == HPSMC_QUAD_BALL;
 }
 
+// Whether the rounds run the windowed 1-D kernel with ns paths per lane
+static bool uses_1d(const hpsmc_plan *plan, int ns)
+{
+    return plan->sample_1d && advance_1d_eligible(plan->d, plan->P, plan->pb.estimator == HPSMC_EST_PICARD,
+                                                  plan->pb.quad == HPSMC_QUAD_BALL, plan->frac ? 1 : 0, ns);
+}
+
 // Whether the rounds of this set run a matrix-core kernel with the current
 // launch shape (its slabs are then written in that kernel's layout): 1 the
 // 2-D kernel, 2 the 5-D kernel, 0 neither.
@@ -1164,7 +1172,9 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     if (mma != 2 && !pick_chunking(plan, nthr, &cf, &chunk_elems, &n_chunks))
         return fail(HPSMC_EINVAL, "slab chunk too large for this block size; use more waves per block");
     const int64_t nvec = chunk_elems * (plan->fp32 ? 4 : 8) / 16;
-    const size_t lds = mma == 2 ? advance_mma5_lds_bytes(plan->P)
+    const bool k1d = mma == 0 && uses_1d(plan, ns);
+    const size_t lds = k1d ? advance_1d_lds_bytes(plan->fp32, set.slab.slab_stride)
+                     : mma == 2 ? advance_mma5_lds_bytes(plan->P)
                      : mma ? advance_mma_lds_bytes(plan->PP)
                      : plan->frac ? frac_lds_bytes(plan->fp32, plan->PP, plan->frac_kmax, plan->P, plan->frac_K,
                                                    plan->frac_nt)
@@ -1218,7 +1228,7 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
                                       set.prefix, plan->counters, s));
             hpsmc_plan::EvPair *ea = next_pair(plan->ev_sample, plan->n_sample);
             if (ea) HIP_TRY(hipEventRecord(ea->a, s));
-            HIP_TRY(launch_advance(a, plan->fp32, ns, waves, blocks, lds, mma, s));
+            HIP_TRY(launch_advance(a, plan->fp32, ns, waves, blocks, lds, k1d ? 3 : mma, s));
             if (ea) HIP_TRY(hipEventRecord(ea->b, s));
         }
         HIP_TRY(launch_slice_reduce(set.result, set.n, mc, plan->part, first, s));
@@ -2195,9 +2205,9 @@ static std::string tune_key(const hpsmc_plan *plan, int iv, int64_t M)
     const bool ball = plan->pb.quad == HPSMC_QUAD_BALL;
     const bool mma = plan->sample_mma && mma_capable(plan);
     char buf[256];
-    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
-             plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", picard ? "_picard" : "", ball ? "_ball" : "",
-             (long long)M, plan->n_inst, arch.c_str());
+    snprintf(buf, sizeof(buf), "d%d_n%d_P%d_deg%d_%s%s%s%s%s_M%lld_I%d_%s", plan->d, plan->n, plan->P, plan->degree[iv],
+             plan->fp32 ? "fp32" : "fp64", mma ? "mma" : "", uses_1d(plan, 1) ? "_win" : "", picard ? "_picard" : "",
+             ball ? "_ball" : "", (long long)M, plan->n_inst, arch.c_str());
     return buf;
 }
 
@@ -2289,6 +2299,11 @@ hpsmc_status hpsmc_tune(hpsmc_plan *plan, int32_t iv, int64_t m_tune, const char
             // two-wave blocks of the matrix-core kernel: 1, 1.5, 2, 3, 4 waves per SIMD
             if (w == 2 && nsv[a] == 1 && plan->sample_mma && advance_mma_eligible(plan->fp32, plan->d, plan->P, 0, 1, 2)) {
                 for (int b : {2, 3, 4, 6, 8}) cands.push_back(hpsmc_launch{1, 2, b, plan->round_steps});
+                continue;
+            }
+            // the windowed 1-D kernel: few registers, so up to 16 blocks per CU
+            if (set.rounds && uses_1d(plan, nsv[a])) {
+                for (int b : {2, 4, 8, 16}) cands.push_back(hpsmc_launch{nsv[a], w, b, plan->round_steps});
                 continue;
             }
             // the LDS-staged slab chunk must fit 4 vectors per thread
@@ -2495,6 +2510,17 @@ hpsmc_status hpsmc_set_option(hpsmc_plan *plan, const char *name, int64_t value)
         plan->sample_split = (int32_t)value;
         return HPSMC_OK;
     }
+    if (strcmp(name, "sample_1d") == 0) {
+        if (value != 0 && value != 1) return fail(HPSMC_EINVAL, "sample_1d must be 0 or 1");
+        if (plan->sample_1d != (int32_t)value && plan->graph_exec) {   // the captured launches used the other kernel
+            (void)hipGraphExecDestroy(plan->graph_exec);
+            (void)hipGraphDestroy(plan->graph);
+            plan->graph_exec = nullptr;
+            plan->graph = nullptr;
+        }
+        plan->sample_1d = (int32_t)value;
+        return HPSMC_OK;
+    }
     return fail(HPSMC_EINVAL, std::string("unknown option ") + name);
 }
 
@@ -2512,6 +2538,13 @@ hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t 
     if (strcmp(name, "adjoint_mfma") == 0) { *value = plan->adj_use_mfma; return HPSMC_OK; }
     if (strcmp(name, "sample_mfma") == 0) { *value = plan->sample_mma; return HPSMC_OK; }
     if (strcmp(name, "sample_split") == 0) { *value = plan->sample_split; return HPSMC_OK; }
+    if (strcmp(name, "sample_1d") == 0) { *value = plan->sample_1d; return HPSMC_OK; }
+    if (strcmp(name, "sample_1d_active") == 0) {
+        const NodeSet &set = plan->sets[0];
+        *value = set.rounds && set_uses_mma(plan, set) == 0 &&
+                 uses_1d(plan, one_sample_per_lane(plan) ? 1 : plan->launch.samples_per_lane);
+        return HPSMC_OK;
+    }
     if (strcmp(name, "sample_mfma_active") == 0) {
         *value = 0;
         for (int iv = 0; iv < (plan->pb.schedule == HPSMC_SEQUENTIAL ? plan->n_iv : 1); ++iv)

@@ -167,8 +167,14 @@ hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t 
                              int64_t mcount, int32_t batch, int32_t batch_split, int64_t split_max,
                              const uint32_t *live_in, uint32_t *live_out, int64_t *batch_prefix,
                              unsigned long long *work, hipStream_t s);
+// kern: 0 the vector-unit kernel, 1 the 2-D matrix-core kernel, 2 the 5-D one,
+// 3 the windowed 1-D kernel
 hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
-                          size_t lds_bytes, int mma, hipStream_t s);
+                          size_t lds_bytes, int kern, hipStream_t s);
+// windowed 1-D round kernel: residual form, centre-point rule, P <= 36, 1, 2 or
+// 4 paths per lane; LDS: two windows of slabs
+bool advance_1d_eligible(int dim, int P, int picard, int ball, int frac, int samples_per_lane);
+size_t advance_1d_lds_bytes(int fp32, int64_t slab_stride);
 // matrix-core form of the round kernel: FP32, d = 2, P <= 32, whole slab per
 // LDS buffer, one path per lane
 bool advance_mma_eligible(int fp32, int dim, int P, int cf, int samples_per_lane, int waves_per_block);

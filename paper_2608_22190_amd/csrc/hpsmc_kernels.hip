@@ -682,10 +682,16 @@ hipError_t launch_round_prep(const GroupDesc *groups, int32_t n_groups, int32_t 
 }
 
 hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, int waves_per_block, int blocks,
-                          size_t lds_bytes, int mma, hipStream_t s)
+                          size_t lds_bytes, int kern, hipStream_t s)
 {
     dim3 block(64 * waves_per_block), grid(blocks);
     if (a.phys.frac) return launch_adv_frac(a, fp32, grid, block, lds_bytes, s);
+    const int mma = kern;
+    if (kern == 3) {
+        if (!advance_1d_eligible(a.phys.dim, a.P, a.phys.picard, a.phys.ball, a.phys.frac, samples_per_lane))
+            return hipErrorInvalidValue;
+        return launch_adv_1d(a, fp32, samples_per_lane, grid, block, lds_bytes, s);
+    }
     if (mma == 2) {
         if (!advance_mma5_eligible(fp32, a.phys.dim, a.P, a.phys.picard, a.phys.ball, samples_per_lane, waves_per_block))
             return hipErrorInvalidValue;
