@@ -21,6 +21,14 @@ SOURCES = ["hpsmc_kern_valu_f32.hip", "hpsmc_kern_valu_f64.hip", "hpsmc_kern_mma
            "hpsmc_kern_adjoint.hip", "hpsmc_kern_frac.hip", "hpsmc_kern_1d.hip", "hpsmc_kernels.hip",
            "hpsmc_host.cpp"]
 HEADERS = ["hpsmc_internal.h", "hpsmc_device.h", "hpsmc_round.h", "hpsmc_lobatto_eigs.h"]
+# per-unit extra flags: in the vector-unit round kernels machine LICM hoists
+# every loop-invariant constant of the walk (series coefficients, source and
+# nonlinearity parameters) into registers held across the step loop, which
+# costs occupancy (FP64, one path per lane: the windowed 1-D kernel 150 -> 77
+# VGPRs without it, the general 2-D kernel 225 -> 153)
+_NO_MLICM = ["-mllvm", "-disable-machine-licm"]
+UNIT_FLAGS = {"hpsmc_kern_1d.hip": _NO_MLICM, "hpsmc_kern_valu_f64.hip": _NO_MLICM,
+              "hpsmc_kern_valu_f32.hip": _NO_MLICM}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -40,7 +48,7 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
         if incremental and os.path.exists(obj) and all(os.path.getmtime(obj) > os.path.getmtime(d) for d in deps):
             continue
         lang = [] if src.endswith(".hip") else ["-x", "hip"]
-        jobs.append([HIPCC] + FLAGS + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        jobs.append([HIPCC] + FLAGS + UNIT_FLAGS.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
 
     def run(cmd):
         if verbose:

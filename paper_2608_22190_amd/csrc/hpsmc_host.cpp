@@ -1113,6 +1113,16 @@ static bool uses_1d(const hpsmc_plan *plan, int ns)
                                                   plan->pb.quad == HPSMC_QUAD_BALL, plan->frac ? 1 : 0, ns);
 }
 
+static int set_uses_mma(const hpsmc_plan *plan, const NodeSet &set);
+
+// Whether the rounds of this set run the windowed 1-D kernel with the current
+// launch shape (its slabs then hold Chebyshev coefficients)
+static bool set_uses_1d(const hpsmc_plan *plan, const NodeSet &set)
+{
+    return set.rounds && set_uses_mma(plan, set) == 0 &&
+           uses_1d(plan, one_sample_per_lane(plan) ? 1 : plan->launch.samples_per_lane);
+}
+
 // Whether the rounds of this set run a matrix-core kernel with the current
 // launch shape (its slabs are then written in that kernel's layout): 1 the
 // 2-D kernel, 2 the 5-D kernel, 0 neither.
@@ -1172,7 +1182,7 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
     if (mma != 2 && !pick_chunking(plan, nthr, &cf, &chunk_elems, &n_chunks))
         return fail(HPSMC_EINVAL, "slab chunk too large for this block size; use more waves per block");
     const int64_t nvec = chunk_elems * (plan->fp32 ? 4 : 8) / 16;
-    const bool k1d = mma == 0 && uses_1d(plan, ns);
+    const bool k1d = set_uses_1d(plan, set);
     const size_t lds = k1d ? advance_1d_lds_bytes(plan->fp32, set.slab.slab_stride)
                      : mma == 2 ? advance_mma5_lds_bytes(plan->P)
                      : mma ? advance_mma_lds_bytes(plan->PP)
@@ -1251,14 +1261,17 @@ static hpsmc_status sample_rounds(hpsmc_plan *plan, NodeSet &set, int tag, int r
 // Slab arguments for `layout`: the 2-D matrix-core image (layout 1) holds
 // Chebyshev coefficients in both spatial dimensions, so c^u and c^v of the
 // set's intervals are converted first (two mode products per table and
-// interval) and the slab kernel reads the converted tensors.
-static hpsmc_status slab_args_for(hpsmc_plan *plan, const NodeSet &set, int layout, SlabArgs &sa, hipStream_t s)
+// interval) and the slab kernel reads the converted tensors.  The rows of the
+// windowed 1-D kernel (cheb1d, row layout) hold Chebyshev coefficients too
+// (one mode product per table and interval).
+static hpsmc_status slab_args_for(hpsmc_plan *plan, const NodeSet &set, int layout, bool cheb1d, SlabArgs &sa,
+                                  hipStream_t s)
 {
     sa = set.slab;
     sa.slab_table = plan->slab_table;
     sa.layout = layout;
-    if (layout != 1) return HPSMC_OK;
-    if (!plan->cu_ch) return fail(HPSMC_EINVAL, "no Chebyshev coefficient buffers for the matrix-core layout");
+    if (layout != 1 && !cheb1d) return HPSMC_OK;
+    if (!plan->cu_ch) return fail(HPSMC_EINVAL, "no Chebyshev coefficient buffers for this slab layout");
     const int P = plan->P;
     const double *A = plan->mats + plan->cheb_off;
     const int64_t I = plan->n_inst;
@@ -1267,8 +1280,12 @@ static hpsmc_status slab_args_for(hpsmc_plan *plan, const NodeSet &set, int layo
         for (int t = 0; t < 2; ++t) {
             const double *in = (t ? plan->cv : plan->cu) + plan->c_off[iv];
             double *out = (t ? plan->cv_ch : plan->cu_ch) + plan->c_off[iv];
-            HIP_TRY(launch_mode_product(in, plan->tmp0, I, P, P, (int64_t)P * T1, A, 1.0, 0, s));
-            HIP_TRY(launch_mode_product(plan->tmp0, out, I * P, P, P, T1, A, 1.0, 0, s));
+            if (plan->d == 1) {
+                HIP_TRY(launch_mode_product(in, out, I, P, P, T1, A, 1.0, 0, s));
+            } else {
+                HIP_TRY(launch_mode_product(in, plan->tmp0, I, P, P, (int64_t)P * T1, A, 1.0, 0, s));
+                HIP_TRY(launch_mode_product(plan->tmp0, out, I * P, P, P, T1, A, 1.0, 0, s));
+            }
         }
     }
     sa.cu = plan->cu_ch;
@@ -1281,7 +1298,8 @@ static hpsmc_status sample_set(hpsmc_plan *plan, NodeSet &set, int tag, int reco
 {
     const int ns = plan->launch.samples_per_lane;
     SlabArgs sa;
-    if (hpsmc_status st = slab_args_for(plan, set, set_uses_mma(plan, set), sa, s)) return st;
+    if (hpsmc_status st = slab_args_for(plan, set, set_uses_mma(plan, set), set_uses_1d(plan, set), sa, s))
+        return st;
     hpsmc_plan::EvPair *es = next_pair(plan->ev_slab, plan->n_slab);
     if (es) HIP_TRY(hipEventRecord(es->a, s));
     HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
@@ -1550,7 +1568,8 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
         plan->ainv_off = (int64_t)mats.size();
         mats.insert(mats.end(), Ainv.begin(), Ainv.end());
     }
-    const bool cheb = plan->d == 2 && !plan->frac && mma_capable(pl);   // the 2-D matrix-core image's basis
+    // the basis of the 2-D matrix-core image and of the windowed 1-D kernel's rows
+    const bool cheb = !plan->frac && ((plan->d == 2 && mma_capable(pl)) || plan->d == 1);
     if (cheb) {
         auto Ach = legendre_to_chebyshev(plan->P);
         plan->cheb_off = (int64_t)mats.size();
@@ -1574,11 +1593,15 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
         const int P = plan->P;
         for (int iv = 0; iv < plan->n_iv; ++iv) {
             const int T1 = plan->degree[iv] + 1;
-            if (launch_mode_product(pl->src_poly + pl->src_off[iv], pl->tmp0, 1, P, P, (int64_t)P * T1, A, 1.0, 0,
-                                    nullptr) != hipSuccess ||
-                launch_mode_product(pl->tmp0, pl->cs_ch + pl->src_off[iv], P, P, P, T1, A, 1.0, 0, nullptr) !=
-                    hipSuccess)
-                return fail(HPSMC_EDEVICE, "source conversion failed");
+            const bool ok =
+                plan->d == 1
+                    ? launch_mode_product(pl->src_poly + pl->src_off[iv], pl->cs_ch + pl->src_off[iv], 1, P, P, T1, A,
+                                          1.0, 0, nullptr) == hipSuccess
+                    : launch_mode_product(pl->src_poly + pl->src_off[iv], pl->tmp0, 1, P, P, (int64_t)P * T1, A, 1.0,
+                                          0, nullptr) == hipSuccess &&
+                          launch_mode_product(pl->tmp0, pl->cs_ch + pl->src_off[iv], P, P, P, T1, A, 1.0, 0, nullptr) ==
+                              hipSuccess;
+            if (!ok) return fail(HPSMC_EDEVICE, "source conversion failed");
         }
     }
 
@@ -2539,12 +2562,7 @@ hpsmc_status hpsmc_get_option(const hpsmc_plan *plan, const char *name, int64_t 
     if (strcmp(name, "sample_mfma") == 0) { *value = plan->sample_mma; return HPSMC_OK; }
     if (strcmp(name, "sample_split") == 0) { *value = plan->sample_split; return HPSMC_OK; }
     if (strcmp(name, "sample_1d") == 0) { *value = plan->sample_1d; return HPSMC_OK; }
-    if (strcmp(name, "sample_1d_active") == 0) {
-        const NodeSet &set = plan->sets[0];
-        *value = set.rounds && set_uses_mma(plan, set) == 0 &&
-                 uses_1d(plan, one_sample_per_lane(plan) ? 1 : plan->launch.samples_per_lane);
-        return HPSMC_OK;
-    }
+    if (strcmp(name, "sample_1d_active") == 0) { *value = set_uses_1d(plan, plan->sets[0]); return HPSMC_OK; }
     if (strcmp(name, "sample_mfma_active") == 0) {
         *value = 0;
         for (int iv = 0; iv < (plan->pb.schedule == HPSMC_SEQUENTIAL ? plan->n_iv : 1); ++iv)
@@ -2677,7 +2695,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
         HIP_TRY(hipMemcpyAsync(plan->cu, plan->hist_u + (size_t)k * csz, csz * 8, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(plan->cv, plan->hist_v + (size_t)k * csz, csz * 8, hipMemcpyDeviceToDevice, s));
         SlabArgs sa;   // the slabs in the layout the adjoint reads
-        if ((st = slab_args_for(plan, set, adjoint_mfma_mode(plan, set) == 2 ? 1 : 0, sa, s))) return st;
+        if ((st = slab_args_for(plan, set, adjoint_mfma_mode(plan, set) == 2 ? 1 : 0, false, sa, s))) return st;
         HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
         HIP_TRY(launch_fill_u64((unsigned long long *)plan->slab_bar, (int64_t)(plan->slab_bytes / 8), 0ull, s));
         if ((st = adjoint_sampling(plan, set, plan->pb.fresh_per_iter ? k : 0, s))) return st;

@@ -13,12 +13,14 @@ namespace hpsmc {
 // dominate.  Here a block copies the slabs of a window of k1dWin steps into
 // LDS at once (straight from the table, double buffered: the next window
 // lands while the current one is walked), computes the window's source time
-// factors one per thread, and meets at a barrier once per window.  The
-// Legendre recurrence runs interleaved with the two dot products, so a path
-// keeps two basis values instead of P.  The walk (Philox words, +-J jumps,
-// the exit test of eq. indexL), the recurrence, the summation order of the
-// contractions and the residual (eq. interIQ) are those of the general
-// kernel, term for term.
+// factors one per thread, and meets at a barrier once per window.  The rows
+// hold the coefficients of u* and v* in the Chebyshev basis (converted from
+// the Legendre tensors by one mode product per table before the time
+// contraction), whose recurrence T_{k+1} = 2x T_k - T_{k-1} has constant
+// coefficients: one fma per basis value, run interleaved with the two dot
+// products, so a path keeps two basis values instead of P.  The walk (Philox
+// words, +-J jumps, the exit test of eq. indexL) and the residual (eq.
+// interIQ) are those of the general kernel.
 // ===========================================================================
 constexpr int k1dWin = 32;
 
@@ -141,11 +143,13 @@ __device__ __forceinline__ void advance_1d_body(const RoundArgs &a)
                 slots += NS;
                 if (__ballot(any_live) == 0ull) continue;
                 // ---- residual at X_q, time tau_q = t_{n,l} - q Delta: u*, v* by the
-                // Legendre recurrence, each value entering both sums as it is formed
+                // Chebyshev recurrence, each value entering both sums as it is formed
                 const T *S = Sw + (int64_t)(q - qw) * sstride;
-                T tu[NS], tv[NS], lp[NS], lc[NS];
+                T tu[NS], tv[NS], lp[NS], lc[NS], x2[NS];
 #pragma unroll
-                for (int s = 0; s < NS; ++s) { tu[s] = (T)0; tv[s] = (T)0; lp[s] = (T)1; lc[s] = X[s]; }
+                for (int s = 0; s < NS; ++s) {
+                    tu[s] = (T)0; tv[s] = (T)0; lp[s] = (T)1; lc[s] = X[s]; x2[s] = X[s] + X[s];
+                }
                 typedef T v4 __attribute__((ext_vector_type(4)));
 #pragma unroll
                 for (int kb = 0; kb < PM / 4; ++kb) {
@@ -157,13 +161,12 @@ __device__ __forceinline__ void advance_1d_body(const RoundArgs &a)
                             const int k = 4 * kb + c;   // mode of this term
 #pragma unroll
                             for (int s = 0; s < NS; ++s) {
-                                // L_k: 1, x, then (2k-1)/k x L_{k-1} - (k-1)/k L_{k-2}
+                                // T_k: 1, x, then 2x T_{k-1} - T_{k-2}
                                 T Lk;
                                 if (k == 0) Lk = (T)1;
                                 else if (k == 1) Lk = X[s];
                                 else {
-                                    const int m = k - 1;
-                                    Lk = (T)((2.0 * m + 1.0) / (m + 1.0)) * X[s] * lc[s] - (T)(m / (m + 1.0)) * lp[s];
+                                    Lk = m_fma(x2[s], lc[s], -lp[s]);
                                     lp[s] = lc[s];
                                     lc[s] = Lk;
                                 }
