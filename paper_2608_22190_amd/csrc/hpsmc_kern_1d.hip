@@ -1,7 +1,7 @@
 // One-dimensional round kernel (vector units, FP64 or FP32): the residual form
 // with the centre-point rule, the path-advancing step of eq. varepsilon_1 on a
-// line, where a step's slab is only the 2 P Legendre coefficients of u* and
-// v* at the step's time.
+// line, where a step's slab is only the 2 P coefficients of u* and v* at the
+// step's time.
 #include "hpsmc_device.h"
 
 namespace hpsmc {

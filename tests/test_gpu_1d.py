@@ -2,10 +2,10 @@
 
 On a line the windowed kernel replaces the general vector-unit kernel for the
 residual form with the centre-point rule: it copies the slabs of 32 walk steps
-into LDS per barrier and forms the Legendre values inside the two dot
-products.  Its walk, recurrence, summation order and residual are the general
-kernel's term for term, so the evaluation counts are identical and the path
-values agree to rounding (in practice bit for bit).  The cases cover FP64 and
+into LDS per barrier and forms the basis values inside the two dot products,
+in the Chebyshev basis (its rows converted from the Legendre tensors).  Its
+walk and residual are the general kernel's, so the evaluation counts are
+identical and the path values agree to rounding.  The cases cover FP64 and
 FP32, one, two and four paths per lane, one-, two- and four-wave blocks, every
 mode tier (P <= 12, 20, 36), rounds shorter than a window and windows cut by
 the round end, and paths that outlive several rounds.
