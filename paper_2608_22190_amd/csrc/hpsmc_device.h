@@ -54,6 +54,8 @@ __device__ __forceinline__ double m_sin(double x) { return sin(x); }
 __device__ __forceinline__ float m_sin(float x) { return sinf(x); }
 __device__ __forceinline__ double m_cos(double x) { return cos(x); }
 __device__ __forceinline__ float m_cos(float x) { return cosf(x); }
+__device__ __forceinline__ void m_sincos(double x, double &s, double &c) { sincos(x, &s, &c); }
+__device__ __forceinline__ void m_sincos(float x, float &s, float &c) { sincosf(x, &s, &c); }
 __device__ __forceinline__ double m_exp(double x) { return exp(x); }
 __device__ __forceinline__ float m_exp(float x) { return expf(x); }
 __device__ __forceinline__ double m_log(double x) { return log(x); }
@@ -242,10 +244,30 @@ __device__ __forceinline__ void sphere_dir(uint32_t c0, uint32_t c1, int q, uint
 // ---------------------------------------------------------------------------
 // Problem terms.
 // ---------------------------------------------------------------------------
-// sin(u) for the nonlinearity: FP32 arguments with |u| <= 2 take the sine's
-// Maclaurin series to u^17/17! (truncation below 4e-10 there, no range
-// reduction); larger ones and FP64 the library sine
-__device__ __forceinline__ double sin_of_u(double u) { return sin(u); }
+// sin(u) for the nonlinearity: arguments with |u| <= 2 take the sine's
+// Maclaurin series, no range reduction (FP32 to u^17/17!, truncation below
+// 4e-10; FP64 to u^27/27!, below 1e-20), larger ones the library sine
+__device__ __forceinline__ double sin_of_u(double u)
+{
+    if (fabs(u) <= 2.0) {
+        const double z = u * u;
+        double p = 1.0 / 10888869450418352160768000000.0;   // +1/27!
+        p = fma(p, z, -1.0 / 15511210043330985984000000.0);  // -1/25!
+        p = fma(p, z, 1.0 / 25852016738884976640000.0);      // +1/23!
+        p = fma(p, z, -1.0 / 51090942171709440000.0);        // -1/21!
+        p = fma(p, z, 1.0 / 121645100408832000.0);           // +1/19!
+        p = fma(p, z, -1.0 / 355687428096000.0);             // -1/17!
+        p = fma(p, z, 1.0 / 1307674368000.0);                // +1/15!
+        p = fma(p, z, -1.0 / 6227020800.0);                  // -1/13!
+        p = fma(p, z, 1.0 / 39916800.0);                     // +1/11!
+        p = fma(p, z, -1.0 / 362880.0);                      // -1/9!
+        p = fma(p, z, 1.0 / 5040.0);                         // +1/7!
+        p = fma(p, z, -1.0 / 120.0);                         // -1/5!
+        p = fma(p, z, 1.0 / 6.0);                            // +1/3!
+        return fma(-p * z, u, u);
+    }
+    return sin(u);
+}
 __device__ __forceinline__ float sin_of_u(float u)
 {
     if (fabsf(u) <= 2.f) {
@@ -263,16 +285,22 @@ __device__ __forceinline__ float sin_of_u(float u)
     return sinf(u);
 }
 
+// The two sine kinds share one call: with a call in each case the compiler
+// hoists the sine's common range reduction above the switch, and every kind
+// pays for it at every walk step.
 template <typename T>
 __device__ __forceinline__ T f_of(const Physics &ph, T u)
 {
     switch (ph.f_kind) {
     case 0: return (T)ph.f_param[0] * u + (T)ph.f_param[1];
     case 1: return u - u * u * u;
-    case 2: return sin_of_u(u);
+    case 2:
+    case 5: {
+        const T sn = sin_of_u(u);
+        return ph.f_kind == 2 ? sn : u * sn;
+    }
     case 3: return u * u / ((T)1 + u * u);
     case 4: return -u * u * u;
-    case 5: return u * sin_of_u(u);
     }
     return (T)0;
 }
@@ -283,10 +311,14 @@ __device__ __forceinline__ T fprime_of(const Physics &ph, T u)
     switch (ph.f_kind) {
     case 0: return (T)ph.f_param[0];
     case 1: return (T)1 - (T)3 * u * u;
-    case 2: return m_cos(u);
+    case 2:
+    case 5: {   // one sine-cosine call for both kinds (as in f_of)
+        T sn, cs;
+        m_sincos(u, sn, cs);
+        return ph.f_kind == 2 ? cs : sn + u * cs;
+    }
     case 3: { T a = (T)1 + u * u; return (T)2 * u / (a * a); }
     case 4: return (T)-3 * u * u;
-    case 5: return m_sin(u) + u * m_cos(u);
     }
     return (T)0;
 }
@@ -318,8 +350,6 @@ __device__ __forceinline__ SrcTime<T> source_time(const Physics &ph, T t)
     return {(T)0, (T)0};
 }
 
-__device__ __forceinline__ void m_sincos(double x, double &s, double &c) { sincos(x, &s, &c); }
-__device__ __forceinline__ void m_sincos(float x, float &s, float &c) { sincosf(x, &s, &c); }
 
 // sin and cos of |x| <= 2 by their Maclaurin series in Horner form (terms to
 // x^17/17! and x^18/18!; the truncation error is below 4e-10 there): no range
