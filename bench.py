@@ -350,8 +350,8 @@ def run_other(name, args, torch):
         achieved = fadj * st["path_steps"] / max(1e-9, adj_ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                           "kernel": (f"adjoint_mma2_kernel<{(P + 1) // 2}> (u* and the outer products on "
-                                      f"v_mfma_f32_32x32x2f32)" if P <= 20 else
+                           "kernel": (f"adjoint_mma2_kernel<{(P + 1) // 2}> (u* on v_mfma_f32_32x32x2f32, the "
+                                      f"outer products on v_mfma_f32_16x16x4f32)" if P <= 20 else
                                       "adjoint_kernel<float,2,PMAX,true> (outer products on v_mfma_f32_32x32x2f32)"),
                            "flops_per_eval": fadj,
                            "evals_per_launch": st["path_steps"] / max(1, st["adjoint_launches"]),

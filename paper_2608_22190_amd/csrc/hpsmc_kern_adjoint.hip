@@ -324,9 +324,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFMA ?
 // layout (coalesced 128-byte rows, L2-resident: every block of a group reads
 // the same image), and run its products and epilogue in the same order
 // -- so u*(X_q), and with it f'(u*), is bit for bit the forward kernel's.  No
-// slab passes through LDS; the weighted outer products are the form above.
+// slab passes through LDS.  The weighted outer products stack the u and v
+// factors as one set of rows in 16 x 16 tiles (P = 18: six tiles of 256 sums
+// where two 32 x 32 tiles hold 1024 each), with the samples as the reduction
+// dimension as above.
 // Templated on KH = ceil(P/2): every per-sample loop has a fixed trip count.
 // ===========================================================================
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 size_t adjoint_mma2_lds_bytes(int P, int nthr)
 {
     const int K2 = 2 * ((P + 1) / 2);
@@ -337,6 +341,10 @@ template <int KH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) adjoint_mma2_kernel(AdjointArgs aa)
 {
     constexpr int K2 = 2 * KH;
+    constexpr int MT = (2 * K2 + 15) / 16;   // 16-row tiles of the stacked factors (2P <= 2 K2 rows)
+    constexpr int NT = (K2 + 15) / 16;       // 16-column tiles of L(X_1)
+    constexpr int TP = MT * NT, TW = (TP + 1) / 2;   // tile pairs; at most TW per wave
+    static_assert(NT <= 2 && TW <= 4, "the upper half's tiles fit the LDS sum buffer");
     const RoundArgs &a = aa.r;
     extern __shared__ u32x4 lds[];
     const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wave = tid >> 6;
@@ -461,53 +469,85 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) a
                 x1 = y1;
             }
             __syncthreads();
-            // ---- block sum of the outer products into the slab adjoint of step q
-            // (the matrix-core form of the kernel above: wave w forms tile w & 1 over
-            // half w >> 1 of the samples; rows and columns >= P are not written out)
+            // ---- block sum of the outer products into the slab adjoint of step q.
+            // The two weighted factors are stacked as rows R < 2P (R < P: wu L_R(X_0),
+            // else wv L_{R-P}(X_0)) against the columns L_j(X_1), in 16 x 16 tiles on
+            // v_mfma_f32_16x16x4f32 with four samples per product (A: lane l holds
+            // A[l % 16][l / 16], B: B[l / 16][l % 16], D register r: D[4 (l / 16) + r][l % 16]).
+            // Tile pairs t = mt NT + nt alternate between the waves w & 1, the waves
+            // w >> 1 take half of the samples each, and the upper half's tiles are added
+            // in LDS.  Rows R >= 2P and columns >= P hold finite values never written out.
             float *dstq = gbar + (int64_t)q * aa.bar_stride;
-            const int tile = wave & 1, half = wave >> 1, i = lane & 31;
-            constexpr int hs = 128;
-            const int ri = i < K2 ? i : K2 - 1;
-            const int base = half * hs + (lane >> 5) * (hs / 2);
-            const float4 *ap = (const float4 *)(Am + ri * NST + base);
-            const float4 *bp = (const float4 *)(Bm + ri * NST + base);
-            const float4 *wp = (const float4 *)(Wm + tile * nthr + base);
-            f32x16 c = {};
-            // operands one group ahead of the products; the fence keeps the
-            // scheduler from hoisting every group's reads (register spills)
-            float4 a4 = ap[0], b4 = bp[0], w4 = wp[0];
+            const int ts = wave & 1, half = wave >> 1, li = lane & 15, ks = lane >> 4;
+            const int base = half * 128 + ks * 32;   // this lane's samples: base + m, m < 32
+            const float4 *bp = (const float4 *)(Bm + min(16 * (ts % NT) + li, K2 - 1) * NST + base);
+            const float4 *ap[TW], *wp[TW];
 #pragma unroll
-            for (int m = 0; m < hs / 8; ++m) {
-                float4 a4n = a4, b4n = b4, w4n = w4;
-                if (m + 1 < hs / 8) {
-                    a4n = ap[m + 1];
-                    b4n = bp[m + 1];
-                    w4n = wp[m + 1];
-                }
-                c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.x * a4.x, b4.x, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.y * a4.y, b4.y, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.z * a4.z, b4.z, c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_32x32x2f32(w4.w * a4.w, b4.w, c, 0, 0, 0);
-                __builtin_amdgcn_sched_barrier(0);
-                a4 = a4n;
-                b4 = b4n;
-                w4 = w4n;
+            for (int j = 0; j < TW; ++j) {
+                const int R = 16 * ((2 * j + ts) / NT) + li;
+                const int tab = R < P ? 0 : 1;
+                ap[j] = (const float4 *)(Am + min(R - tab * P, K2 - 1) * NST + base);
+                wp[j] = (const float4 *)(Wm + tab * nthr + base);
             }
-            float *cm = gsum + tile * 16 * 64 + lane;
+            f32x4 c[TW];
+            float4 b4 = bp[0], a4[TW], w4[TW];
+#pragma unroll
+            for (int j = 0; j < TW; ++j) {
+                c[j] = f32x4{};
+                a4[j] = ap[j][0];
+                w4[j] = wp[j][0];
+            }
+            // operands one group of four samples ahead of the products; the fence
+            // keeps the scheduler from hoisting every group's reads
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                float4 b4n = b4, a4n[TW], w4n[TW];
+#pragma unroll
+                for (int j = 0; j < TW; ++j) { a4n[j] = a4[j]; w4n[j] = w4[j]; }
+                if (m + 1 < 8) {
+                    b4n = bp[m + 1];
+#pragma unroll
+                    for (int j = 0; j < TW; ++j) { a4n[j] = ap[j][m + 1]; w4n[j] = wp[j][m + 1]; }
+                }
+#pragma unroll
+                for (int j = 0; j < TW; ++j) {
+                    if (2 * j + ts < TP) {
+                        c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j].x * a4[j].x, b4.x, c[j], 0, 0, 0);
+                        c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j].y * a4[j].y, b4.y, c[j], 0, 0, 0);
+                        c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j].z * a4[j].z, b4.z, c[j], 0, 0, 0);
+                        c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j].w * a4[j].w, b4.w, c[j], 0, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                b4 = b4n;
+#pragma unroll
+                for (int j = 0; j < TW; ++j) { a4[j] = a4n[j]; w4[j] = w4n[j]; }
+            }
+            float *cm = gsum + ts * 16 * 64 + lane;
             if (half == 1) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) cm[r * 64] = c[r];
+                for (int j = 0; j < TW; ++j)
+                    if (2 * j + ts < TP) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) cm[(4 * j + r) * 64] = c[j][r];
+                    }
             }
             const int any_alive = __syncthreads_or(alive ? 1 : 0);
             if (half == 0) {
-                // row ii = 8 (r / 4) + 4 (lane / 32) + r % 4 of tile `tile`, column i:
-                // a lane offset plus a uniform row offset from the step's uniform base
-                const int ii0 = 4 * (lane >> 5), loff = ii0 * 2 * PP + tile * PP + i;
+                const int col = 16 * (ts % NT) + li;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int rr = 8 * (r >> 2) + (r & 3);
-                    const float val = c[r] + cm[r * 64];
-                    if (ii0 + rr < P && i < P && val != 0.f) atomicAdd(dstq + (loff + rr * 2 * PP), val);
+                for (int j = 0; j < TW; ++j) {
+                    if (2 * j + ts >= TP || col >= P) continue;
+                    const int R0 = 16 * ((2 * j + ts) / NT) + 4 * ks;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int R = R0 + r;
+                        const float val = c[j][r] + cm[(4 * j + r) * 64];
+                        if (R < 2 * P && val != 0.f) {
+                            const int tab = R < P ? 0 : 1;
+                            atomicAdd(dstq + ((R - tab * P) * 2 * PP + tab * PP + col), val);
+                        }
+                    }
                 }
             }
             if (any_alive == 0) break;

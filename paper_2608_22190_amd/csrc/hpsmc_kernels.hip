@@ -303,16 +303,17 @@ hipError_t launch_mode_product(const double *in, double *out, int64_t outer, int
 // Slabs: for group g = (inst, iv, l) and step q < N*, the spatial coefficient
 // rows of u* and v* at the reference time xi = 2 (span - q Delta)/h - 1.
 // A block takes kSlabQ consecutive steps of one group: the Legendre values
-// L_k(xi_q) of its steps go to LDS once, and every entry's T1 time
-// coefficients are loaded once into registers and contracted with each step's
-// values (the same products in the same order as entry by entry).
+// L_k(xi_q) of its steps go to LDS once (one row per degree k, the steps
+// contiguous), and every entry runs over its T1 time coefficients once,
+// each feeding the kSlabQ independent step sums -- the same products in the
+// same order as entry by entry, with no per-degree branch in the loop.
 // ---------------------------------------------------------------------------
 constexpr int kSlabQ = 32;
 
 template <typename T>
 __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
 {
-    __shared__ double Lq[kSlabQ][kMaxDeg + 2];
+    __shared__ __align__(16) double Lt[kMaxDeg + 1][kSlabQ];
     const int g = blockIdx.y;
     const int nq = a.nstar[g] + a.extra;
     const int T1 = a.deg[g] + 1;
@@ -326,12 +327,13 @@ __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
     const double span = a.span[g], delta = a.delta[g], h2 = a.h2[g];
     for (int q0 = blockIdx.x * kSlabQ; q0 < nq; q0 += gridDim.x * kSlabQ) {
         const int qn = min(kSlabQ, nq - q0);
-        __syncthreads();   // the previous chunk's reads of Lq are over
-        if ((int)threadIdx.x < qn) {
-            const double xi = h2 * (span - (double)(q0 + (int)threadIdx.x) * delta) - 1.0;
+        __syncthreads();   // the previous chunk's reads of Lt are over
+        if ((int)threadIdx.x < kSlabQ) {   // steps past the chunk's end get zeros (never stored)
+            const int j = threadIdx.x;
+            const double xi = h2 * (span - (double)(q0 + j) * delta) - 1.0;
             double lp = 0.0, lc = 1.0;
             for (int k = 0; k < T1; ++k) {
-                Lq[threadIdx.x][k] = lc;
+                Lt[k][j] = j < qn ? lc : 0.0;
                 const double nx = c_rec.ad[k] * xi * lc - c_rec.bd[k] * lp;
                 lp = lc;
                 lc = nx;
@@ -358,27 +360,27 @@ __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
                 }
                 live = kl < a.P && row < a.rows;
             }
-            double c[kMaxDeg + 1];
+            double acc[kSlabQ];
+#pragma unroll
+            for (int j = 0; j < kSlabQ; ++j) acc[j] = 0.0;
             if (live) {
                 const double *cp = (uv ? cv : cu) + (row * a.P + kl) * T1;
+                const double *sp = uv && cs ? cs + (row * a.P + kl) * T1 : nullptr;
+                for (int k = 0; k < T1; ++k) {
+                    const double ck = sp ? cp[k] + sp[k] : cp[k];
+                    const double2 *lk = (const double2 *)Lt[k];
 #pragma unroll
-                for (int k = 0; k <= kMaxDeg; ++k) c[k] = k < T1 ? cp[k] : 0.0;
-                if (uv && cs) {
-                    const double *sp = cs + (row * a.P + kl) * T1;
-#pragma unroll
-                    for (int k = 0; k <= kMaxDeg; ++k)
-                        if (k < T1) c[k] += sp[k];
+                    for (int j = 0; j < kSlabQ / 2; ++j) {
+                        const double2 l2 = lk[j];
+                        acc[2 * j] = fma(ck, l2.x, acc[2 * j]);
+                        acc[2 * j + 1] = fma(ck, l2.y, acc[2 * j + 1]);
+                    }
                 }
             }
-            for (int j = 0; j < qn; ++j) {
-                double val = 0.0;
-                if (live) {
+            T *dst = table + base + (int64_t)q0 * stride + e;
 #pragma unroll
-                    for (int k = 0; k <= kMaxDeg; ++k)
-                        if (k < T1) val = fma(c[k], Lq[j][k], val);
-                }
-                table[base + (int64_t)(q0 + j) * stride + e] = (T)val;
-            }
+            for (int j = 0; j < kSlabQ; ++j)
+                if (j < qn) dst[(int64_t)j * stride] = (T)acc[j];
         }
     }
 }
@@ -732,17 +734,17 @@ hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mc
 // node times l and steps q of Sbar_{g,q}[k] L_m(xi_{l,q}).  A block takes one
 // instance and 256 consecutive entries e of the row layout ([row][u: PP][v:
 // PP]) and streams their columns over every step of every group of the
-// instance: one coalesced 1 KiB row per step, eight steps' loads in flight per
-// thread, the Legendre values of kSlabQ steps at a time in LDS (computed once
-// per block).  Each entry's sums run over (l, q) in order, with the
-// recurrence of the slab kernel.
-template <typename T>
-__global__ void __launch_bounds__(256) slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t n_inst,
-                                                           double *__restrict__ cbar_u, double *__restrict__ cbar_v,
-                                                           int64_t coef_inst_stride)
+// instance: one coalesced 1 KiB row per step, a chunk of kSlabQ steps' loads
+// in flight per thread, the Legendre values of those steps in LDS (computed
+// once per block).  Each entry's sums run over (l, q) in order, with the
+// recurrence of the slab kernel.  The degree loop has a fixed trip count T1P
+// (T1 rounded up to a multiple of 4): the degrees past T1 sum finite values
+// that are never stored, and steps past a chunk's end read zeros.
+template <typename T, int T1P>
+__device__ __forceinline__ void slab_adjoint_body(const SlabArgs &a, int32_t groups_per_inst, double *cbar_u,
+                                                  double *cbar_v, int64_t coef_inst_stride,
+                                                  double (*Lq)[kMaxDeg + 2])
 {
-    __shared__ double Lq[kSlabQ][kMaxDeg + 2];
-    constexpr int QB = 8;   // loads in flight per thread
     const int inst = blockIdx.y;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t row = e / (2 * a.PP);
@@ -750,9 +752,9 @@ __global__ void __launch_bounds__(256) slab_adjoint_kernel(SlabArgs a, int32_t g
     const bool live = e < a.slab_stride && kl < a.P;
     const T *tab = (const T *)a.slab_table;
     const int T1 = a.deg[inst * groups_per_inst] + 1;
-    double acc[kMaxDeg + 1];
+    double acc[T1P];
 #pragma unroll
-    for (int m = 0; m <= kMaxDeg; ++m) acc[m] = 0.0;
+    for (int m = 0; m < T1P; ++m) acc[m] = 0.0;
     for (int gl = 0; gl < groups_per_inst; ++gl) {
         const int g = inst * groups_per_inst + gl;
         const int nstar = a.nstar[g];
@@ -761,11 +763,13 @@ __global__ void __launch_bounds__(256) slab_adjoint_kernel(SlabArgs a, int32_t g
         for (int q0 = 0; q0 < nstar; q0 += kSlabQ) {
             const int qn = min(kSlabQ, nstar - q0);
             __syncthreads();   // the previous chunk's reads of Lq are over
-            if ((int)threadIdx.x < qn) {
-                const double xi = h2 * (span - (double)(q0 + (int)threadIdx.x) * delta) - 1.0;
+            if ((int)threadIdx.x < kSlabQ) {
+                const int j = threadIdx.x;
+                const double xi = h2 * (span - (double)(q0 + j) * delta) - 1.0;
                 double lp = 0.0, lc = 1.0;
-                for (int m = 0; m < T1; ++m) {
-                    Lq[threadIdx.x][m] = lc;
+#pragma unroll
+                for (int m = 0; m < T1P; ++m) {
+                    Lq[j][m] = j < qn ? lc : 0.0;
                     const double nx = c_rec.ad[m] * xi * lc - c_rec.bd[m] * lp;
                     lp = lc;
                     lc = nx;
@@ -773,27 +777,42 @@ __global__ void __launch_bounds__(256) slab_adjoint_kernel(SlabArgs a, int32_t g
             }
             __syncthreads();
             if (!live) continue;
-            for (int j0 = 0; j0 < qn; j0 += QB) {
-                double v[QB];
+            T v[kSlabQ];
 #pragma unroll
-                for (int j = 0; j < QB; ++j)
-                    v[j] = j0 + j < qn ? (double)src[(int64_t)(q0 + j0 + j) * a.slab_stride] : 0.0;
+            for (int j = 0; j < kSlabQ; ++j) v[j] = j < qn ? src[(int64_t)(q0 + j) * a.slab_stride] : (T)0;
 #pragma unroll
-                for (int j = 0; j < QB; ++j) {
-                    if (v[j] == 0.0) continue;
-                    // fully unrolled with a guard so that acc stays in registers
+            for (int j = 0; j < kSlabQ; ++j) {
+                const double vj = (double)v[j];
 #pragma unroll
-                    for (int m = 0; m <= kMaxDeg; ++m)
-                        if (m < T1) acc[m] = fma(v[j], Lq[j0 + j][m], acc[m]);
-                }
+                for (int m = 0; m < T1P; ++m) acc[m] = fma(vj, Lq[j][m], acc[m]);
             }
         }
     }
     if (!live) return;
     double *out = (uv ? cbar_v : cbar_u) + (int64_t)inst * coef_inst_stride + (row * a.P + kl) * T1;
 #pragma unroll
-    for (int m = 0; m <= kMaxDeg; ++m)
+    for (int m = 0; m < T1P; ++m)
         if (m < T1) out[m] = acc[m];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t n_inst,
+                                                           double *__restrict__ cbar_u, double *__restrict__ cbar_v,
+                                                           int64_t coef_inst_stride)
+{
+    __shared__ double Lq[kSlabQ][kMaxDeg + 2];
+    (void)n_inst;
+    switch ((a.deg[blockIdx.y * groups_per_inst] + 4) >> 2) {   // ceil(T1 / 4), T1 <= kMaxDeg + 1 = 32
+    case 1: slab_adjoint_body<T, 4>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    case 2: slab_adjoint_body<T, 8>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    case 3: slab_adjoint_body<T, 12>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    case 4: slab_adjoint_body<T, 16>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    case 5: slab_adjoint_body<T, 20>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    case 6: slab_adjoint_body<T, 24>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    case 7: slab_adjoint_body<T, 28>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    default: slab_adjoint_body<T, 32>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    }
 }
 
 hipError_t launch_slab_adjoint(const SlabArgs &a, int32_t groups_per_inst, int32_t n_inst, int fp32, double *cbar_u,
