@@ -735,16 +735,18 @@ hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mc
 // instance and 256 consecutive entries e of the row layout ([row][u: PP][v:
 // PP]) and streams their columns over every step of every group of the
 // instance: one coalesced 1 KiB row per step, a chunk of kSlabQ steps' loads
-// in flight per thread, the Legendre values of those steps in LDS (computed
-// once per block).  Each entry's sums run over (l, q) in order, with the
+// in flight per thread (a half or a quarter of it past degree 15), the Legendre values of
+// those steps in LDS (computed once per block, one row per degree with the
+// steps contiguous).  Each entry's sums run over (l, q) in order, with the
 // recurrence of the slab kernel.  The degree loop has a fixed trip count T1P
 // (T1 rounded up to a multiple of 4): the degrees past T1 sum finite values
-// that are never stored, and steps past a chunk's end read zeros.
+// that are never stored, and steps past a chunk's end meet zero Legendre rows.
 template <typename T, int T1P>
 __device__ __forceinline__ void slab_adjoint_body(const SlabArgs &a, int32_t groups_per_inst, double *cbar_u,
                                                   double *cbar_v, int64_t coef_inst_stride,
-                                                  double (*Lq)[kMaxDeg + 2])
+                                                  double (*Lt)[kSlabQ])
 {
+    constexpr int QB = T1P <= 16 ? kSlabQ : T1P <= 20 ? kSlabQ / 2 : kSlabQ / 4;   // loads in flight per thread
     const int inst = blockIdx.y;
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t row = e / (2 * a.PP);
@@ -762,14 +764,14 @@ __device__ __forceinline__ void slab_adjoint_body(const SlabArgs &a, int32_t gro
         const T *src = tab + a.slab_off[g] + (live ? e : 0);
         for (int q0 = 0; q0 < nstar; q0 += kSlabQ) {
             const int qn = min(kSlabQ, nstar - q0);
-            __syncthreads();   // the previous chunk's reads of Lq are over
+            __syncthreads();   // the previous chunk's reads of Lt are over
             if ((int)threadIdx.x < kSlabQ) {
                 const int j = threadIdx.x;
                 const double xi = h2 * (span - (double)(q0 + j) * delta) - 1.0;
                 double lp = 0.0, lc = 1.0;
-#pragma unroll
-                for (int m = 0; m < T1P; ++m) {
-                    Lq[j][m] = j < qn ? lc : 0.0;
+#pragma unroll 1
+                for (int m = 0; m < T1P; ++m) {   // rolled: the recurrence constants stay out of registers
+                    Lt[m][j] = j < qn ? lc : 0.0;
                     const double nx = c_rec.ad[m] * xi * lc - c_rec.bd[m] * lp;
                     lp = lc;
                     lc = nx;
@@ -777,14 +779,23 @@ __device__ __forceinline__ void slab_adjoint_body(const SlabArgs &a, int32_t gro
             }
             __syncthreads();
             if (!live) continue;
-            T v[kSlabQ];
 #pragma unroll
-            for (int j = 0; j < kSlabQ; ++j) v[j] = j < qn ? src[(int64_t)(q0 + j) * a.slab_stride] : (T)0;
+            for (int j0 = 0; j0 < kSlabQ; j0 += QB) {
+                double v[QB];
 #pragma unroll
-            for (int j = 0; j < kSlabQ; ++j) {
-                const double vj = (double)v[j];
+                for (int j = 0; j < QB; ++j)   // past the chunk's end: a finite entry against zero rows of Lt
+                    v[j] = (double)src[(int64_t)(q0 + min(j0 + j, qn - 1)) * a.slab_stride];
 #pragma unroll
-                for (int m = 0; m < T1P; ++m) acc[m] = fma(vj, Lq[j][m], acc[m]);
+                for (int m = 0; m < T1P; ++m) {
+                    const double2 *lm = (const double2 *)(Lt[m] + j0);
+#pragma unroll
+                    for (int jj = 0; jj < QB / 2; ++jj) {
+                        const double2 l2 = lm[jj];
+                        acc[m] = fma(v[2 * jj], l2.x, acc[m]);
+                        acc[m] = fma(v[2 * jj + 1], l2.y, acc[m]);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);   // the next batch's loads after this batch's sums
             }
         }
     }
@@ -801,17 +812,17 @@ slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t n_inst,
                                                            double *__restrict__ cbar_u, double *__restrict__ cbar_v,
                                                            int64_t coef_inst_stride)
 {
-    __shared__ double Lq[kSlabQ][kMaxDeg + 2];
+    __shared__ __align__(16) double Lt[kMaxDeg + 1][kSlabQ];
     (void)n_inst;
     switch ((a.deg[blockIdx.y * groups_per_inst] + 4) >> 2) {   // ceil(T1 / 4), T1 <= kMaxDeg + 1 = 32
-    case 1: slab_adjoint_body<T, 4>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
-    case 2: slab_adjoint_body<T, 8>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
-    case 3: slab_adjoint_body<T, 12>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
-    case 4: slab_adjoint_body<T, 16>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
-    case 5: slab_adjoint_body<T, 20>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
-    case 6: slab_adjoint_body<T, 24>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
-    case 7: slab_adjoint_body<T, 28>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
-    default: slab_adjoint_body<T, 32>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lq); break;
+    case 1: slab_adjoint_body<T, 4>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
+    case 2: slab_adjoint_body<T, 8>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
+    case 3: slab_adjoint_body<T, 12>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
+    case 4: slab_adjoint_body<T, 16>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
+    case 5: slab_adjoint_body<T, 20>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
+    case 6: slab_adjoint_body<T, 24>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
+    case 7: slab_adjoint_body<T, 28>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
+    default: slab_adjoint_body<T, 32>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
     }
 }
 
