@@ -509,14 +509,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) a
 #pragma unroll
                     for (int j = 0; j < TW; ++j) { a4n[j] = ap[j][m + 1]; w4n[j] = wp[j][m + 1]; }
                 }
+                // the weighted operands first, then the products round-robin over the
+                // tile pairs: no product waits on the one just issued
+                float wa[TW][4];
 #pragma unroll
                 for (int j = 0; j < TW; ++j) {
-                    if (2 * j + ts < TP) {
-                        c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j].x * a4[j].x, b4.x, c[j], 0, 0, 0);
-                        c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j].y * a4[j].y, b4.y, c[j], 0, 0, 0);
-                        c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j].z * a4[j].z, b4.z, c[j], 0, 0, 0);
-                        c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4[j].w * a4[j].w, b4.w, c[j], 0, 0, 0);
-                    }
+                    wa[j][0] = w4[j].x * a4[j].x;
+                    wa[j][1] = w4[j].y * a4[j].y;
+                    wa[j][2] = w4[j].z * a4[j].z;
+                    wa[j][3] = w4[j].w * a4[j].w;
+                }
+                const float bb[4] = {b4.x, b4.y, b4.z, b4.w};
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) {
+#pragma unroll
+                    for (int j = 0; j < TW; ++j)
+                        if (2 * j + ts < TP) c[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[j][k4], bb[k4], c[j], 0, 0, 0);
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 b4 = b4n;
