@@ -325,6 +325,7 @@ struct NodeSet {               // the nodes one sampling launch covers
     // slab groups
     int32_t n_groups = 0, max_nstar = 0;
     int64_t slab_elems = 0;
+    int64_t slab_elems_row = 0;   // the row layout's extent (the slab adjoint's table)
     void *group_mem = nullptr; // coef_off, slab_off, span, delta, h2, nstar, deg
     SlabArgs slab{};
     // outputs (canonical order)
@@ -732,6 +733,7 @@ static hpsmc_status build_set(hpsmc_plan *plan, NodeSet &set, const std::vector<
     set.n_groups = (int32_t)coef_off.size();
     set.max_nstar = *std::max_element(nst.begin(), nst.end());
     set.slab_elems = std::max(slab_pos, slab_pos_mma);   // one layout is live at a time
+    set.slab_elems_row = slab_pos;
     hpsmc_status st;
     if ((st = dalloc(plan, (void **)&set.dev, sizeof(NodeDesc) * set.n))) return st;
     const size_t G = set.n_groups;
@@ -2697,7 +2699,9 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
         SlabArgs sa;   // the slabs in the layout the adjoint reads
         if ((st = slab_args_for(plan, set, adjoint_mfma_mode(plan, set) == 2 ? 1 : 0, false, sa, s))) return st;
         HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
-        HIP_TRY(launch_fill_u64((unsigned long long *)plan->slab_bar, (int64_t)(plan->slab_bytes / 8), 0ull, s));
+        // the adjoint accumulates into the row layout's extent of the table
+        const int64_t bar_bytes = set.slab_elems_row * (plan->fp32 ? 4 : 8);
+        HIP_TRY(launch_fill_u64((unsigned long long *)plan->slab_bar, (bar_bytes + 7) / 8, 0ull, s));
         if ((st = adjoint_sampling(plan, set, plan->pb.fresh_per_iter ? k : 0, s))) return st;
         SlabArgs sb = set.slab;
         sb.slab_table = plan->slab_bar;

@@ -18,6 +18,14 @@
 
 namespace hpsmc {
 
+// Element-wise kernels stride over their range from a grid of at most kGridCap
+// blocks: a dispatch counts its work-items in 32 bits, so a grid of one
+// thread per element wraps past 2^32 elements (a c5 slab-adjoint table holds
+// 10.7 G 8-byte words).
+constexpr int64_t kGridCap = 1 << 20;
+static inline unsigned grid_blocks(int64_t n, int block) { return (unsigned)std::min<int64_t>((n + block - 1) / block, kGridCap); }
+
+
 hipError_t set_rec_tables_main() { return upload_recurrence_tables(); }
 
 hipError_t set_recurrence_tables()
@@ -532,35 +540,35 @@ hipError_t launch_aitken(const NodeDesc *nodes, const int64_t *vbeg, int n_vec, 
 __global__ void start_columns_kernel(double *__restrict__ U, const double *__restrict__ src, int64_t src_stride,
                                      int64_t src_off, int64_t dst_stride, int T1, int64_t count, int replicate)
 {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= count) return;
-    const double v = src[r * src_stride + src_off];
-    double *d = U + r * dst_stride;
-    if (replicate)
-        for (int l = 0; l < T1; ++l) d[l] = v;
-    else
-        d[0] = v;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < count; r += (int64_t)gridDim.x * blockDim.x) {
+        const double v = src[r * src_stride + src_off];
+        double *d = U + r * dst_stride;
+        if (replicate)
+            for (int l = 0; l < T1; ++l) d[l] = v;
+        else
+            d[0] = v;
+    }
 }
 
 hipError_t launch_start_columns(double *U, const double *src, int64_t src_stride, int64_t src_off, int64_t dst_stride,
                                 int T1, int64_t count, int replicate, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(start_columns_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, U, src,
+    hipLaunchKernelGGL(start_columns_kernel, dim3(grid_blocks(count, 256)), dim3(256), 0, s, U, src,
                        src_stride, src_off, dst_stride, T1, count, replicate);
     return hipGetLastError();
 }
 
 __global__ void fill_u64_kernel(unsigned long long *p, int64_t n, unsigned long long v)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_blocks(n, 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 
@@ -603,10 +611,14 @@ __global__ void eval_kernel(const double *__restrict__ cu, const double *__restr
 hipError_t launch_eval(const double *cu, const double *cv, int dim, int P, int T1, double t_prev, double h,
                        const double *pts, int64_t npts, double *out, hipStream_t s)
 {
-    if (npts <= 0) return hipSuccess;
-    hipLaunchKernelGGL(eval_kernel, dim3((unsigned)((npts + 63) / 64)), dim3(64), 0, s, cu, cv, dim, P, T1, t_prev,
-                       h, pts, npts, out);
-    return hipGetLastError();
+    // one thread per point, in launches of at most kGridCap blocks
+    for (int64_t k0 = 0; k0 < npts; k0 += kGridCap * 64) {
+        const int64_t n = std::min<int64_t>(npts - k0, kGridCap * 64);
+        hipLaunchKernelGGL(eval_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, cu, cv, dim, P, T1, t_prev,
+                           h, pts + k0 * (dim + 1), n, out + 2 * k0);
+        if (hipError_t e = hipGetLastError()) return e;
+    }
+    return hipSuccess;
 }
 
 size_t path_state_bytes(int fp32, int dim)
@@ -870,30 +882,30 @@ hipError_t launch_loss_lambda(const double *U, const double *target, int n_inst,
 
 __global__ void column_sum_kernel(const double *__restrict__ lambda, int64_t rows, int T1, double *__restrict__ out)
 {
-    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= rows) return;
-    double s = 0.0;
-    for (int l = 0; l < T1; ++l) s += lambda[r * T1 + l];
-    out[r] = s;
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int l = 0; l < T1; ++l) s += lambda[r * T1 + l];
+        out[r] = s;
+    }
 }
 
 hipError_t launch_column_sum(const double *lambda, int64_t rows, int T1, double *out, hipStream_t s)
 {
     if (rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(column_sum_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, lambda, rows, T1, out);
+    hipLaunchKernelGGL(column_sum_kernel, dim3(grid_blocks(rows, 256)), dim3(256), 0, s, lambda, rows, T1, out);
     return hipGetLastError();
 }
 
 __global__ void axpy_kernel(double *__restrict__ y, const double *__restrict__ x, int64_t n)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) y[i] += x[i];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
 }
 
 hipError_t launch_axpy(double *y, const double *x, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x, n);
+    hipLaunchKernelGGL(axpy_kernel, dim3(grid_blocks(n, 256)), dim3(256), 0, s, y, x, n);
     return hipGetLastError();
 }
 

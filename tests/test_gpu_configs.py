@@ -339,6 +339,31 @@ def test_fp32_adjoint_p18_mfma_matches_vector():
     assert np.max(np.abs(g1 - g0)) <= 1e-5 * (1 + np.max(np.abs(g0)))
 
 
+def test_fp32_gradient_with_a_slab_adjoint_table_past_2_32_words():
+    """The batched-gradient shape, 256 instances: the slab-adjoint table (row
+    layout, 2 PP = 40 columns of P = 18 rows per step) holds 5.84 G 8-byte
+    words (46.7 GB), more work-items than one dispatch can count (2^32), and
+    it is cleared before every iteration's adjoint.  Two gradient calls on one
+    plan then agree to the FP32 summation order of the table's atomics; a
+    clear that stopped short would leave the previous iteration's sums in the
+    table's tail and move the later instances' gradients by their own size."""
+    H = _hp()
+    I = 256
+    wl, c0, target = _grad_problem("fp32", I=I, M=4, iters=2)
+    ns = np.asarray(H.resolve_nstar(wl)[0]).ravel()
+    words = I * int(ns.sum()) * 40 * 18 // 2
+    assert words > 2 ** 32, words
+    _say("slab-adjoint table words", words)
+    with H.Plan(wl) as plan:
+        L1, g1 = plan.hpsmc_loss_grad_c0(target)
+        L2, g2 = plan.hpsmc_loss_grad_c0(target)
+    assert np.array_equal(L1, L2)
+    scale = np.max(np.abs(g1), axis=1, keepdims=True)
+    d = np.max(np.abs(g2 - g1) / scale, axis=1)
+    print("max relative difference per instance: first", d[:4], "last", d[-4:], flush=True)
+    assert np.all(d <= 1e-4), (int(np.argmax(d)), float(np.max(d)))
+
+
 def test_tolerance_mode_solves_twice_on_one_plan():
     """Algorithm 1's stop test reads this solve's own max|eps| records: after a
     solve from larger initial data (larger increments), a solve from the
