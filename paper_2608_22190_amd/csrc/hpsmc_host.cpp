@@ -1008,6 +1008,35 @@ static hpsmc_status frac_tables(hpsmc_plan *plan)
     double S = 1.0, t = 1.0;
     for (int k = 0; k < 200; ++k) { t *= 0.5 * (k + 1.0) / (a + 1.0 + k); S += t; }
     plan->frac_half = std::exp(-std::log(2.0) - plan->frac_lpb1) * S;
+    // start tables of the inverse per branch (p = a with log(a B), p = b with
+    // log(b B)): at X0_i = i X0max / kFracTab the converged log x minus log X0_i,
+    // by the kernel's Newton iteration run in FP64 with 200 series terms, where
+    // X0max = e^{z0} at x = 1/2 (z0 the small-x asymptote of the branch)
+    double x0max[2];
+    for (int br = 0; br < 2; ++br) {
+        const double p = br ? b : a, lpb = br ? plan->frac_lpb2 : plan->frac_lpb1;
+        auto series = [&](double x) {
+            double Ss = 1.0, tt = 1.0;
+            for (int k = 0; k < 200; ++k) { tt *= x * (k + 1.0) / (p + 1.0 + k); Ss += tt; }
+            return Ss;
+        };
+        const double lhalf = -std::log(2.0);
+        const double l_half_cdf = lhalf - lpb + std::log(series(0.5));   // log I_{1/2}(p, 1-p)
+        x0max[br] = std::exp((l_half_cdf + lpb) / p);
+        tab.push_back(0.0);   // X0 -> 0: x / X0 -> 1
+        for (int i = 1; i <= kFracTab; ++i) {
+            const double lx0 = std::log(x0max[br] * i / kFracTab), ly = p * lx0 - lpb;
+            double z = std::min(lx0, lhalf);
+            for (int it = 0; it < 60; ++it) {
+                const double x = std::exp(z), Sx = series(x);
+                const double lI = p * z + (1.0 - p) * std::log1p(-x) - lpb + std::log(Sx);
+                z = std::min(z - (lI - ly) * (1.0 - x) * Sx / p, lhalf);
+            }
+            tab.push_back(z - lx0);
+        }
+    }
+    tab.push_back(x0max[0]);
+    tab.push_back(x0max[1]);
     hpsmc_status st;
     if ((st = dalloc(plan, (void **)&plan->frac_tab, tab.size() * 8))) return st;
     if (hipMemcpy(plan->frac_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice) != hipSuccess)

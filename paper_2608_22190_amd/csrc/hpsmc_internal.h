@@ -40,6 +40,10 @@ struct GroupDesc {
     uint32_t c3;           // Philox counter word 3 without the tag
 };
 
+// intervals of the start tables of the fractional walk's inverse incomplete
+// beta (da, db: kFracTab + 1 values each)
+constexpr int kFracTab = 256;
+
 // Problem constants every sampling lane needs.
 struct Physics {
     int32_t dim, f_kind, src_kind;
@@ -51,7 +55,7 @@ struct Physics {
     double frac_a;               // alpha / 2
     double frac_half;            // I_{1/2}(a, 1 - a): the branch of the inverse
     double frac_lpb1, frac_lpb2; // log(a B(a, 1-a)), log((1-a) B(1-a, a))
-    const double *frac_tab;      // A[kmax], C[kmax], lambda[P], src[K], ra[nt], rb[nt]
+    const double *frac_tab;      // A[kmax], C[kmax], lambda[P], src[K], ra[nt], rb[nt], da, db, X0max[2]
     double f_param[4];
     double src_param[8];
 };

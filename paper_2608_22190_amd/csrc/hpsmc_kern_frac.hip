@@ -20,17 +20,30 @@ hipError_t set_rec_tables_frac() { return upload_recurrence_tables(); }
 
 // log x solving I_x(p, 1-p) = y for x <= 1/2: Newton on log x with the series
 // I_x = x^p (1-x)^{1-p} / (p B) sum_k t_k, t_{k+1} = t_k x (k+1)/(p+1+k)
-// (ratios rt[k] from the block's LDS copy of the table), started from the
-// small-x asymptote.  FP64: 6 iterations of 60 terms; FP32: 4 of 26.
-template <typename T> struct FracIters { static constexpr int nit = sizeof(T) == 8 ? 6 : 4, nt = sizeof(T) == 8 ? 60 : 26; };
+// (ratios rt[k] from the block's LDS copy of the table).  The small-x
+// asymptote z0 = (log y + log(p B)) / p gives X0 = e^{z0}; the solution is
+// x = X0 e^{-h(x)/p}, h(x) = (1-p) log(1-x) + log sum_k t_k, an analytic
+// function of X0 on [0, X0max] (X0max the asymptote at x = 1/2), so the start
+// is z0 plus log(x / X0) interpolated linearly in a table of kFracTab
+// intervals (the host runs the same Newton to convergence at each grid
+// point); from there one Newton step (FP32, 26 terms) or two (FP64, 60 terms)
+// reach the iteration's fixed point to rounding.
+template <typename T> struct FracIters { static constexpr int nit = sizeof(T) == 8 ? 2 : 1, nt = sizeof(T) == 8 ? 60 : 26; };
 
 template <typename T>
-__device__ __forceinline__ T ibeta_inv_log(T y, T p, T lpb, const T *rt)
+__device__ __forceinline__ T ibeta_inv_log(T y, T p, T lpb, const T *rt, const T *dtab, T x0max)
 {
     constexpr int NIT = FracIters<T>::nit, NT = FracIters<T>::nt;
     const T lhalf = (T)-0.69314718055994530942;
     const T ly = m_log(y);
-    T z = (ly + lpb) / p;
+    const T z0 = (ly + lpb) / p;
+    const T f = m_exp(z0) * ((T)kFracTab / x0max);
+    T z = lhalf;
+    if (f < (T)kFracTab) {
+        const int i = (int)f;
+        const T w = f - (T)i;
+        z = z0 + m_fma(w, dtab[i + 1] - dtab[i], dtab[i]);
+    }
     z = z < lhalf ? z : lhalf;
     for (int it = 0; it < NIT; ++it) {
         const T x = m_exp(z);
@@ -50,14 +63,17 @@ __device__ __forceinline__ T ibeta_inv_log(T y, T p, T lpb, const T *rt)
 
 // one Newton solve per lane whichever half of (0,1) omega falls in (no
 // divergent second solve): x <= 1/2 solves I_x(a, 1-a) = omega for log x;
-// otherwise z = 1 - x solves I_z(1-a, a) = 1 - omega for log z
+// otherwise z = 1 - x solves I_z(1-a, a) = 1 - omega for log z.  The start
+// tables follow the series ratios: [ra | rb | da | db | X0max_a, X0max_b].
 template <typename T>
 __device__ __forceinline__ T frac_jump(const Physics &ph, T R, T om, const T *ra, const T *rb)
 {
     const T a = (T)ph.frac_a;
     const bool lower = om <= (T)ph.frac_half;
+    const T *da = rb + ph.frac_nt, *db = da + kFracTab + 1, *xm = db + kFracTab + 1;
     const T z = ibeta_inv_log<T>(lower ? om : (T)1 - om, lower ? a : (T)1 - a,
-                                 lower ? (T)ph.frac_lpb1 : (T)ph.frac_lpb2, lower ? ra : rb);
+                                 lower ? (T)ph.frac_lpb1 : (T)ph.frac_lpb2, lower ? ra : rb, lower ? da : db,
+                                 lower ? xm[0] : xm[1]);
     return lower ? R * m_exp((T)-0.5 * z) : R / m_sqrt((T)1 - m_exp(z));
 }
 
@@ -73,7 +89,7 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
     const int cv = (nv + 1) & ~1;
     // the tables, in the sampling precision, after the two slab buffers
     T *tl = (T *)(lds + 2 * cv);
-    const int ntab = 2 * kmax + P + K + 2 * ph.frac_nt;
+    const int ntab = 2 * kmax + P + K + 2 * ph.frac_nt + 2 * (kFracTab + 1) + 2;
     for (int i = tid; i < ntab; i += blockDim.x) tl[i] = (T)ph.frac_tab[i];
     const T *tA = tl, *tC = tl + kmax, *tlam = tl + 2 * kmax, *tsrc = tlam + P, *ra = tsrc + K, *rb = ra + ph.frac_nt;
     cptr<GroupDesc> groups = as_const(a.groups);
@@ -268,7 +284,7 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
 size_t frac_lds_bytes(int fp32, int PP, int kmax, int P, int K, int nt)
 {
     const int nv = 2 * PP * (fp32 ? 4 : 8) / 16, cv = (nv + 1) & ~1;
-    return (size_t)2 * cv * 16 + (size_t)(2 * kmax + P + K + 2 * nt) * (fp32 ? 4 : 8);
+    return (size_t)2 * cv * 16 + (size_t)(2 * kmax + P + K + 2 * nt + 2 * (kFracTab + 1) + 2) * (fp32 ? 4 : 8);
 }
 
 hipError_t launch_adv_frac(const RoundArgs &a, int fp32, dim3 grid, dim3 block, size_t lds_bytes, hipStream_t s)

@@ -720,25 +720,41 @@ hipError_t launch_advance(const RoundArgs &a, int fp32, int samples_per_lane, in
                 : launch_adv_valu_f64(a, samples_per_lane, grid, block, lds_bytes, s);
 }
 
-// sums[out][0..1] (+)= sum over the slice's samples of S and S^2, in sample order
-__global__ void slice_reduce_kernel(const double *__restrict__ result, int64_t n_nodes, int64_t mcount,
-                                    double *__restrict__ sums, int first)
+// sums[out][0..1] (+)= sum over the slice's samples of S and S^2: one wave per
+// node (nodes strided over a capped grid), lane l summing samples l, l + 64,
+// ... in order from coalesced loads, then a fixed xor butterfly over the lanes
+// (every lane ends with the same sums, the same way every run)
+__global__ void __launch_bounds__(256) slice_reduce_kernel(const double *__restrict__ result, int64_t n_nodes,
+                                                           int64_t mcount, double *__restrict__ sums, int first)
 {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n_nodes) return;
-    const double *r = result + i * mcount;
-    double s1 = 0.0, s2 = 0.0;
-    for (int64_t k = 0; k < mcount; ++k) { s1 += r[k]; s2 += r[k] * r[k]; }
-    if (first) { sums[2 * i] = s1; sums[2 * i + 1] = s2; }
-    else { sums[2 * i] += s1; sums[2 * i + 1] += s2; }
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; i < n_nodes; i += nwaves) {
+        const double *r = result + i * mcount;
+        double s1 = 0.0, s2 = 0.0;
+        for (int64_t k = lane; k < mcount; k += 64) {
+            const double v = r[k];
+            s1 += v;
+            s2 = fma(v, v, s2);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            s1 += __shfl_xor(s1, o, 64);
+            s2 += __shfl_xor(s2, o, 64);
+        }
+        if (lane == 0) {
+            if (first) { sums[2 * i] = s1; sums[2 * i + 1] = s2; }
+            else { sums[2 * i] += s1; sums[2 * i + 1] += s2; }
+        }
+    }
 }
 
 hipError_t launch_slice_reduce(const double *result, int64_t n_nodes, int64_t mcount, double *sums, int first,
                                hipStream_t s)
 {
     if (n_nodes <= 0) return hipSuccess;
-    hipLaunchKernelGGL(slice_reduce_kernel, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, result, n_nodes,
-                       mcount, sums, first);
+    hipLaunchKernelGGL(slice_reduce_kernel, dim3(grid_blocks(n_nodes, 4)), dim3(256), 0, s, result, n_nodes, mcount,
+                       sums, first);
     return hipGetLastError();
 }
 
