@@ -640,10 +640,11 @@ __global__ void round_prep_kernel(const GroupDesc *__restrict__ groups, int32_t 
 {
     // one block of 256 threads: clear the output counters, then an exclusive
     // prefix over groups of their work items (each thread a contiguous chunk,
-    // a scan of the 256 chunk sums in LDS, then the chunks again).  With
-    // batch_split > 0 a round whose paths fit in at most split_max items of
-    // batch_split paths takes that batch instead; batch_prefix[n_groups + 1]
-    // holds the paths per item the round kernel is to use.
+    // an inclusive scan of the 256 chunk sums in LDS in eight doubling steps,
+    // then the chunks again).  With batch_split > 0 a round whose paths fit in
+    // at most split_max items of batch_split paths takes that batch instead;
+    // batch_prefix[n_groups + 1] holds the paths per item the round kernel is
+    // to use.
     __shared__ int64_t part[256], part_s[256];
     __shared__ int32_t s_split;
     const int t = threadIdx.x, nt = blockDim.x;
@@ -664,14 +665,16 @@ __global__ void round_prep_kernel(const GroupDesc *__restrict__ groups, int32_t 
     part[t] = sum;
     part_s[t] = sum_s;
     __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {   // inclusive scans of both sets of chunk sums
+        const int64_t v = t >= o ? part[t - o] : 0, v_s = t >= o ? part_s[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        part_s[t] += v_s;
+        __syncthreads();
+    }
     if (t == 0) {
-        int64_t tot_s = 0;
-        for (int i = 0; i < nt; ++i) tot_s += part_s[i];
-        const bool split = batch_split > 0 && tot_s <= split_max;
-        int64_t *pp = split ? part_s : part;
-        int64_t acc = 0;
-        for (int i = 0; i < nt; ++i) { const int64_t v = pp[i]; pp[i] = acc; acc += v; }
-        batch_prefix[n_groups] = acc;
+        const bool split = batch_split > 0 && part_s[nt - 1] <= split_max;
+        batch_prefix[n_groups] = split ? part_s[nt - 1] : part[nt - 1];
         batch_prefix[n_groups + 1] = split ? batch_split : batch;
         s_split = split ? 1 : 0;
         *work = 0ull;
@@ -679,7 +682,7 @@ __global__ void round_prep_kernel(const GroupDesc *__restrict__ groups, int32_t 
     __syncthreads();
     const bool split = s_split != 0;
     const int32_t bsz = split ? batch_split : batch;
-    int64_t acc = split ? part_s[t] : part[t];
+    int64_t acc = split ? part_s[t] - sum_s : part[t] - sum;   // this chunk's exclusive prefix
     for (int g = g0; g < g1; ++g) {
         batch_prefix[g] = acc;
         acc += items(g, bsz);
