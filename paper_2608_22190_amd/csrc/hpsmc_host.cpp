@@ -2675,6 +2675,13 @@ static hpsmc_status adjoint_sampling(hpsmc_plan *plan, NodeSet &set, int tag, hi
     return HPSMC_OK;
 }
 
+// the slab-adjoint table: the row layout of the set's slabs (the adjoint kernels
+// accumulate in it and the slab adjoint reads it), in whole 8-byte words
+static size_t bar_alloc_bytes(const hpsmc_plan *plan, const NodeSet &set)
+{
+    return ((size_t)set.slab_elems_row * (plan->fp32 ? 4 : 8) + 7) & ~(size_t)7;
+}
+
 hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *loss, double *grad,
                                 int32_t on_device, void *stream)
 {
@@ -2704,7 +2711,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
             (st = dalloc(plan, (void **)&plan->dtarget, (size_t)I * nsp * 8)) ||
             (st = dalloc(plan, (void **)&plan->dloss, (size_t)I * 8)) ||
             (st = dalloc(plan, (void **)&plan->dgrad, (size_t)I * nsp * 8)) ||
-            (st = dalloc(plan, &plan->slab_bar, plan->slab_bytes)))
+            (st = dalloc(plan, &plan->slab_bar, bar_alloc_bytes(plan, set))))
             return st;
     }
     HIP_TRY(hipMemcpyAsync(plan->dtarget, target, (size_t)I * nsp * 8,
@@ -2729,8 +2736,7 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
         if ((st = slab_args_for(plan, set, adjoint_mfma_mode(plan, set) == 2 ? 1 : 0, false, sa, s))) return st;
         HIP_TRY(launch_slabs(sa, plan->fp32, set.max_nstar, s));
         // the adjoint accumulates into the row layout's extent of the table
-        const int64_t bar_bytes = set.slab_elems_row * (plan->fp32 ? 4 : 8);
-        HIP_TRY(launch_fill_u64((unsigned long long *)plan->slab_bar, (bar_bytes + 7) / 8, 0ull, s));
+        HIP_TRY(launch_fill_u64((unsigned long long *)plan->slab_bar, (int64_t)(bar_alloc_bytes(plan, set) / 8), 0ull, s));
         if ((st = adjoint_sampling(plan, set, plan->pb.fresh_per_iter ? k : 0, s))) return st;
         SlabArgs sb = set.slab;
         sb.slab_table = plan->slab_bar;
