@@ -23,6 +23,8 @@ namespace hpsmc {
 // thread per element wraps past 2^32 elements (a c5 slab-adjoint table holds
 // 10.7 G 8-byte words).
 constexpr int64_t kGridCap = 1 << 20;
+// a grid's y and z extents are at most 65536 blocks: counts past that run over y and z
+constexpr int kGridYZ = 65535;
 static inline unsigned grid_blocks(int64_t n, int block) { return (unsigned)std::min<int64_t>((n + block - 1) / block, kGridCap); }
 
 
@@ -322,7 +324,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) slab_kernel(SlabArgs a)
 {
     __shared__ __align__(16) double Lt[kMaxDeg + 1][kSlabQ];
-    const int g = blockIdx.y;
+    const int g = blockIdx.z * kGridYZ + blockIdx.y;   // groups over y and z (y at most 65535)
+    if (g >= a.n_groups) return;
     const int nq = a.nstar[g] + a.extra;
     const int T1 = a.deg[g] + 1;
     const bool mma = a.layout == 1, mma5 = a.layout == 2;
@@ -398,7 +401,8 @@ hipError_t launch_slabs(const SlabArgs &a, int fp32, int max_nstar, hipStream_t 
     if (a.n_groups <= 0) return hipSuccess;
     int64_t bx = (max_nstar + a.extra + kSlabQ - 1) / kSlabQ;
     if (bx > 65535) bx = 65535;
-    dim3 grid((unsigned)bx, (unsigned)a.n_groups);
+    dim3 grid((unsigned)bx, (unsigned)std::min<int64_t>(a.n_groups, kGridYZ),
+              (unsigned)((a.n_groups + kGridYZ - 1) / kGridYZ));
     if (fp32)
         hipLaunchKernelGGL(slab_kernel<float>, grid, dim3(256), 0, s, a);
     else
@@ -778,7 +782,7 @@ __device__ __forceinline__ void slab_adjoint_body(const SlabArgs &a, int32_t gro
                                                   double (*Lt)[kSlabQ])
 {
     constexpr int QB = T1P <= 16 ? kSlabQ : T1P <= 20 ? kSlabQ / 2 : kSlabQ / 4;   // loads in flight per thread
-    const int inst = blockIdx.y;
+    const int inst = blockIdx.z * kGridYZ + blockIdx.y;   // instances over y and z (y at most 65535)
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t row = e / (2 * a.PP);
     const int rem = (int)(e - row * 2 * a.PP), uv = rem / a.PP, kl = rem - uv * a.PP;
@@ -844,8 +848,8 @@ slab_adjoint_kernel(SlabArgs a, int32_t groups_per_inst, int32_t n_inst,
                                                            int64_t coef_inst_stride)
 {
     __shared__ __align__(16) double Lt[kMaxDeg + 1][kSlabQ];
-    (void)n_inst;
-    switch ((a.deg[blockIdx.y * groups_per_inst] + 4) >> 2) {   // ceil(T1 / 4), T1 <= kMaxDeg + 1 = 32
+    if ((int)(blockIdx.z * kGridYZ + blockIdx.y) >= n_inst) return;
+    switch ((a.deg[(blockIdx.z * kGridYZ + blockIdx.y) * groups_per_inst] + 4) >> 2) {   // ceil(T1 / 4), T1 <= 32
     case 1: slab_adjoint_body<T, 4>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
     case 2: slab_adjoint_body<T, 8>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
     case 3: slab_adjoint_body<T, 12>(a, groups_per_inst, cbar_u, cbar_v, coef_inst_stride, Lt); break;
@@ -861,7 +865,8 @@ hipError_t launch_slab_adjoint(const SlabArgs &a, int32_t groups_per_inst, int32
                                double *cbar_v, int64_t coef_inst_stride, hipStream_t s)
 {
     if (n_inst <= 0) return hipSuccess;
-    dim3 grid((unsigned)((a.slab_stride + 255) / 256), (unsigned)n_inst), block(256);
+    dim3 grid((unsigned)((a.slab_stride + 255) / 256), (unsigned)std::min<int32_t>(n_inst, kGridYZ),
+              (unsigned)((n_inst + kGridYZ - 1) / kGridYZ)), block(256);
     if (fp32)
         hipLaunchKernelGGL(slab_adjoint_kernel<float>, grid, block, 0, s, a, groups_per_inst, n_inst, cbar_u, cbar_v, coef_inst_stride);
     else
