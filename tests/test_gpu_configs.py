@@ -364,6 +364,30 @@ def test_fp32_gradient_with_a_slab_adjoint_table_past_2_32_words():
     assert np.all(d <= 1e-4), (int(np.argmax(d)), float(np.max(d)))
 
 
+def test_slab_groups_past_the_grid_y_extent():
+    """4100 instances x 16 node times: 65,600 slab groups, past the 65,535 blocks
+    of a grid's y extent, so the slab kernel takes the last instances' groups
+    from grid z; their sampled FP64 paths equal the oracle's walks."""
+    H = _hp()
+    wl = W.small(dim=2, n=2, M_deg=16, M=4, T=0.5, precision="fp64", nstar=8, n_instances=4100)
+    assert wl.n_instances * wl.degree[0] > 65535
+    _say("slab groups", wl.n_instances * wl.degree[0])
+    pb = O.Problem(wl)
+    with H.Plan(wl) as plan:
+        plan.hpsmc_set_probe(4)
+        plan.hpsmc_iterate(0, 0)
+        probe = plan.hpsmc_get_probe(0)
+    U0 = _ic_replicated(wl, pb)
+    rng = np.random.default_rng(11)
+    nodes = wl.nsp * wl.degree[0]
+    for inst in (0, 4095, 4099):   # groups 0.., 65520.., 65584..
+        Ut = O.reconstruct(2, wl.n, wl.degree[0], U0[inst].reshape(-1))
+        for _ in range(3):
+            node, smp = int(rng.integers(nodes)), int(rng.integers(4))
+            S, _ = pb.sample_path(Ut, inst, 0, 0, node, smp)
+            assert abs(probe[inst, node, smp] - S) <= 1e-12 * (1 + abs(S)), (inst, node, smp, probe[inst, node, smp], S)
+
+
 def test_tolerance_mode_solves_twice_on_one_plan():
     """Algorithm 1's stop test reads this solve's own max|eps| records: after a
     solve from larger initial data (larger increments), a solve from the
