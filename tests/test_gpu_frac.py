@@ -30,7 +30,7 @@ def _close(a, b, tol=TOL):
 
 
 @pytest.mark.parametrize("alpha,n,deg,M,waves", [(0.4, 9, 4, 97, 4), (1.0, 5, 2, 130, 2), (1.6, 7, 3, 64, 4),
-                                                 (0.4, 16, 6, 33, 1)])
+                                                 (0.4, 16, 6, 33, 1), (0.1, 6, 3, 64, 2), (1.9, 6, 3, 80, 4)])
 def test_frac_iteration_matches_oracle_fp64(alpha, n, deg, M, waves):
     H = _hp()
     wl = W.small(dim=1, n=n, M_deg=deg, M=M, T=0.5, f="u_minus_u3", src="frac_longtime", alpha=alpha)
