@@ -380,7 +380,6 @@ struct hpsmc_plan {
     // source) in the Chebyshev basis of both spatial dimensions, the slab image's basis
     double *cu_ch = nullptr, *cv_ch = nullptr, *cs_ch = nullptr;
     int64_t cheb_off = -1;               // in mats: Legendre -> Chebyshev, A[j][k] = coefficient of T_j in L_k
-    int64_t cheb_t_off = -1;             // in mats: A^T (Chebyshev-basis sums to the Legendre basis)
     double *tmp0 = nullptr, *tmp1 = nullptr;
     double *ic = nullptr;                // [inst][nsp]
     double *mats = nullptr;              // G0 (P x n), D2 (P x P), then per interval Bt, D1
@@ -1606,9 +1605,6 @@ hpsmc_status hpsmc_create(const hpsmc_problem *pb, hpsmc_plan **out)
         auto Ach = legendre_to_chebyshev(plan->P);
         plan->cheb_off = (int64_t)mats.size();
         mats.insert(mats.end(), Ach.begin(), Ach.end());
-        plan->cheb_t_off = (int64_t)mats.size();
-        for (int k = 0; k < plan->P; ++k)
-            for (int j = 0; j < plan->P; ++j) mats.push_back(Ach[(size_t)j * plan->P + k]);
         if ((st = dalloc(pl, (void **)&pl->cu_ch, csz * 8))) return st;
         if ((st = dalloc(pl, (void **)&pl->cv_ch, csz * 8))) return st;
     }
@@ -2745,14 +2741,6 @@ hpsmc_status hpsmc_loss_grad_c0(hpsmc_plan *plan, const double *target, double *
         SlabArgs sb = set.slab;
         sb.slab_table = plan->slab_bar;
         HIP_TRY(launch_slab_adjoint(sb, plan->degree[0], (int)I, plan->fp32, plan->cbar_u, plan->cbar_v, psp * T1, s));
-        if (adjoint_mfma_mode(plan, set) == 2) {   // Chebyshev-basis sums to the Legendre basis: A^T in both modes
-            if (plan->cheb_t_off < 0) return fail(HPSMC_EINVAL, "no Chebyshev basis change for the adjoint");
-            const double *At = M + plan->cheb_t_off;
-            for (double *cb : {plan->cbar_u, plan->cbar_v}) {
-                HIP_TRY(launch_mode_product(cb, plan->tmp0, I, P, P, (int64_t)P * T1, At, 1.0, 0, s));
-                HIP_TRY(launch_mode_product(plan->tmp0, cb, I * P, P, P, T1, At, 1.0, 0, s));
-            }
-        }
         // cbar_u += (c^u -> c^v)^T cbar_v
         for (int i = 0; i < d; ++i)
             HIP_TRY(launch_mode_product(plan->cbar_v, plan->cbar_u, I * ipow(P, i), P, P, ipow(P, d - 1 - i) * T1,

@@ -327,10 +327,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MFMA ?
 // slab passes through LDS.  The weighted outer products stack the u and v
 // factors as one set of rows in 16 x 16 tiles (P = 18: six tiles of 256 sums
 // where two 32 x 32 tiles hold 1024 each), with the samples as the reduction
-// dimension as above, and take their factors in the Chebyshev basis T_k (one
-// fma per value): the slab-adjoint table this kernel fills holds
-// sum w T_a(X_0) T_b(X_1), which the host maps to the Legendre basis
-// (L_k = sum_a A[a][k] T_a, by A^T in both modes) after the time contraction.
+// dimension as above.
 // Templated on KH = ceil(P/2): every per-sample loop has a fixed trip count.
 // ===========================================================================
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -450,19 +447,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) a
                     wu = lam * fprime_of<float>(a.phys, u);
                 }
             }
-            // ---- outer-product factors of this sample in the Chebyshev basis (one
-            // fma per value; the host converts the summed table to the Legendre
-            // basis after the slab adjoint): rows T(X_0) weighted, columns T(X_1)
+            // ---- outer-product factors of this sample: rows L(X_0) weighted, columns L(X_1)
             Wm[tid] = wu;
             Wm[nthr + tid] = wv;
             {
-                const float x02 = x0 + x0, x12 = x1 + x1;
                 float lp = 0.f, lc = 1.f, mp = 0.f, mc = 1.f;
 #pragma unroll
                 for (int i = 0; i < K2; ++i) {
                     Am[i * NST + tid] = lc;
                     Bm[i * NST + tid] = mc;
-                    const float nx = i == 0 ? x0 : fmaf(x02, lc, -lp), ny = i == 0 ? x1 : fmaf(x12, mc, -mp);
+                    const float ai = (float)((2.0 * i + 1.0) / (i + 1.0)), bi = (float)(i / (i + 1.0));
+                    const float nx = ai * x0 * lc - bi * lp, ny = ai * x1 * mc - bi * mp;
                     lp = lc;
                     lc = nx;
                     mp = mc;

@@ -67,7 +67,7 @@ def test_gradient_matches_central_differences_fp64():
             assert np.max(np.abs(fd - grad[:, k]) / (1 + np.abs(grad[:, k]))) <= 1e-6, (k, fd, grad[:, k])
 
 
-@pytest.mark.parametrize("dim,n", [(1, 9), (2, 6), (2, 7)])
+@pytest.mark.parametrize("dim,n", [(1, 9), (2, 6), (2, 7), (2, 17), (2, 18)])
 def test_fp32_mfma_and_vector_outer_products_agree(dim, n):
     H = _hp()
     wl, c0, target = _problem(dim=dim, n=n, deg=3, M=96, precision="fp32", I=3)
@@ -79,7 +79,10 @@ def test_fp32_mfma_and_vector_outer_products_agree(dim, n):
             res[mf] = plan.hpsmc_loss_grad_c0(target)
     assert np.array_equal(res[0][0], res[1][0])            # same forward
     g1, g0 = res[1][1], res[0][1]
+    print("max |g_mfma - g_vector| / max |g_vector| =", np.max(np.abs(g1 - g0)) / np.max(np.abs(g0)))
     assert np.max(np.abs(g1 - g0)) <= 1e-5 * (1 + np.max(np.abs(g0)))
+    if n + 2 >= 18:   # the FP64 adjoint's slab chunks stop short of P = 18 (its accuracy there: the FD test)
+        return
     with H.Plan(wl.with_(precision="fp64")) as plan:
         _, g64 = plan.hpsmc_loss_grad_c0(target)
     print("max |g32 - g64| / max |g64| =", np.max(np.abs(g1 - g64)) / np.max(np.abs(g64)))
