@@ -81,8 +81,9 @@ template <typename T>
 __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
 {
     extern __shared__ u32x4 lds[];
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
     __shared__ long long s_item;
+    __shared__ T s_tt[256], s_tp[256];   // source time factors of a window of blockDim.x steps
     const Physics &ph = a.phys;
     const int P = a.P, PP = a.PP, K = ph.frac_K, kmax = ph.frac_kmax;
     const int nv = 2 * PP * (int)sizeof(T) / 16;   // 16-byte vectors per slab
@@ -143,6 +144,29 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
             }
             c0 = nodes[node].c0;
         }
+        // time factors T(tau_q), T'(tau_q) of the manufactured source for a window
+        // of blockDim.x steps (the same for every lane of the item), one step a thread
+        auto fill_time = [&](int qs) {
+            const int qq = qs + tid;
+            if (ph.src_kind < 5 || qq >= q1) return;
+            const T tau = (T)(t_prev + (span - (double)qq * ddelta));
+            T Tt, Tp;
+            if (ph.src_kind == 5) {
+                const T qd = (T)1 + tau * tau;
+                Tt = m_exp(m_cos(tau)) / qd;
+                Tp = Tt * (-m_sin(tau) - (T)2 * tau / qd);
+            } else if (ph.src_kind == 6) {
+                const T rho = (T)ph.src_param[0];
+                Tt = m_exp(rho * m_log(tau));
+                Tp = rho * Tt / tau;
+            } else {
+                Tt = (T)1 + (T)ph.src_param[3] * tau;
+                Tp = (T)ph.src_param[3];
+            }
+            s_tt[tid] = Tt;
+            s_tp[tid] = Tp;
+        };
+        fill_time(q0);
         // the slab of the first step into buffer 0
         {
             const u32x4 *src = (const u32x4 *)(gtab + (int64_t)q0 * a.slab_stride);
@@ -151,8 +175,13 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
         __syncthreads();
 
         uint32_t w[4] = {0u, 0u, 0u, 0u};
-        int q = q0;
-        for (; q < q1; ++q) {
+        int q = q0, tslot = 0;
+        for (; q < q1; ++q, ++tslot) {
+            if (tslot == nthr) {   // the previous step's barrier ended every read of the old window
+                tslot = 0;
+                fill_time(q);
+                __syncthreads();
+            }
             const int buf = (q - q0) & 1;
             if (q + 1 < q1 && tid < nv)
                 lds[(buf ^ 1) * cv + tid] = ((const u32x4 *)(gtab + (int64_t)(q + 1) * a.slab_stride))[tid];
@@ -182,26 +211,18 @@ __global__ void __launch_bounds__(256) frac_advance_kernel(RoundArgs a)
                         pm = pc;
                         pc = pn;
                     }
-                    // manufactured source s = w g T' + T (-Delta)^{alpha/2}(w g) - f(w g T)
+                    // manufactured source s = w g T' + T (-Delta)^{alpha/2}(w g) - f(w g T),
+                    // the step's time factors T, T' from the block's window table
                     T src = (T)0;
                     if (ph.src_kind >= 5) {
-                        const T tau = (T)(t_prev + (span - (double)q * ddelta));
-                        T gx, Tt, Tp;
-                        if (ph.src_kind == 5) {
+                        const T Tt = s_tt[tslot], Tp = s_tp[tslot];
+                        T gx;
+                        if (ph.src_kind == 5)
                             gx = m_sin(X);
-                            const T qq = (T)1 + tau * tau;
-                            Tt = m_exp(m_cos(tau)) / qq;
-                            Tp = Tt * (-m_sin(tau) - (T)2 * tau / qq);
-                        } else if (ph.src_kind == 6) {
+                        else if (ph.src_kind == 6)
                             gx = m_cos(X * X * X + (T)1) / ((T)10 * X * X + (T)1);
-                            const T rho = (T)ph.src_param[0];
-                            Tt = m_exp(rho * m_log(tau));
-                            Tp = rho * Tt / tau;
-                        } else {
+                        else
                             gx = (T)ph.src_param[0] + X * ((T)ph.src_param[1] + X * (T)ph.src_param[2]);
-                            Tt = (T)1 + (T)ph.src_param[3] * tau;
-                            Tp = (T)ph.src_param[3];
-                        }
                         src = wgt * gx * Tp + Gs * Tt - f_of<T>(ph, wgt * gx * Tt);
                     }
                     // Picard form (eq. uast): the integrand f(u*) + s only
