@@ -406,11 +406,11 @@ def run_compare(args, torch):
 def flops_per_eval_frac(P, K, fp32):
     """Algorithmic FP operations of one step of the fractional walk: the Newton
     inverse of the incomplete beta (a start interpolated from a table, ~10, then
-    1 or 2 iterations of a 26- or 60-term series at 3 flops a term, plus ~30 for
+    one iteration of a 26- or 60-term series at 3 flops a term, plus ~30 for
     the logarithms and the update), the Jacobi recurrence with three
     contractions over P modes (9 flops a mode) and the source series over K
     modes (4 flops a mode), ~40 for w, f and the source."""
-    nit, nt = (1, 26) if fp32 else (2, 60)
+    nit, nt = (1, 26) if fp32 else (1, 60)
     return 10 + nit * (3 * nt + 30) + 9 * P + 4 * K + 40
 
 

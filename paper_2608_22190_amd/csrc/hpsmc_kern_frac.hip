@@ -26,9 +26,9 @@ hipError_t set_rec_tables_frac() { return upload_recurrence_tables(); }
 // function of X0 on [0, X0max] (X0max the asymptote at x = 1/2), so the start
 // is z0 plus log(x / X0) interpolated linearly in a table of kFracTab
 // intervals (the host runs the same Newton to convergence at each grid
-// point); from there one Newton step (FP32, 26 terms) or two (FP64, 60 terms)
-// reach the iteration's fixed point to rounding.
-template <typename T> struct FracIters { static constexpr int nit = sizeof(T) == 8 ? 2 : 1, nt = sizeof(T) == 8 ? 60 : 26; };
+// point); from there one Newton step (FP32: 26 terms, FP64: 60) reaches the
+// iteration's fixed point to rounding.
+template <typename T> struct FracIters { static constexpr int nit = 1, nt = sizeof(T) == 8 ? 60 : 26; };
 
 template <typename T>
 __device__ __forceinline__ T ibeta_inv_log(T y, T p, T lpb, const T *rt, const T *dtab, T x0max)
